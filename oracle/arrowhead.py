@@ -1,0 +1,105 @@
+"""Monolithic assembly of the arrowhead KKT system (test infrastructure only).
+
+K (Eq. hessianPerm, section 4.1) in the ordering u = (u_1, ..., u_N, u_g) of
+Eq. orderingMPOPF:
+
+    [ A_1              B_1^T ]
+    [      ...          ...  ]
+    [           A_N    B_N^T ]
+    [ B_1  ...  B_N    C     ]
+
+with the MPOPF border of Eq. B12N: B_n is (N*Ns) x nA with block row m equal
+to 0 for m < n, C_1 for m = n and C_0 for m > n (periods numbered 1..N).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def block_lower(inst, n: int) -> sp.csc_matrix:
+    """Stored lower triangle of A_n (0-based period n)."""
+    return sp.csc_matrix((inst.vals[n], inst.rowind.astype(np.int64), inst.colptr),
+                         shape=(inst.n_A, inst.n_A))
+
+
+def block(inst, n: int) -> sp.csr_matrix:
+    """Full symmetric A_n."""
+    L = block_lower(inst, n)
+    D = sp.diags(L.diagonal())
+    return (L + L.T - D).tocsr()
+
+
+def coupling(inst):
+    """(C_0, C_1) as Ns x nA CSR matrices."""
+    C0 = sp.csr_matrix((inst.C0_vals, inst.C0_colind.astype(np.int64), inst.C0_rowptr),
+                       shape=(inst.ns, inst.n_A))
+    C1 = sp.csr_matrix((inst.C1_vals, inst.C1_colind.astype(np.int64), inst.C1_rowptr),
+                       shape=(inst.ns, inst.n_A))
+    return C0, C1
+
+
+def border(inst, n: int) -> sp.csr_matrix:
+    """B_n of Eq. B12N, 0-based period n: block rows m < n zero, m == n C_1,
+    m > n C_0."""
+    C0, C1 = coupling(inst)
+    rows = []
+    for m in range(inst.N):
+        if m < n:
+            rows.append(sp.csr_matrix((inst.ns, inst.n_A)))
+        elif m == n:
+            rows.append(C1)
+        else:
+            rows.append(C0)
+    return sp.vstack(rows, format="csr")
+
+
+def corner(inst) -> sp.csr_matrix:
+    return sp.diags(inst.corner_diag).tocsr()
+
+
+def assemble(inst) -> sp.csr_matrix:
+    """The monolithic symmetric KKT matrix K."""
+    N = inst.N
+    blocks = [[None] * (N + 1) for _ in range(N + 1)]
+    for n in range(N):
+        blocks[n][n] = block(inst, n)
+        if inst.n_g:
+            Bn = border(inst, n)
+            blocks[N][n] = Bn
+            blocks[n][N] = Bn.T
+    if inst.n_g:
+        blocks[N][N] = corner(inst)
+    return sp.bmat(blocks, format="csr")
+
+
+def split(inst, v: np.ndarray):
+    """Split a vector (or [.., n_total] array) in u order into
+    ([b_1..b_N] as [N, nA, ...], b_C)."""
+    v = np.asarray(v)
+    nA, N = inst.n_A, inst.N
+    parts = v[..., : N * nA].reshape(v.shape[:-1] + (N, nA))
+    return parts, v[..., N * nA:]
+
+
+def residual(inst, x: np.ndarray, b: np.ndarray, K=None):
+    """r = b - K x for x, b of shape [nrhs, n_total]; returns (r, K)."""
+    K = assemble(inst) if K is None else K
+    r = b - (K @ x.T).T
+    return r, K
+
+
+def rel_residual(inst, x, b, K=None):
+    """max over right-hand sides of ||b - K x||_2 / ||b||_2 (FP64)."""
+    r, K = residual(inst, x, b, K)
+    return float(np.max(np.linalg.norm(r, axis=-1) / np.linalg.norm(b, axis=-1))), K
+
+
+def backward_error(inst, x, b, K=None):
+    """Componentwise backward error omega = max_i |r_i| / (|K||x| + |b|)_i."""
+    K = assemble(inst) if K is None else K
+    r = b - (K @ x.T).T
+    den = (abs(K) @ np.abs(x).T).T + np.abs(b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = np.where(den > 0, np.abs(r) / den, 0.0)
+    return float(np.max(w))

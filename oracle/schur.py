@@ -1,0 +1,162 @@
+"""Algorithm 1: Schur-complement decomposition of the arrowhead KKT system
+(test infrastructure only; section 4.2, Eqs. SCform, SCsolve, SCsolve1, and
+the MPOPF local Schur structure of section 4.3, Eqs. LocalSchurBs,
+LocalSchurBs3).
+
+Readings of the paper (the equations win where the algorithm listing differs):
+  * Sign convention: S = C - sum_i B_i A_i^-1 B_i^T (Eq. SCform); the
+    per-period contribution of section 4.3 is S_n := -B_n A_n^-1 B_n^T, so
+    S = C + sum_n S_n.
+  * Local solve: A_i du_i = b_i - B_i^T du_g (Eq. SCsolve1); the listing's
+    final step has the sign and the transpose the other way round.
+  * r = sum_i B_i A_i^-1 b_i and S du_g = b_C - r (Eq. SCsolve).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import arrowhead as ah
+from .ldlt import ldlt, ldlt_solve, inertia_from_d
+
+
+class BlockFactor:
+    """Factor of one diagonal block A_n: the oracle's own dense LDL^T for
+    small blocks (with inertia), else SuperLU as a library solve primitive
+    (the solution A_n^-1 y is unique, inertia is then not reported)."""
+
+    def __init__(self, A: sp.spmatrix, n_primal: int, dense_limit: int = 2500, eps: float = 1e-14):
+        n = A.shape[0]
+        self.n = n
+        if n <= dense_limit:
+            signs = np.where(np.arange(n) < n_primal, 1.0, -1.0)
+            self.L, self.d, self.n_perturbed, raw = ldlt(A.toarray(), signs=signs, eps=eps, return_raw=True)
+            self.inertia = inertia_from_d(raw)
+            self.kind = "dense"
+        else:
+            self.lu = spla.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A",
+                                diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+            self.inertia = None
+            self.n_perturbed = 0
+            self.kind = "splu"
+
+    def solve(self, y: np.ndarray) -> np.ndarray:
+        """A_n^-1 y for y of shape [n] or [n, k]."""
+        if self.kind == "dense":
+            return ldlt_solve(self.L, self.d, y)
+        return self.lu.solve(np.asarray(y, dtype=np.float64))
+
+
+def local_schur_bar(inst, Fn: BlockFactor) -> np.ndarray:
+    """S_bar_n = [[S_11, S_10^T], [S_10, S_00]] with S_ij = -C_i A_n^-1 C_j^T
+    (Eq. LocalSchurBs3): 2*Ns right-hand sides [C_1^T C_0^T]."""
+    C0, C1 = ah.coupling(inst)
+    Chat = sp.vstack([C1, C0]).tocsr()           # 2Ns x nA
+    W = Fn.solve(Chat.T.toarray())               # nA x 2Ns = A^-1 Chat^T
+    return -(Chat @ W)
+
+
+def place_local_schur(inst, n: int, Sbar: np.ndarray) -> np.ndarray:
+    """Dense S_n (n_g x n_g) of Eq. LocalSchurBs for 0-based period n: zero in
+    block rows/cols m < n, S_11 at (n, n), S_10 at (m, n) for m > n, S_00 at
+    (m, m') for m, m' > n (plus the transposes above the diagonal)."""
+    ns, N = inst.ns, inst.N
+    S11, S10, S00 = Sbar[:ns, :ns], Sbar[ns:, :ns], Sbar[ns:, ns:]
+    Sn = np.zeros((inst.n_g, inst.n_g))
+    blk = lambda m: slice(m * ns, (m + 1) * ns)
+    Sn[blk(n), blk(n)] = S11
+    for m in range(n + 1, N):
+        Sn[blk(m), blk(n)] = S10
+        Sn[blk(n), blk(m)] = S10.T
+        for mp in range(n + 1, N):
+            Sn[blk(m), blk(mp)] = S00
+    return Sn
+
+
+def algorithm1(inst, b=None, structured: bool = True, dense_limit: int = 2500, eps: float = 1e-14,
+               factors=None):
+    """Solve K x = b by Algorithm 1 on one process. Returns a dict with x
+    ([nrhs, n_total]), S (dense n_g x n_g), Sbar ([N, 2Ns, 2Ns], structured
+    only), r ([nrhs, n_g]), ug, the block factors, inertia (when every block
+    was factored densely) and the perturbed-pivot count."""
+    b = inst.b if b is None else np.atleast_2d(b)
+    N, nA, ng = inst.N, inst.n_A, inst.n_g
+    bparts, bC = ah.split(inst, b)              # [nrhs, N, nA], [nrhs, n_g]
+    # step 2: factor every diagonal block
+    if factors is None:
+        factors = [BlockFactor(ah.block(inst, n), inst.n_primal, dense_limit, eps) for n in range(N)]
+    # steps 3-6: Schur complement S = C - sum_n B_n A_n^-1 B_n^T
+    S = np.diag(inst.corner_diag).astype(np.float64)
+    Sbar = np.zeros((N, 2 * inst.ns, 2 * inst.ns))
+    if ng:
+        for n in range(N):
+            if structured:
+                Sbar[n] = local_schur_bar(inst, factors[n])
+                S += place_local_schur(inst, n, Sbar[n])
+            else:
+                Bn = ah.border(inst, n)
+                S -= Bn @ factors[n].solve(Bn.T.toarray())
+    # steps 8-11: r = sum_n B_n A_n^-1 b_n
+    y = np.stack([factors[n].solve(bparts[:, n, :].T).T.reshape(b.shape[0], nA) for n in range(N)], 1)
+    r = np.zeros((b.shape[0], ng))
+    if ng:
+        for n in range(N):
+            r += (ah.border(inst, n) @ y[:, n, :].T).T
+    # steps 12-13: S = L_s D_s L_s^T, solve S du_g = b_C - r
+    if ng:
+        Ls, ds, npert_s, raw_s = ldlt(S, signs=-np.ones(ng), eps=eps, return_raw=True)
+        ug = ldlt_solve(Ls, ds, (bC - r).T).T
+    else:
+        ds = raw_s = np.zeros(0)
+        npert_s = 0
+        ug = np.zeros((b.shape[0], 0))
+    # step 16: A_n du_n = b_n - B_n^T du_g
+    x = np.zeros_like(b, dtype=np.float64)
+    for n in range(N):
+        rhs = bparts[:, n, :]
+        if ng:
+            rhs = rhs - (ah.border(inst, n).T @ ug.T).T
+        x[:, n * nA:(n + 1) * nA] = factors[n].solve(rhs.T).T.reshape(b.shape[0], nA)
+    x[:, N * nA:] = ug
+    inertia = None
+    if all(f.inertia is not None for f in factors):
+        pos = sum(f.inertia[0] for f in factors)
+        neg = sum(f.inertia[1] for f in factors)
+        zer = sum(f.inertia[2] for f in factors)
+        ps, ns_, zs = inertia_from_d(raw_s)
+        inertia = (pos + ps, neg + ns_, zer + zs)
+    return dict(x=x, S=S, Sbar=Sbar if structured else None, r=r, ug=ug, factors=factors,
+                inertia=inertia, schur_d=ds,
+                n_perturbed=sum(f.n_perturbed for f in factors) + npert_s)
+
+
+def solve_mono(inst, b=None, dense_limit: int = 4000):
+    """Monolithic reference: assemble K and solve it directly (LAPACK
+    dgesv when dense, SuperLU otherwise)."""
+    b = inst.b if b is None else np.atleast_2d(b)
+    K = ah.assemble(inst)
+    if K.shape[0] <= dense_limit:
+        x = np.linalg.solve(K.toarray(), b.T).T
+    else:
+        lu = spla.splu(K.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        x = lu.solve(b.T).T
+    return x, K
+
+
+def refine(inst, x, b, solve_fn, tol: float = 1e-12, maxit: int = 10, K=None):
+    """FP64 iterative refinement x <- x + solve(b - K x) until the relative
+    residual is below tol, stagnates (no 2x gain over two steps) or maxit.
+    Returns (x, history of relative residuals)."""
+    K = ah.assemble(inst) if K is None else K
+    hist = []
+    for it in range(maxit + 1):
+        r = b - (K @ x.T).T
+        rel = float(np.max(np.linalg.norm(r, axis=-1) / np.linalg.norm(b, axis=-1)))
+        hist.append(rel)
+        if rel <= tol or it == maxit:
+            break
+        if len(hist) >= 3 and hist[-1] > 0.5 * hist[-3]:
+            break
+        x = x + solve_fn(r)
+    return x, hist

@@ -1,0 +1,286 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix:
+brute-force dense solves (LAPACK), eigenvalue inertia, the exact identity
+decomposed == monolithic (Eqs. SCform, SCsolve, SCsolve1), Haynsworth inertia
+additivity, the MPOPF Schur structure (Eqs. LocalSchurBs, GlobalSchur) and the
+special cases Ns = 0 and N = 1. The mutant tests plant plausible mistakes in
+the oracle and check that a pin catches each one."""
+import numpy as np
+import pytest
+
+import kktgen
+from oracle import arrowhead as ah
+from oracle import schur as sc
+from oracle.ldlt import ldlt, ldlt_solve, inertia_from_d, inertia_eig
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# --------------------------------------------------------------------------
+# dense LDL^T
+# --------------------------------------------------------------------------
+
+def _quasi_definite(n1, n2, seed):
+    rng = np.random.default_rng(seed)
+    H = rng.standard_normal((n1, n1))
+    H = H @ H.T + n1 * np.eye(n1)
+    J = rng.standard_normal((n2, n1))
+    D = np.diag(rng.uniform(0.1, 1.0, n2))
+    return np.block([[H, J.T], [J, -D]])
+
+
+@pytest.mark.parametrize("n1,n2,seed", [(5, 3, 0), (20, 12, 1), (60, 40, 2)])
+def test_ldlt_reconstructs_and_solves(n1, n2, seed):
+    A = _quasi_definite(n1, n2, seed)
+    signs = np.r_[np.ones(n1), -np.ones(n2)]
+    L, d, npert = ldlt(A, signs=signs)
+    assert npert == 0
+    assert np.allclose(np.tril(L), L) and np.allclose(np.diag(L), 1.0)
+    assert _rel(L @ np.diag(d) @ L.T, A) < 1e-13
+    b = np.random.default_rng(seed).standard_normal((n1 + n2, 3))
+    assert _rel(ldlt_solve(L, d, b), np.linalg.solve(A, b)) < 1e-11
+    assert inertia_from_d(d) == inertia_eig(A) == (n1, n2, 0)
+
+
+def test_ldlt_perturbs_vanishing_pivot_and_reports_wrong_sign():
+    A = _quasi_definite(6, 4, 3)
+    # column 2 made a copy of column 1 (and row likewise): pivot 2 vanishes
+    # after pivot 1 is eliminated, up to rounding
+    A[:, 2] = A[:, 1]
+    A[2, :] = A[1, :]
+    L, d, npert, raw = ldlt(A, signs=np.r_[np.ones(6), -np.ones(4)], return_raw=True)
+    assert npert == 1 and abs(raw[2]) <= 1e-14 * abs(A[2, 2])
+    assert np.isfinite(L).all()
+    # a wrong-sign (not vanishing) pivot is kept and shows in the inertia
+    B = _quasi_definite(6, 4, 4)
+    B[3, 3] = -1e3
+    L, d, npert, raw = ldlt(B, signs=np.r_[np.ones(6), -np.ones(4)], return_raw=True)
+    assert npert == 0 and inertia_from_d(raw) == inertia_eig(B) != (6, 4, 0)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 vs the monolithic solve
+# --------------------------------------------------------------------------
+
+CASES = [
+    dict(nb=8, nextra=3, ng=2, ns=2, N=3, nrhs=1, seed=0),
+    dict(nb=12, nextra=6, ng=3, ns=3, N=4, nrhs=4, seed=1),
+    dict(nb=10, nextra=4, ng=2, ns=1, N=1, nrhs=2, seed=2),       # N = 1
+    dict(nb=9, nextra=5, ng=3, ns=0, N=3, nrhs=1, seed=3),        # Ns = 0
+    dict(nb=15, nextra=8, ng=4, ns=2, N=5, nrhs=1, seed=4, corner="zero"),
+]
+
+
+def pin_decomposed_equals_monolithic(inst, tol=1e-8, tol_unrefined=1e-11):
+    """Algorithm 1 (refined in FP64 with its own factors, section 2.1) and the
+    LAPACK solve of the assembled K agree; the unrefined Algorithm 1 residual
+    is already small (refinement cannot hide a wrong step)."""
+    out = sc.algorithm1(inst)
+    x_mono, K = sc.solve_mono(inst)
+    rel0, _ = ah.rel_residual(inst, out["x"], inst.b, K)
+    assert rel0 < tol_unrefined, rel0
+    solve = lambda r: sc.algorithm1(inst, b=r, factors=out["factors"])["x"]
+    x_dec, hist = sc.refine(inst, out["x"], inst.b, solve, tol=1e-13, K=K)
+    rel_mono, _ = ah.rel_residual(inst, x_mono, inst.b, K)
+    assert hist[-1] < 1e-10 and rel_mono < 1e-10, (hist, rel_mono)
+    assert _rel(x_dec, x_mono) < tol, _rel(x_dec, x_mono)
+    return out, x_mono, K
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_decomposed_equals_monolithic(case):
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    pin_decomposed_equals_monolithic(inst)
+
+
+def test_decomposed_equals_monolithic_ring30():
+    inst = kktgen.make_workload(1)
+    out, x_mono, K = pin_decomposed_equals_monolithic(inst, tol=1e-6, tol_unrefined=1e-6)
+
+
+def pin_plain_equals_structured(inst):
+    a = sc.algorithm1(inst, structured=True)
+    b = sc.algorithm1(inst, structured=False)
+    assert _rel(a["S"], b["S"]) < 1e-11, _rel(a["S"], b["S"])
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_structured_schur_equals_plain(case):
+    """Eq. LocalSchurBs placement of S_bar_n == C - sum_n B_n A_n^-1 B_n^T."""
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    pin_plain_equals_structured(inst)
+
+
+def pin_inertia_additivity(inst):
+    out = sc.algorithm1(inst)
+    K = ah.assemble(inst).toarray()
+    expect = (inst.N * inst.n_primal, inst.N * (inst.n_A - inst.n_primal) + inst.n_g, 0)
+    assert inertia_eig(K) == expect
+    assert out["inertia"] == expect
+    # S is negative definite when every A_n and K have the correct inertia
+    if inst.n_g:
+        np.linalg.cholesky(-out["S"])
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_haynsworth_inertia(case):
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    pin_inertia_additivity(inst)
+
+
+def test_haynsworth_inertia_ring30():
+    pin_inertia_additivity(kktgen.make_workload(1))
+
+
+def pin_local_schur_blocks(inst):
+    """S_ij,n = -C_i A_n^-1 C_j^T (Eq. LocalSchurBs) with a LAPACK solve, and
+    the placement of Eq. LocalSchurBs: S_11 at the diagonal block (n, n), S_10
+    below it, S_00 further down and right, zero before period n."""
+    out = sc.algorithm1(inst, structured=False)    # S from the full B_n of Eq. B12N
+    # C_0, C_1 straight from the instance's CSR arrays, not via the oracle
+    C0 = np.zeros((inst.ns, inst.n_A))
+    C1 = np.zeros((inst.ns, inst.n_A))
+    for s_ in range(inst.ns):
+        for k in range(inst.C0_rowptr[s_], inst.C0_rowptr[s_ + 1]):
+            C0[s_, inst.C0_colind[k]] += inst.C0_vals[k]
+        for k in range(inst.C1_rowptr[s_], inst.C1_rowptr[s_ + 1]):
+            C1[s_, inst.C1_colind[k]] += inst.C1_vals[k]
+    ns, N = inst.ns, inst.N
+    blk = lambda m: slice(m * ns, (m + 1) * ns)
+    P = np.zeros((ns, ns))            # running sum of S_00,n, n < m'
+    S = out["S"]
+    Cc = np.diag(inst.corner_diag)
+    for mp in range(N):
+        A = ah.block(inst, mp).toarray()
+        S11 = -C1 @ np.linalg.solve(A, C1.T)
+        S10 = -C0 @ np.linalg.solve(A, C1.T)
+        S00 = -C0 @ np.linalg.solve(A, C0.T)
+        assert _rel(S[blk(mp), blk(mp)], Cc[blk(mp), blk(mp)] + P + S11) < 1e-9
+        for m in range(mp + 1, N):
+            assert _rel(S[blk(m), blk(mp)], P + S10) < 1e-9
+        P = P + S00
+
+
+@pytest.mark.parametrize("case", CASES[:2] + CASES[4:])
+def test_local_schur_blocks(case):
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    pin_local_schur_blocks(inst)
+
+
+def test_schur_subdiagonal_blocks_equal_and_independent_of_horizon():
+    """Eq. GlobalSchur: below the diagonal every block of a block column is the
+    same matrix; S_bar_n does not depend on N (section 4.3)."""
+    inst = kktgen.make_small(nb=10, nextra=4, ng=2, ns=2, N=5, seed=7, barrier_range=(1e-2, 1e2))
+    out = sc.algorithm1(inst)
+    ns, S = inst.ns, out["S"]
+    blk = lambda m: slice(m * ns, (m + 1) * ns)
+    for mp in range(inst.N):
+        for m in range(mp + 2, inst.N):
+            assert np.array_equal(S[blk(m), blk(mp)], S[blk(mp + 1), blk(mp)])
+    # truncate the horizon to the first 3 periods
+    import copy
+    short = copy.copy(inst)
+    short.N = 3
+    short.vals = inst.vals[:3]
+    short.corner_diag = inst.corner_diag[: 3 * ns]
+    short.b = np.concatenate([inst.b[:, : 3 * inst.n_A], inst.b[:, inst.N * inst.n_A: inst.N * inst.n_A + 3 * ns]], 1)
+    out2 = sc.algorithm1(short)
+    assert np.allclose(out2["Sbar"], out["Sbar"][:3], rtol=1e-13, atol=0)
+
+
+def test_ns0_is_independent_block_solves():
+    inst = kktgen.make_small(nb=9, nextra=5, ng=3, ns=0, N=3, seed=3, barrier_range=(1e-2, 1e2))
+    out = sc.algorithm1(inst)
+    for n in range(inst.N):
+        A = ah.block(inst, n).toarray()
+        xn = np.linalg.solve(A, inst.b[0, n * inst.n_A:(n + 1) * inst.n_A])
+        assert _rel(out["x"][0, n * inst.n_A:(n + 1) * inst.n_A], xn) < 1e-10
+
+
+def test_refinement_reaches_tolerance_wide_barrier():
+    """[1e-8, 1e8] barrier range: FP64 Algorithm 1 + refinement reaches the
+    1e-10 relative residual on the 30-bus grid."""
+    inst = kktgen.make_workload(1, barrier=(1e-8, 1e8))
+    out = sc.algorithm1(inst)
+    K = ah.assemble(inst)
+    solve = lambda r: sc.algorithm1(inst, b=r, factors=out["factors"])["x"]
+    x, hist = sc.refine(inst, out["x"], inst.b, solve, tol=1e-12, K=K)
+    assert hist[-1] < 1e-10, hist
+
+
+# --------------------------------------------------------------------------
+# planted mistakes: each must be caught by at least one pin
+# --------------------------------------------------------------------------
+
+def _mut_swap_c0_c1(monkeypatch):
+    orig = ah.coupling
+    monkeypatch.setattr(ah, "coupling", lambda inst: tuple(reversed(orig(inst))))
+
+
+def _mut_border_transposed_periods(monkeypatch):
+    orig = ah.border
+
+    def wrong(inst, n):          # cumulative coupling on the wrong side
+        return orig(inst, inst.N - 1 - n)
+    monkeypatch.setattr(ah, "border", wrong)
+
+
+def _mut_schur_sign(monkeypatch):
+    orig = sc.place_local_schur
+    monkeypatch.setattr(sc, "place_local_schur", lambda inst, n, Sb: -orig(inst, n, Sb))
+
+
+def _mut_drop_s00(monkeypatch):
+    orig = sc.place_local_schur
+
+    def wrong(inst, n, Sbar):
+        Sb = Sbar.copy()
+        Sb[inst.ns:, inst.ns:] = 0.0
+        return orig(inst, n, Sb)
+    monkeypatch.setattr(sc, "place_local_schur", wrong)
+
+
+def _mut_local_solve_sign(monkeypatch):
+    orig = sc.algorithm1
+
+    def wrong(inst, b=None, **kw):
+        out = orig(inst, b=b, **kw)
+        ug = out["ug"]
+        b_ = inst.b if b is None else np.atleast_2d(b)
+        for n in range(inst.N):        # A_n du_n = b_n + B_n^T du_g (wrong sign)
+            rhs = b_[:, n * inst.n_A:(n + 1) * inst.n_A] + (ah.border(inst, n).T @ ug.T).T
+            out["x"][:, n * inst.n_A:(n + 1) * inst.n_A] = out["factors"][n].solve(rhs.T).T
+        return out
+    monkeypatch.setattr(sc, "algorithm1", wrong)
+
+
+def _mut_ldlt_update(monkeypatch):
+    import oracle.ldlt as lm
+    orig = lm.ldlt
+
+    def wrong(A, signs=None, eps=1e-14, return_raw=False):
+        A = np.array(A, dtype=float)
+        if A.shape[0] > 3:
+            A[3, 1] *= 1.0000001      # a dropped/garbled term
+            A[1, 3] = A[3, 1]
+        return orig(A, signs=signs, eps=eps, return_raw=return_raw)
+    monkeypatch.setattr(sc, "ldlt", wrong)
+
+
+MUTANTS = [_mut_swap_c0_c1, _mut_border_transposed_periods, _mut_schur_sign, _mut_drop_s00,
+           _mut_local_solve_sign, _mut_ldlt_update]
+
+
+@pytest.mark.parametrize("mutant", MUTANTS, ids=lambda f: f.__name__)
+def test_pins_catch_planted_mistakes(mutant, monkeypatch):
+    inst = kktgen.make_small(nb=12, nextra=6, ng=3, ns=2, N=4, nrhs=1, seed=11, barrier_range=(1e-2, 1e2))
+    mutant(monkeypatch)
+    caught = 0
+    for pin in (pin_decomposed_equals_monolithic, pin_plain_equals_structured, pin_local_schur_blocks,
+                pin_inertia_additivity):
+        try:
+            pin(inst)
+        except (AssertionError, np.linalg.LinAlgError):
+            caught += 1
+    assert caught >= 1
