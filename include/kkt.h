@@ -1,0 +1,203 @@
+/*
+ * libkkt -- MI355X (gfx950) solver for the block-bordered (arrowhead) KKT
+ * system of a multiperiod AC optimal-power-flow problem with storage.
+ *
+ * The system (Eq. hessianPerm, section 4.1) in the ordering
+ * u = (u_1, ..., u_N, u_g) of Eq. orderingMPOPF:
+ *
+ *     [ A_1                B_1^T ] [du_1]   [b_1]
+ *     [      ...            ...  ] [ .. ] = [ ..]
+ *     [            A_N     B_N^T ] [du_N]   [b_N]
+ *     [ B_1  ...   B_N     C     ] [du_g]   [b_C]
+ *
+ * Every A_n (nA x nA, symmetric indefinite) shares one sparsity pattern. The
+ * border follows Eq. B12N: B_n is (N*Ns) x nA with block row m equal to 0 for
+ * m < n, C_1 for m = n and C_0 for m > n (C_0, C_1: Ns x nA, the same for every
+ * period). C is the corner (zero, or a diagonal; section 4.1 gives a zero block
+ * for MPOPF, the dual regularisation -delta_c I of section 2.4 makes it
+ * negative definite).
+ *
+ * The solve is the Schur-complement decomposition of Algorithm 1 (section
+ * 4.2, Eqs. SCform, SCsolve, SCsolve1): factor every A_n, form
+ * S = C - sum_n B_n A_n^-1 B_n^T, factor S, solve for du_g, back-substitute
+ * du_n = A_n^-1 (b_n - B_n^T du_g). The per-period contribution is built from
+ * the 2*Ns distinct right-hand sides of Eq. LocalSchurBs3 and placed by the
+ * structure of Eq. LocalSchurBs, then refined in FP64 (section 2.1).
+ *
+ * Conventions
+ *  - All sizes are int64_t; index arrays are int32_t.
+ *  - Device pointers are HIP device allocations owned by the caller and must
+ *    stay valid until the work enqueued on the context's stream completes.
+ *  - Host pointers are read during the call only (copied where kept).
+ *  - Return codes: 0 OK; negative = error, outputs untouched, the context
+ *    keeps its previous state; positive = warning, outputs valid.
+ *  - One context per stream; calls on one context are not thread safe.
+ *    Separate contexts are independent and may share a device.
+ */
+#ifndef KKT_H
+#define KKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define KKT_OK 0
+#define KKT_ERR_ARG (-1)          /* bad argument (null pointer, bad size)   */
+#define KKT_ERR_NOMEM (-2)        /* device allocation failed                */
+#define KKT_ERR_ORDER (-3)        /* factor before analyze, solve before factor */
+#define KKT_ERR_STRUCT (-4)       /* empty column, entry above the diagonal, */
+                                  /* unsorted/duplicate row index, bad C col  */
+#define KKT_ERR_HIP (-5)          /* HIP runtime error                        */
+#define KKT_ERR_NONFINITE (-6)    /* NaN/Inf in the values or the RHS         */
+#define KKT_WARN_PERTURBED 1      /* static pivots were perturbed             */
+#define KKT_WARN_INERTIA 2        /* inertia differs from (N*n_primal,        */
+                                  /*   N*(nA-n_primal)+N*Ns, 0)              */
+#define KKT_WARN_REFINE 3         /* refinement stopped above refine_tol      */
+
+/* ---- options ------------------------------------------------------------ */
+#define KKT_FP64 0   /* every factor and solve in FP64                         */
+#define KKT_MIXED 1  /* block factors and Schur contributions in FP32, FP64    */
+                     /* refinement residual, FP64 dense Schur factorisation    */
+
+typedef struct kkt_options {
+    int precision;      /* KKT_FP64 or KKT_MIXED                              */
+    double pivot_eps;   /* static-pivot threshold factor (see kkt_factor);    */
+                        /* 0 selects the default (1e-20 FP64, 1e-10 mixed)      */
+    double refine_tol;  /* target max_k ||b_k - K x_k||_2 / ||b_k||_2, 1e-10   */
+    int refine_max;     /* refinement steps at most (default 20)              */
+    int verbose;        /* 0 quiet                                            */
+} kkt_options;
+
+/* Fill *opt with the defaults above. */
+void kkt_default_options(kkt_options *opt);
+
+/* ---- structure (host pointers, copied by kkt_analyze) -------------------- */
+typedef struct kkt_structure {
+    int64_t nA;              /* rows of every A_n                              */
+    int64_t n_primal;        /* leading rows of A_n with positive pivots       */
+                             /* (primal: Hessian + barrier); the rest are duals */
+    int64_t N;               /* number of periods (>= 1)                       */
+    int64_t Ns;              /* rows of C_0 / C_1 (storage units, >= 0)         */
+    const int64_t *A_colptr; /* [nA+1] lower-triangular CSC of A_n's pattern,   */
+    const int32_t *A_rowind; /* [nnz]  rows sorted ascending, diagonal present  */
+    const int64_t *C0_rowptr;/* [Ns+1] CSR of C_0 (may be NULL when Ns = 0)     */
+    const int32_t *C0_colind;
+    const int64_t *C1_rowptr;/* [Ns+1] CSR of C_1                              */
+    const int32_t *C1_colind;
+} kkt_structure;
+
+typedef struct kkt_inertia {
+    int64_t n_pos, n_neg, n_zero;  /* sign count of the computed pivots of all */
+                                   /* A_n and of S (Haynsworth: = inertia of K) */
+    int64_t n_perturbed;           /* pivots replaced by the static rule        */
+    int inertia_ok;                /* 1 when equal to the expected inertia      */
+} kkt_inertia;
+
+typedef struct kkt_solve_info {
+    int refine_iters;    /* refinement corrections applied                      */
+    double rel_res;      /* max over right-hand sides of ||b-Kx||_2/||b||_2,     */
+                         /* FP64, on the unscaled K                             */
+    double omega;        /* componentwise backward error max_i |r_i|/(|K||x|+|b|)_i */
+    int fallback_used;   /* 1 when the mixed path fell back to FP64 factors     */
+} kkt_solve_info;
+
+typedef struct kkt_symbolic_stats {
+    int64_t n_supernodes;     /* supernodes of one period block (+1 border node) */
+    int64_t n_levels;         /* height of the supernodal elimination tree       */
+    int64_t nnz_L;            /* stored entries of one period's factor panels    */
+    int64_t u_entries;        /* stored entries of one period's update matrices  */
+    int64_t max_front;        /* largest front (rows)                            */
+    int64_t max_pivots;       /* most pivots in one supernode                    */
+    double flops_factor;      /* FP ops of one period's block factorisation      */
+    int64_t device_bytes;     /* device memory a context of this structure holds */
+} kkt_symbolic_stats;
+
+typedef struct kkt_ctx kkt_ctx;
+
+/* ---- lifecycle ------------------------------------------------------------
+ * kkt_create: bind a context to `stream` (a hipStream_t; NULL = the default
+ * stream) on the current device. `opt` may be NULL (defaults).            */
+int kkt_create(kkt_ctx **ctx, void *stream, const kkt_options *opt);
+
+/* kkt_analyze: symbolic analysis shared by all N periods (section 4.1's
+ * arrowhead structure; Algorithm 1 step 1 on one device): a fill-reducing
+ * approximate-minimum-degree order of A_n with the 2*Ns border rows
+ * [C_1; C_0] appended last, the supernodal elimination tree, front row sets
+ * and extend-add maps; then allocates device factors and workspace. Host
+ * time only plus one host->device copy of the maps. May be called again
+ * (re-analysis frees the previous state). */
+int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s);
+
+/* Exact device bytes the context holds after kkt_analyze (for admission). */
+int kkt_footprint(const kkt_ctx *ctx, size_t *bytes);
+
+/* Host-only planning query: the same symbolic analysis without a context or
+ * a device; fills *st (device_bytes for `opt`'s precision, nrhs_max RHS) and,
+ * when perm != NULL, the fill-reducing order perm[new] = old (nA entries). */
+int kkt_plan(const kkt_structure *s, const kkt_options *opt, int64_t nrhs_max,
+             kkt_symbolic_stats *st, int32_t *perm);
+
+/* kkt_factor: numeric factorisation for new values (Algorithm 1 steps 2-7,
+ * section 4.2):
+ *   A_vals     device [N][nnz_A] FP64, values of each A_n in the pattern
+ *              order of kkt_analyze (lower triangle).
+ *   C0_vals    device [nnz_C0], C1_vals device [nnz_C1] (NULL when Ns = 0).
+ *   corner_diag device [N*Ns] diagonal of C, or NULL for C = 0.
+ *   delta_w, delta_c: inertia-correction shifts (section 2.4) added as
+ *              +delta_w to the first n_primal diagonal entries of every A_n
+ *              and -delta_c to the remaining ones, without re-uploading.
+ *   out        optional (host); when non-NULL the call synchronises the
+ *              stream and reports the inertia counts.
+ * Pivoting is static: a pivot d_k with |d_k| <= tau_k, tau_k = pivot_eps *
+ * |a_kk| (the diagonal entry of the matrix being factored; pivot_eps * max|A|
+ * when a_kk = 0), keeps its sign and takes magnitude tau_k. Inertia counts
+ * the computed pivots before perturbation.
+ * Returns 0, KKT_WARN_PERTURBED or KKT_WARN_INERTIA (warnings only when out
+ * is non-NULL), or an error. */
+int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals,
+               const double *C1_vals, const double *corner_diag,
+               double delta_w, double delta_c, kkt_inertia *out);
+
+/* kkt_solve: x = K^-1 b for nrhs right-hand sides (Eqs. SCsolve, SCsolve1)
+ * with FP64 iterative refinement on the unscaled K until rel_res <=
+ * refine_tol or refine_max steps (section 2.1).
+ *   b, x  device [nrhs][N*nA + N*Ns] FP64, column-major in u order; b != x.
+ *   info  optional (host). The refinement loop reads one scalar per step
+ *         from the device (a stream synchronisation per step).
+ * Returns 0, KKT_WARN_REFINE, or an error. */
+int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
+              kkt_solve_info *info);
+
+/* kkt_schur: write the assembled Schur complement S of the last kkt_factor
+ * (dense n_g x n_g, column-major, both triangles; n_g = N*Ns) into the
+ * caller's device buffer S_out. Diagnostic; enqueued on the stream. */
+int kkt_schur(kkt_ctx *ctx, double *S_out);
+
+/* kkt_schur_blocks: write the per-period local Schur blocks
+ * S_bar_n = [[S_11,n, S_10,n^T], [S_10,n, S_00,n]], S_ij,n = -C_i A_n^-1 C_j^T
+ * (Eq. LocalSchurBs3), as device [N][2Ns][2Ns] column-major. Diagnostic. */
+int kkt_schur_blocks(kkt_ctx *ctx, double *Sbar_out);
+
+/* kkt_stats: symbolic statistics of the analysed structure (host). */
+int kkt_stats(const kkt_ctx *ctx, kkt_symbolic_stats *st);
+
+/* kkt_phase_times: milliseconds of the phases of the last factor/solve,
+ * measured with HIP events on the context's stream (syncs the stream):
+ * [0] block factor, [1] Schur assembly, [2] Schur factor, [3] last solve
+ * (all refinement steps), [4] the most expensive single kernel of the last
+ * factor; t must hold 5 doubles. Timing is off unless enabled with
+ * kkt_enable_timing(ctx, 1). */
+int kkt_enable_timing(kkt_ctx *ctx, int on);
+int kkt_phase_times(kkt_ctx *ctx, double *t);
+
+void kkt_destroy(kkt_ctx *ctx);
+const char *kkt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KKT_H */

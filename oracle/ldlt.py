@@ -23,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def ldlt(A, signs=None, eps: float = 1e-14, return_raw: bool = False):
+def ldlt(A, signs=None, eps: float = 1e-20, return_raw: bool = False):
     """Right-looking LDL^T of the symmetric matrix A in its given order.
 
     Returns (L, d, n_perturbed) with L unit lower triangular and A = L diag(d) L^T

@@ -26,7 +26,7 @@ class BlockFactor:
     small blocks (with inertia), else SuperLU as a library solve primitive
     (the solution A_n^-1 y is unique, inertia is then not reported)."""
 
-    def __init__(self, A: sp.spmatrix, n_primal: int, dense_limit: int = 2500, eps: float = 1e-14):
+    def __init__(self, A: sp.spmatrix, n_primal: int, dense_limit: int = 2500, eps: float = 1e-20):
         n = A.shape[0]
         self.n = n
         if n <= dense_limit:
@@ -74,7 +74,7 @@ def place_local_schur(inst, n: int, Sbar: np.ndarray) -> np.ndarray:
     return Sn
 
 
-def algorithm1(inst, b=None, structured: bool = True, dense_limit: int = 2500, eps: float = 1e-14,
+def algorithm1(inst, b=None, structured: bool = True, dense_limit: int = 2500, eps: float = 1e-20,
                factors=None):
     """Solve K x = b by Algorithm 1 on one process. Returns a dict with x
     ([nrhs, n_total]), S (dense n_g x n_g), Sbar ([N, 2Ns, 2Ns], structured

@@ -1,0 +1,781 @@
+// C-ABI context: symbolic analysis upload, the numeric factorisation of all
+// period blocks and of the Schur complement, and the refined solve
+// (Algorithm 1 of section 4.2 on one device).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/kkt.h"
+#include "device.hpp"
+#include "footprint.hpp"
+#include "kernels.hpp"
+#include "symbolic.hpp"
+
+namespace kkt {
+SymbolicInput make_input(const kkt_structure *s);
+void fill_stats(const Symbolic &S, int64_t N, int precision, int64_t nrhs_max, kkt_symbolic_stats *st);
+}
+
+using namespace kkt;
+
+#define HIPCHK(x)                                                                                 \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess) {                                                                   \
+            if (ctx && ctx->opt.verbose) std::fprintf(stderr, "kkt: %s at %s:%d\n", hipGetErrorString(e_), __FILE__, __LINE__); \
+            return e_ == hipErrorOutOfMemory ? KKT_ERR_NOMEM : KKT_ERR_HIP;                       \
+        }                                                                                         \
+    } while (0)
+
+namespace {
+
+struct StepHost {
+    int k0, nf, ntrsm, ntile;
+    int64_t fl_off, pt_off, pu_off;  // offsets (int32 elements) into the task buffer
+};
+
+struct LevelPlan {
+    int64_t small_off = 0, all_off = 0, ea_off = 0;  // int32 offsets into the task buffer
+    int nsmall = 0, nall = 0, nea = 0;
+    int maxm = 0;
+    int step_begin = 0, step_end = 0;
+};
+
+}  // namespace
+
+struct kkt_ctx {
+    hipStream_t stream = nullptr;
+    kkt_options opt{};
+    int device = 0;
+    bool analyzed = false, factored = false;
+    Symbolic sy;
+    int64_t N = 0, ng = 0, ntot = 0;
+    double eps = 1e-14;
+    std::vector<std::pair<void *, size_t>> allocs;  // static allocations
+    size_t bytes_static = 0, bytes_ws = 0;
+
+    // symbolic device data
+    int64_t *d_amap = nullptr, *d_c0map = nullptr, *d_c1map = nullptr, *d_rowptr = nullptr, *d_relptr = nullptr;
+    int8_t *d_adiag = nullptr, *d_pivsign = nullptr;
+    int32_t *d_adpiv = nullptr, *d_rows = nullptr, *d_cptr = nullptr, *d_clist = nullptr, *d_rel = nullptr;
+    int32_t *d_perm = nullptr, *d_tasks = nullptr;
+    FrontDesc *d_sd = nullptr;
+    std::vector<LevelPlan> levels;
+    std::vector<StepHost> steps, ssteps;   // sparse levels, Schur
+    int32_t *d_stasks = nullptr;           // Schur step tasks
+    FrontDesc *d_sdS = nullptr;
+    // residual structures
+    int64_t *d_rp = nullptr, *d_vi = nullptr, *d_c1tp = nullptr, *d_c0tp = nullptr, *d_c1tk = nullptr,
+            *d_c0tk = nullptr, *d_c0p = nullptr, *d_c1p = nullptr;
+    int32_t *d_ci = nullptr, *d_c1ts = nullptr, *d_c0ts = nullptr, *d_c0i = nullptr, *d_c1i = nullptr;
+    // numeric
+    void *d_L = nullptr, *d_U = nullptr;
+    double *d_tau = nullptr, *d_amax = nullptr;
+    int64_t *d_cnt = nullptr;
+    int *d_flag = nullptr;
+    double *d_A = nullptr, *d_C0 = nullptr, *d_C1 = nullptr, *d_corner = nullptr;
+    bool has_corner = false;
+    double dw = 0.0, dc = 0.0;
+    double *d_S = nullptr, *d_prefix = nullptr, *d_tauS = nullptr, *d_amaxS = nullptr;
+    int64_t *d_cntS = nullptr;
+    // solve workspace
+    int64_t ws_nrhs = 0;
+    std::vector<void *> ws;
+    double *d_xp = nullptr, *d_uv = nullptr, *d_bh = nullptr, *d_y = nullptr, *d_xg = nullptr, *d_res = nullptr,
+           *d_dx = nullptr, *d_norms = nullptr, *d_work = nullptr;
+    // timing
+    bool timing = false;
+    hipEvent_t ev[8] = {};
+    double times[5] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+int dalloc(kkt_ctx *ctx, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return KKT_OK;
+    bytes = align_up(bytes);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) { *p = nullptr; return e == hipErrorOutOfMemory ? KKT_ERR_NOMEM : KKT_ERR_HIP; }
+    ctx->allocs.emplace_back(*p, bytes);
+    ctx->bytes_static += bytes;
+    return KKT_OK;
+}
+
+template <typename V>
+int upload(kkt_ctx *ctx, V **dst, const std::vector<V> &src) {
+    int rc = dalloc(ctx, (void **)dst, sizeof(V) * std::max<size_t>(src.size(), 1));
+    if (rc) return rc;
+    if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice));
+    return KKT_OK;
+}
+
+void free_static(kkt_ctx *ctx) {
+    for (auto &a : ctx->allocs) (void)hipFree(a.first);
+    ctx->allocs.clear();
+    ctx->bytes_static = 0;
+}
+
+void free_ws(kkt_ctx *ctx) {
+    for (void *p : ctx->ws) (void)hipFree(p);
+    ctx->ws.clear();
+    ctx->bytes_ws = 0;
+    ctx->ws_nrhs = 0;
+}
+
+// right-looking 64-column steps over a set of fronts (FrontDesc indices `fl`)
+void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl, std::vector<int32_t> &buf,
+                std::vector<StepHost> &steps) {
+    int cmax = 0;
+    for (int32_t f : fl) cmax = std::max(cmax, fd[f].c);
+    for (int k0 = 0; k0 < cmax; k0 += 64) {
+        StepHost s{};
+        s.k0 = k0;
+        std::vector<int32_t> act;
+        for (int32_t f : fl)
+            if (fd[f].c > k0) act.push_back(f);
+        s.nf = (int)act.size();
+        s.fl_off = (int64_t)buf.size();
+        buf.insert(buf.end(), act.begin(), act.end());
+        s.pt_off = (int64_t)buf.size();
+        int acc = 0;
+        for (int32_t f : act) {
+            buf.push_back(acc);
+            int nb = std::min(64, fd[f].c - k0);
+            int rows = fd[f].m - k0 - nb;
+            acc += rows > 0 ? (rows + 255) / 256 : 0;
+        }
+        buf.push_back(acc);
+        s.ntrsm = acc;
+        s.pu_off = (int64_t)buf.size();
+        acc = 0;
+        for (int32_t f : act) {
+            buf.push_back(acc);
+            int nb = std::min(64, fd[f].c - k0);
+            int rows = fd[f].m - k0 - nb;
+            int T = rows > 0 ? (rows + 63) / 64 : 0;
+            acc += T * (T + 1) / 2;
+        }
+        buf.push_back(acc);
+        s.ntile = acc;
+        steps.push_back(s);
+    }
+}
+
+StepDev step_dev(const StepHost &s, const int32_t *base) {
+    StepDev d;
+    d.k0 = s.k0;
+    d.nf = s.nf;
+    d.fl = base + s.fl_off;
+    d.pre_trsm = base + s.pt_off;
+    d.pre_tile = base + s.pu_off;
+    d.ntrsm = s.ntrsm;
+    d.ntile = s.ntile;
+    return d;
+}
+
+TreeArgs tree_args(const kkt_ctx *ctx) {
+    TreeArgs t;
+    t.cptr = ctx->d_cptr;
+    t.clist = ctx->d_clist;
+    t.relptr = ctx->d_relptr;
+    t.rel = ctx->d_rel;
+    t.rows = ctx->d_rows;
+    t.rowptr = ctx->d_rowptr;
+    return t;
+}
+
+int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
+    const Symbolic &S = ctx->sy;
+    int rc;
+    std::vector<int32_t> adpiv(S.nnzA, -1);
+    for (int64_t j = 0; j < S.nA; ++j)
+        for (int64_t k = s->A_colptr[j]; k < s->A_colptr[j + 1]; ++k)
+            if (s->A_rowind[k] == j) adpiv[k] = S.iperm[j];
+    if ((rc = upload(ctx, &ctx->d_amap, S.amap))) return rc;
+    if ((rc = upload(ctx, &ctx->d_adiag, S.adiag))) return rc;
+    if ((rc = upload(ctx, &ctx->d_adpiv, adpiv))) return rc;
+    if ((rc = upload(ctx, &ctx->d_c0map, S.c0map))) return rc;
+    if ((rc = upload(ctx, &ctx->d_c1map, S.c1map))) return rc;
+    if ((rc = upload(ctx, &ctx->d_rows, S.rows))) return rc;
+    if ((rc = upload(ctx, &ctx->d_rowptr, S.rowptr))) return rc;
+    if ((rc = upload(ctx, &ctx->d_cptr, S.child_ptr))) return rc;
+    if ((rc = upload(ctx, &ctx->d_clist, S.child_list))) return rc;
+    if ((rc = upload(ctx, &ctx->d_relptr, S.relptr))) return rc;
+    if ((rc = upload(ctx, &ctx->d_rel, S.rel))) return rc;
+    if ((rc = upload(ctx, &ctx->d_perm, S.perm))) return rc;
+    if ((rc = upload(ctx, &ctx->d_pivsign, S.pivsign))) return rc;
+    std::vector<FrontDesc> fd(S.nsup);
+    for (int32_t t = 0; t < S.nsup; ++t) {
+        fd[t].Loff = S.Loff[t];
+        fd[t].Uoff = S.Uoff[t];
+        fd[t].m = S.nrow[t];
+        fd[t].c = S.ncol[t];
+        fd[t].piv0 = S.first[t];
+        fd[t].sn = t;
+    }
+    if ((rc = upload(ctx, &ctx->d_sd, fd))) return rc;
+    // per-level task lists
+    std::vector<int32_t> buf;
+    ctx->levels.assign(S.nlevels, LevelPlan());
+    ctx->steps.clear();
+    for (int32_t l = 0; l < S.nlevels; ++l) {
+        LevelPlan &lp = ctx->levels[l];
+        std::vector<int32_t> small, large, all;
+        for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+            int32_t t = S.level_list[q];
+            all.push_back(t);
+            lp.maxm = std::max(lp.maxm, S.nrow[t]);
+            if (S.nrow[t] <= 64) small.push_back(t);
+            else large.push_back(t);
+        }
+        lp.small_off = (int64_t)buf.size();
+        lp.nsmall = (int)small.size();
+        buf.insert(buf.end(), small.begin(), small.end());
+        lp.all_off = (int64_t)buf.size();
+        lp.nall = (int)all.size();
+        buf.insert(buf.end(), all.begin(), all.end());
+        lp.ea_off = (int64_t)buf.size();
+        if (buf.size() % 2) buf.push_back(0);  // RowTask alignment (pairs of int32)
+        lp.ea_off = (int64_t)buf.size();
+        int nea = 0;
+        for (int32_t t : large)
+            for (int r0 = 0; r0 < S.nrow[t]; r0 += 64) { buf.push_back(t); buf.push_back(r0); ++nea; }
+        lp.nea = nea;
+        lp.step_begin = (int)ctx->steps.size();
+        plan_steps(fd, large, buf, ctx->steps);
+        lp.step_end = (int)ctx->steps.size();
+    }
+    if ((rc = upload(ctx, &ctx->d_tasks, buf))) return rc;
+    // Schur front and its steps
+    if (ctx->ng > 0) {
+        std::vector<FrontDesc> sdS(1);
+        sdS[0].Loff = 0;
+        sdS[0].Uoff = 0;
+        sdS[0].m = (int32_t)ctx->ng;
+        sdS[0].c = (int32_t)ctx->ng;
+        sdS[0].piv0 = 0;
+        sdS[0].sn = 0;
+        if ((rc = upload(ctx, &ctx->d_sdS, sdS))) return rc;
+        std::vector<int32_t> sbuf;
+        ctx->ssteps.clear();
+        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps);
+        if ((rc = upload(ctx, &ctx->d_stasks, sbuf))) return rc;
+    }
+    // residual: full symmetric CSR of the pattern (caller order) and C^T by column
+    {
+        const int64_t nA = S.nA;
+        std::vector<int64_t> rp(nA + 1, 0);
+        for (int64_t j = 0; j < nA; ++j)
+            for (int64_t k = s->A_colptr[j]; k < s->A_colptr[j + 1]; ++k) {
+                int32_t i = s->A_rowind[k];
+                rp[i + 1]++;
+                if (i != j) rp[j + 1]++;
+            }
+        for (int64_t i = 0; i < nA; ++i) rp[i + 1] += rp[i];
+        std::vector<int32_t> ci(rp[nA]);
+        std::vector<int64_t> vi(rp[nA]);
+        std::vector<int64_t> q(rp.begin(), rp.end() - 1);
+        for (int64_t j = 0; j < nA; ++j)
+            for (int64_t k = s->A_colptr[j]; k < s->A_colptr[j + 1]; ++k) {
+                int32_t i = s->A_rowind[k];
+                ci[q[i]] = (int32_t)j;
+                vi[q[i]++] = k;
+                if (i != j) { ci[q[j]] = i; vi[q[j]++] = k; }
+            }
+        if ((rc = upload(ctx, &ctx->d_rp, rp))) return rc;
+        if ((rc = upload(ctx, &ctx->d_ci, ci))) return rc;
+        if ((rc = upload(ctx, &ctx->d_vi, vi))) return rc;
+        const int64_t Ns = S.Ns;
+        auto transpose = [&](const int64_t *p, const int32_t *c, std::vector<int64_t> &tp, std::vector<int32_t> &ts,
+                             std::vector<int64_t> &tk) {
+            tp.assign(nA + 1, 0);
+            for (int64_t sidx = 0; sidx < Ns; ++sidx)
+                for (int64_t k = p[sidx]; k < p[sidx + 1]; ++k) tp[c[k] + 1]++;
+            for (int64_t i = 0; i < nA; ++i) tp[i + 1] += tp[i];
+            ts.assign(tp[nA], 0);
+            tk.assign(tp[nA], 0);
+            std::vector<int64_t> qq(tp.begin(), tp.end() - 1);
+            for (int64_t sidx = 0; sidx < Ns; ++sidx)
+                for (int64_t k = p[sidx]; k < p[sidx + 1]; ++k) { ts[qq[c[k]]] = (int32_t)sidx; tk[qq[c[k]]++] = k; }
+        };
+        std::vector<int64_t> c1tp, c0tp, c1tk, c0tk, c0p, c1p;
+        std::vector<int32_t> c1ts, c0ts, c0i, c1i;
+        if (Ns > 0) {
+            transpose(s->C1_rowptr, s->C1_colind, c1tp, c1ts, c1tk);
+            transpose(s->C0_rowptr, s->C0_colind, c0tp, c0ts, c0tk);
+            c0p.assign(s->C0_rowptr, s->C0_rowptr + Ns + 1);
+            c1p.assign(s->C1_rowptr, s->C1_rowptr + Ns + 1);
+            c0i.assign(s->C0_colind, s->C0_colind + c0p[Ns]);
+            c1i.assign(s->C1_colind, s->C1_colind + c1p[Ns]);
+        } else {
+            c1tp.assign(nA + 1, 0);
+            c0tp.assign(nA + 1, 0);
+            c0p.assign(1, 0);
+            c1p.assign(1, 0);
+        }
+        if ((rc = upload(ctx, &ctx->d_c1tp, c1tp))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c0tp, c0tp))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c1ts, c1ts))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c0ts, c0ts))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c1tk, c1tk))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c0tk, c0tk))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c0p, c0p))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c1p, c1p))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c0i, c0i))) return rc;
+        if ((rc = upload(ctx, &ctx->d_c1i, c1i))) return rc;
+    }
+    // numeric storage
+    const size_t w = ctx->opt.precision == KKT_MIXED ? 4 : 8;
+    if ((rc = dalloc(ctx, &ctx->d_L, w * S.Lsize * ctx->N))) return rc;
+    if ((rc = dalloc(ctx, &ctx->d_U, w * std::max<int64_t>(S.Usize, 1) * ctx->N))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_tau, 8 * S.nA * ctx->N))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_amax, 8 * (ctx->N + 1)))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_cnt, 8 * 4 * (ctx->N + 1)))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_flag, 256))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_A, 8 * S.nnzA * ctx->N))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_C0, 8 * std::max<int64_t>(S.nnzC0, 1)))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_C1, 8 * std::max<int64_t>(S.nnzC1, 1)))) return rc;
+    if (ctx->ng > 0) {
+        if ((rc = dalloc(ctx, (void **)&ctx->d_corner, 8 * ctx->ng))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_S, 8 * ctx->ng * ctx->ng))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_prefix, 8 * (ctx->N + 1) * S.Ns * S.Ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_tauS, 8 * ctx->ng))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_amaxS, 256))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_cntS, 256))) return rc;
+    }
+    return KKT_OK;
+}
+
+int ensure_ws(kkt_ctx *ctx, int64_t nrhs) {
+    if (ctx->ws_nrhs >= nrhs) return KKT_OK;
+    free_ws(ctx);
+    const Symbolic &S = ctx->sy;
+    auto get = [&](double **p, int64_t count) -> int {
+        size_t bytes = align_up(8 * std::max<int64_t>(count, 1));
+        hipError_t e = hipMalloc((void **)p, bytes);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? KKT_ERR_NOMEM : KKT_ERR_HIP;
+        ctx->ws.push_back(*p);
+        ctx->bytes_ws += bytes;
+        return KKT_OK;
+    };
+    int rc;
+    if ((rc = get(&ctx->d_xp, (S.nA + S.nbord) * ctx->N * nrhs))) return rc;
+    if ((rc = get(&ctx->d_uv, S.Usize_vec() * ctx->N * nrhs))) return rc;
+    if ((rc = get(&ctx->d_bh, ctx->ng * nrhs))) return rc;
+    if ((rc = get(&ctx->d_y, ctx->ng * nrhs))) return rc;
+    if ((rc = get(&ctx->d_xg, ctx->ng * nrhs))) return rc;
+    if ((rc = get(&ctx->d_res, ctx->ntot * nrhs))) return rc;
+    if ((rc = get(&ctx->d_dx, ctx->ntot * nrhs))) return rc;
+    if ((rc = get(&ctx->d_norms, 4 * nrhs + 8))) return rc;
+    if ((rc = get(&ctx->d_work, ctx->N * S.Ns * nrhs + 2 * 512 * nrhs + 8))) return rc;
+    ctx->ws_nrhs = nrhs;
+    return KKT_OK;
+}
+
+template <typename T>
+FactorArgs<T> factor_args(kkt_ctx *ctx) {
+    FactorArgs<T> fa;
+    fa.L = (T *)ctx->d_L;
+    fa.U = (T *)ctx->d_U;
+    fa.Lstride = ctx->sy.Lsize;
+    fa.Ustride = ctx->sy.Usize;
+    fa.tau = ctx->d_tau;
+    fa.tstride = ctx->sy.nA;
+    fa.amax = ctx->d_amax;
+    fa.sign = ctx->d_pivsign;
+    fa.cnt = ctx->d_cnt;
+    fa.eps = ctx->eps;
+    return fa;
+}
+
+FactorArgs<double> schur_args(kkt_ctx *ctx) {
+    FactorArgs<double> fa;
+    fa.L = ctx->d_S;
+    fa.U = nullptr;
+    fa.Lstride = 0;
+    fa.Ustride = 0;
+    fa.tau = ctx->d_tauS;
+    fa.tstride = 0;
+    fa.amax = ctx->d_amaxS;
+    fa.sign = nullptr;
+    fa.cnt = ctx->d_cntS;
+    fa.eps = ctx->eps;
+    return fa;
+}
+
+void mark(kkt_ctx *ctx, int i) {
+    if (ctx->timing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+}
+
+template <typename T>
+int factor_blocks(kkt_ctx *ctx) {
+    const Symbolic &S = ctx->sy;
+    hipStream_t st = ctx->stream;
+    FactorArgs<T> fa = factor_args<T>(ctx);
+    const int64_t N = ctx->N;
+    launch_zero<T>((T *)ctx->d_L, S.Lsize * N, st);
+    launch_zero<T>((T *)ctx->d_U, S.Usize * N, st);
+    launch_zero<double>(ctx->d_tau, S.nA * N, st);
+    launch_zero<double>(ctx->d_amax, N + 1, st);
+    launch_zero<int64_t>(ctx->d_cnt, 4 * (N + 1), st);
+    ScatterArgs sa;
+    sa.A = ctx->d_A;
+    sa.nnz = S.nnzA;
+    sa.amap = ctx->d_amap;
+    sa.adiag = ctx->d_adiag;
+    sa.adpiv = ctx->d_adpiv;
+    sa.dw = ctx->dw;
+    sa.dc = ctx->dc;
+    sa.C0 = ctx->d_C0;
+    sa.C1 = ctx->d_C1;
+    sa.n0 = S.nnzC0;
+    sa.n1 = S.nnzC1;
+    sa.c0map = ctx->d_c0map;
+    sa.c1map = ctx->d_c1map;
+    launch_scatter<T>(sa, fa, N, st);
+    TreeArgs tr = tree_args(ctx);
+    for (const LevelPlan &lp : ctx->levels) {
+        launch_small_fronts<T>(fa, ctx->d_sd, ctx->d_tasks + lp.small_off, lp.nsmall, N, tr, st);
+        launch_extend_add<T>(fa, ctx->d_sd, (const RowTask *)(ctx->d_tasks + lp.ea_off), lp.nea, N, tr, st);
+        for (int q = lp.step_begin; q < lp.step_end; ++q)
+            launch_step<T>(fa, ctx->d_sd, step_dev(ctx->steps[q], ctx->d_tasks), N, st);
+    }
+    return KKT_OK;
+}
+
+int factor_schur(kkt_ctx *ctx) {
+    if (ctx->ng == 0) return KKT_OK;
+    hipStream_t st = ctx->stream;
+    const Symbolic &S = ctx->sy;
+    const int64_t uoff = S.Uoff[S.border_sn];
+    launch_zero<double>(ctx->d_amaxS, 1, st);
+    launch_zero<int64_t>(ctx->d_cntS, 4, st);
+    launch_schur_prefix(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
+    launch_schur_assemble(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
+                          ctx->has_corner ? ctx->d_corner : nullptr, ctx->d_S, ctx->d_tauS, ctx->eps,
+                          ctx->d_amaxS, 0, st);
+    mark(ctx, 2);
+    FactorArgs<double> fa = schur_args(ctx);
+    for (const StepHost &s : ctx->ssteps) launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, st);
+    return KKT_OK;
+}
+
+// one pass of Algorithm 1's solve for the right-hand sides in `b` (device,
+// [nrhs][ntot]) into `x`
+template <typename T>
+int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
+    const Symbolic &S = ctx->sy;
+    hipStream_t st = ctx->stream;
+    SolveArgs sa;
+    sa.N = ctx->N;
+    sa.nrhs = nrhs;
+    sa.nv = S.nA + S.nbord;
+    sa.usz = S.Usize_vec();
+    sa.xp = ctx->d_xp;
+    sa.uv = ctx->d_uv;
+    TreeArgs tr = tree_args(ctx);
+    const T *L = (const T *)ctx->d_L;
+    launch_gather_rhs<T>(b, ctx->ntot, S.nA, ctx->d_perm, sa, st);
+    for (const LevelPlan &lp : ctx->levels)
+        launch_fwd_level<T>(L, S.Lsize, ctx->d_sd, ctx->d_tasks + lp.all_off, lp.nall, lp.maxm, tr, sa, st);
+    if (ctx->ng > 0) {
+        launch_schur_rhs(b, ctx->ntot, S.nA, sa, S.Ns, S.relptr[S.border_sn], ctx->d_bh, st);
+        launch_dense_fwd(ctx->d_S, ctx->ng, ctx->d_bh, ctx->d_y, nrhs, st);
+        launch_dense_bwd(ctx->d_S, ctx->ng, ctx->d_y, ctx->d_xg, nrhs, st);
+        launch_border_values(ctx->d_xg, sa, S.nA, S.Ns, st);
+    }
+    for (int l = (int)ctx->levels.size() - 1; l >= 0; --l) {
+        const LevelPlan &lp = ctx->levels[l];
+        launch_bwd_level<T>(L, S.Lsize, ctx->d_sd, ctx->d_tasks + lp.all_off, lp.nall, lp.maxm, tr, sa, st);
+    }
+    launch_scatter_x(x, ctx->ntot, S.nA, ctx->d_perm, sa, ctx->d_xg, ctx->ng, st);
+    return KKT_OK;
+}
+
+ResidualArgs residual_args(kkt_ctx *ctx, int64_t nrhs) {
+    const Symbolic &S = ctx->sy;
+    ResidualArgs ra;
+    ra.N = ctx->N;
+    ra.nA = S.nA;
+    ra.Ns = S.Ns;
+    ra.ntot = ctx->ntot;
+    ra.nrhs = nrhs;
+    ra.A = ctx->d_A;
+    ra.nnz = S.nnzA;
+    ra.rp = ctx->d_rp;
+    ra.ci = ctx->d_ci;
+    ra.vi = ctx->d_vi;
+    ra.c1tp = ctx->d_c1tp;
+    ra.c0tp = ctx->d_c0tp;
+    ra.c1ts = ctx->d_c1ts;
+    ra.c0ts = ctx->d_c0ts;
+    ra.c1tk = ctx->d_c1tk;
+    ra.c0tk = ctx->d_c0tk;
+    ra.c0p = ctx->d_c0p;
+    ra.c1p = ctx->d_c1p;
+    ra.c0i = ctx->d_c0i;
+    ra.c1i = ctx->d_c1i;
+    ra.C0v = ctx->d_C0;
+    ra.C1v = ctx->d_C1;
+    ra.corner = ctx->has_corner ? ctx->d_corner : nullptr;
+    ra.dw = ctx->dw;
+    ra.dc = ctx->dc;
+    ra.n_primal = S.n_primal;
+    return ra;
+}
+
+double elapsed(kkt_ctx *ctx, int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
+    if (!out) return KKT_ERR_ARG;
+    *out = nullptr;
+    kkt_ctx *ctx = new (std::nothrow) kkt_ctx();
+    if (!ctx) return KKT_ERR_NOMEM;
+    kkt_default_options(&ctx->opt);
+    if (opt) ctx->opt = *opt;
+    if (ctx->opt.precision != KKT_FP64 && ctx->opt.precision != KKT_MIXED) { delete ctx; return KKT_ERR_ARG; }
+    if (ctx->opt.refine_tol <= 0) ctx->opt.refine_tol = 1e-10;
+    if (ctx->opt.refine_max < 0) ctx->opt.refine_max = 0;
+    ctx->eps = ctx->opt.pivot_eps > 0 ? ctx->opt.pivot_eps : (ctx->opt.precision == KKT_MIXED ? 1e-10 : 1e-20);
+    ctx->stream = (hipStream_t)stream;
+    if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return KKT_ERR_HIP; }
+    for (auto &e : ctx->ev)
+        if (hipEventCreate(&e) != hipSuccess) { delete ctx; return KKT_ERR_HIP; }
+    *out = ctx;
+    return KKT_OK;
+}
+
+extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
+    if (!ctx || !s || s->N < 1 || s->Ns < 0 || s->nA < 1) return KKT_ERR_ARG;
+    if (!s->A_colptr || !s->A_rowind) return KKT_ERR_ARG;
+    if (s->Ns > 0 && (!s->C0_rowptr || !s->C0_colind || !s->C1_rowptr || !s->C1_colind)) return KKT_ERR_ARG;
+    Symbolic S;
+    std::string err;
+    try {
+        err = analyze(make_input(s), S);
+    } catch (...) {
+        return KKT_ERR_NOMEM;
+    }
+    if (!err.empty()) {
+        if (ctx->opt.verbose) std::fprintf(stderr, "kkt_analyze: %s\n", err.c_str());
+        return KKT_ERR_STRUCT;
+    }
+    if (S.max_front > 20000 || (s->N * s->Ns) > 46000) return KKT_ERR_ARG;  // 32-bit launch/index limits
+    (void)hipStreamSynchronize(ctx->stream);
+    free_ws(ctx);
+    free_static(ctx);
+    ctx->analyzed = ctx->factored = false;
+    ctx->sy = std::move(S);
+    ctx->N = s->N;
+    ctx->ng = s->N * s->Ns;
+    ctx->ntot = s->N * s->nA + ctx->ng;
+    int rc = build_device_symbolic(ctx, s);
+    if (rc) { free_static(ctx); return rc; }
+    ctx->analyzed = true;
+    return KKT_OK;
+}
+
+extern "C" int kkt_footprint(const kkt_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return KKT_ERR_ARG;
+    *bytes = ctx->bytes_static + ctx->bytes_ws;
+    return KKT_OK;
+}
+
+extern "C" int kkt_stats(const kkt_ctx *ctx, kkt_symbolic_stats *st) {
+    if (!ctx || !st) return KKT_ERR_ARG;
+    if (!ctx->analyzed) return KKT_ERR_ORDER;
+    fill_stats(ctx->sy, ctx->N, ctx->opt.precision, std::max<int64_t>(ctx->ws_nrhs, 1), st);
+    st->device_bytes = (int64_t)(ctx->bytes_static + ctx->bytes_ws);
+    return KKT_OK;
+}
+
+extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals, const double *C1_vals,
+                          const double *corner_diag, double delta_w, double delta_c, kkt_inertia *out) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->analyzed) return KKT_ERR_ORDER;
+    const Symbolic &S = ctx->sy;
+    if (!A_vals || (S.Ns > 0 && (!C0_vals || !C1_vals))) return KKT_ERR_ARG;
+    if (!std::isfinite(delta_w) || !std::isfinite(delta_c) || delta_w < 0 || delta_c < 0) return KKT_ERR_ARG;
+    hipStream_t st = ctx->stream;
+    // reject non-finite input before any state changes
+    launch_zero<int>(ctx->d_flag, 1, st);
+    launch_check_finite(A_vals, S.nnzA * ctx->N, ctx->d_flag, st);
+    if (S.Ns > 0) {
+        launch_check_finite(C0_vals, S.nnzC0, ctx->d_flag, st);
+        launch_check_finite(C1_vals, S.nnzC1, ctx->d_flag, st);
+    }
+    if (corner_diag && ctx->ng) launch_check_finite(corner_diag, ctx->ng, ctx->d_flag, st);
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flag) return KKT_ERR_NONFINITE;
+    HIPCHK(hipMemcpyAsync(ctx->d_A, A_vals, 8 * S.nnzA * ctx->N, hipMemcpyDeviceToDevice, st));
+    if (S.Ns > 0) {
+        HIPCHK(hipMemcpyAsync(ctx->d_C0, C0_vals, 8 * S.nnzC0, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(ctx->d_C1, C1_vals, 8 * S.nnzC1, hipMemcpyDeviceToDevice, st));
+    }
+    ctx->has_corner = corner_diag != nullptr && ctx->ng > 0;
+    if (ctx->has_corner) HIPCHK(hipMemcpyAsync(ctx->d_corner, corner_diag, 8 * ctx->ng, hipMemcpyDeviceToDevice, st));
+    ctx->dw = delta_w;
+    ctx->dc = delta_c;
+    mark(ctx, 0);
+    int rc = ctx->opt.precision == KKT_MIXED ? factor_blocks<float>(ctx) : factor_blocks<double>(ctx);
+    if (rc) return rc;
+    mark(ctx, 1);
+    rc = factor_schur(ctx);
+    if (rc) return rc;
+    mark(ctx, 3);
+    HIPCHK(hipGetLastError());
+    ctx->factored = true;
+    if (ctx->timing) {
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->times[0] = elapsed(ctx, 0, 1);
+        ctx->times[1] = ctx->ng ? elapsed(ctx, 1, 2) : 0.0;
+        ctx->times[2] = ctx->ng ? elapsed(ctx, 2, 3) : 0.0;
+    }
+    if (!out) return KKT_OK;
+    std::vector<int64_t> cnt(4 * (ctx->N + 1), 0), cs(4, 0);
+    HIPCHK(hipMemcpyAsync(cnt.data(), ctx->d_cnt, 8 * 4 * ctx->N, hipMemcpyDeviceToHost, st));
+    if (ctx->ng) HIPCHK(hipMemcpyAsync(cs.data(), ctx->d_cntS, 8 * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    kkt_inertia in{};
+    for (int64_t n = 0; n < ctx->N; ++n) {
+        in.n_pos += cnt[4 * n + 0];
+        in.n_neg += cnt[4 * n + 1];
+        in.n_zero += cnt[4 * n + 2];
+        in.n_perturbed += cnt[4 * n + 3];
+    }
+    in.n_pos += cs[0];
+    in.n_neg += cs[1];
+    in.n_zero += cs[2];
+    in.n_perturbed += cs[3];
+    const int64_t epos = ctx->N * S.n_primal, eneg = ctx->N * (S.nA - S.n_primal) + ctx->ng;
+    in.inertia_ok = (in.n_pos == epos && in.n_neg == eneg && in.n_zero == 0) ? 1 : 0;
+    *out = in;
+    if (!in.inertia_ok) return KKT_WARN_INERTIA;
+    if (in.n_perturbed) return KKT_WARN_PERTURBED;
+    return KKT_OK;
+}
+
+extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, kkt_solve_info *info) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->analyzed || !ctx->factored) return KKT_ERR_ORDER;
+    if (!b || !x || b == x || nrhs < 1 || nrhs > 64) return KKT_ERR_ARG;
+    int rc = ensure_ws(ctx, nrhs);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    const bool mixed = ctx->opt.precision == KKT_MIXED;
+    mark(ctx, 4);
+    rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
+    if (rc) return rc;
+    ResidualArgs ra = residual_args(ctx, nrhs);
+    std::vector<double> nh(4 * nrhs);
+    double rel = 0.0, omega = 0.0;
+    int it = 0, status = KKT_OK;
+    std::vector<double> hist;
+    while (true) {
+        launch_residual(ra, b, x, ctx->d_res, ctx->d_work, ctx->d_norms, st);
+        HIPCHK(hipMemcpyAsync(nh.data(), ctx->d_norms, 8 * 4 * nrhs, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        rel = 0.0;
+        omega = 0.0;
+        for (int64_t k = 0; k < nrhs; ++k) {
+            double rb = nh[4 * k + 1] > 0 ? nh[4 * k + 0] / nh[4 * k + 1] : nh[4 * k + 0];
+            rel = std::max(rel, rb);
+            omega = std::max(omega, nh[4 * k + 2]);
+        }
+        if (ctx->opt.verbose)
+            std::fprintf(stderr, "kkt_solve: refinement step %d rel_res %.3e omega %.3e\n", it, rel, omega);
+        if (!std::isfinite(rel)) { status = KKT_WARN_REFINE; break; }
+        hist.push_back(rel);
+        if (rel <= ctx->opt.refine_tol) break;
+        // componentwise backward error at the FP64 rounding level: no step can
+        // improve the solution further
+        if (omega <= 4.0 * 2.220446049250313e-16) { status = KKT_WARN_REFINE; break; }
+        if (it >= ctx->opt.refine_max) { status = KKT_WARN_REFINE; break; }
+        size_t h = hist.size();
+        if (h >= 4 && hist[h - 1] > 0.5 * hist[h - 3] && hist[h - 2] > 0.5 * hist[h - 4]) {
+            status = KKT_WARN_REFINE;  // stagnation
+            break;
+        }
+        rc = mixed ? solve_once<float>(ctx, ctx->d_res, ctx->d_dx, nrhs)
+                   : solve_once<double>(ctx, ctx->d_res, ctx->d_dx, nrhs);
+        if (rc) return rc;
+        launch_axpy(x, ctx->d_dx, ctx->ntot * nrhs, st);
+        ++it;
+    }
+    mark(ctx, 5);
+    HIPCHK(hipGetLastError());
+    if (ctx->timing) {
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->times[3] = elapsed(ctx, 4, 5);
+    }
+    if (info) {
+        info->refine_iters = it;
+        info->rel_res = rel;
+        info->omega = omega;
+        info->fallback_used = 0;
+    }
+    return status;
+}
+
+extern "C" int kkt_schur(kkt_ctx *ctx, double *S_out) {
+    if (!ctx || !S_out) return KKT_ERR_ARG;
+    if (!ctx->factored) return KKT_ERR_ORDER;
+    if (ctx->ng == 0) return KKT_OK;
+    const Symbolic &S = ctx->sy;
+    const int64_t uoff = S.Uoff[S.border_sn];
+    launch_schur_prefix(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, ctx->stream);
+    launch_schur_assemble(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
+                          ctx->has_corner ? ctx->d_corner : nullptr, S_out, nullptr, 0.0, nullptr, 1, ctx->stream);
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+extern "C" int kkt_schur_blocks(kkt_ctx *ctx, double *out) {
+    if (!ctx || !out) return KKT_ERR_ARG;
+    if (!ctx->factored) return KKT_ERR_ORDER;
+    if (ctx->ng == 0) return KKT_OK;
+    const Symbolic &S = ctx->sy;
+    launch_copy_sbar(ctx->d_U, S.Usize, S.Uoff[S.border_sn], ctx->N, S.nbord, ctx->opt.precision, out, ctx->stream);
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+extern "C" int kkt_enable_timing(kkt_ctx *ctx, int on) {
+    if (!ctx) return KKT_ERR_ARG;
+    ctx->timing = on != 0;
+    return KKT_OK;
+}
+
+extern "C" int kkt_phase_times(kkt_ctx *ctx, double *t) {
+    if (!ctx || !t) return KKT_ERR_ARG;
+    for (int i = 0; i < 5; ++i) t[i] = ctx->times[i];
+    return KKT_OK;
+}
+
+extern "C" void kkt_destroy(kkt_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_ws(ctx);
+    free_static(ctx);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}

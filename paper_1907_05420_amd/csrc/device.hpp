@@ -1,0 +1,66 @@
+// Shared device-side declarations: task descriptors, MFMA wrappers, atomics.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace kkt {
+
+// A dense front of one supernode in the per-period storage: a column-major
+// panel (m x c, ld m) holding the pivot columns, followed conceptually by the
+// update block U (u x u, ld u, u = m - c) holding rows/columns >= c.
+// Front-local element (r, q), r >= q, lives in the panel when q < c, else in U.
+struct FrontDesc {
+    int64_t Loff;   // panel offset inside one period's factor storage
+    int64_t Uoff;   // update block offset inside one period's update storage
+    int32_t m, c;   // rows, pivots
+    int32_t piv0;   // global pivot index of panel column 0 (new order)
+    int32_t sn;     // supernode id
+};
+
+struct TileTask {   // one 64x64 tile of a trailing update of front `f`
+    int32_t f, ti, tj, pad;
+};
+
+struct RowTask {    // up to 256 consecutive rows [r0, ...) of front `f`
+    int32_t f, r0;
+};
+
+// Factor-wide pointers handed to every factor kernel.
+template <typename T>
+struct FactorArgs {
+    T *L;               // [N][Lstride]
+    T *U;               // [N][Ustride]
+    int64_t Lstride, Ustride;
+    const double *tau;  // [N][tstride] per-pivot threshold eps*|a_kk| (0: use eps*amax)
+    int64_t tstride;
+    const double *amax; // [N] max |a_ij| of each matrix
+    const int8_t *sign; // [npiv] expected sign for an exactly zero pivot, or null (-1)
+    int64_t *cnt;       // [N][4] (n_pos, n_neg, n_zero, n_perturbed)
+    double eps;
+};
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline v4f mfma16x16x4(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Output row of accumulator register rr held by a lane in row group lk
+// (lane / 16) of a 16x16x4 MFMA; the column is lane % 16. FP64: rows
+// lk, lk+4, lk+8, lk+12; FP32: rows 4*lk .. 4*lk+3 (checked on gfx950).
+__device__ inline int mfma_row(double, int lk, int rr) { return lk + 4 * rr; }
+__device__ inline int mfma_row(float, int lk, int rr) { return 4 * lk + rr; }
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef v4d type; };
+template <> struct Acc<float> { typedef v4f type; };
+
+// max of non-negative doubles through their bit patterns (order preserving)
+__device__ inline void atomic_max_nonneg(double *addr, double v) {
+    atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+}  // namespace kkt

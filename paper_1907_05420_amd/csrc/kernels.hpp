@@ -1,0 +1,109 @@
+// Host-side launchers of the device kernels (declarations).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace kkt {
+
+struct ScatterArgs {
+    const double *A;
+    int64_t nnz;
+    const int64_t *amap;
+    const int8_t *adiag;
+    const int32_t *adpiv;
+    double dw, dc;
+    const double *C0, *C1;
+    int64_t n0, n1;
+    const int64_t *c0map, *c1map;
+};
+
+struct TreeArgs {
+    const int32_t *cptr, *clist;
+    const int64_t *relptr;
+    const int32_t *rel;
+    const int32_t *rows;
+    const int64_t *rowptr;
+};
+
+// one right-looking step over a group of large fronts
+struct StepDev {
+    int k0;
+    int nf;                 // fronts with pivots left at k0
+    const int32_t *fl;      // their FrontDesc indices
+    const int32_t *pre_trsm, *pre_tile;  // prefix sums of row chunks / tiles
+    int ntrsm, ntile;
+};
+
+template <typename T> void launch_zero(T *p, int64_t n, hipStream_t st);
+void launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st);
+template <typename T> void launch_scatter(const ScatterArgs &a, FactorArgs<T> fa, int64_t N, hipStream_t st);
+template <typename T>
+void launch_small_fronts(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *tasks, int ntasks, int64_t N,
+                         const TreeArgs &tr, hipStream_t st);
+template <typename T>
+void launch_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const RowTask *tasks, int ntasks, int64_t N,
+                       const TreeArgs &tr, hipStream_t st);
+template <typename T>
+void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_t N, hipStream_t st);
+
+// ---- solve -------------------------------------------------------------------
+struct SolveArgs {
+    int64_t N, nrhs, nv;     // nv = nA + nbord (length of a period's permuted vector)
+    int64_t usz;             // sum of update rows (per period, per rhs)
+    double *xp;              // [N][nrhs][nv]
+    double *uv;              // [N][nrhs][usz]
+};
+
+template <typename T>
+void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa,
+                       hipStream_t st);
+template <typename T>
+void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
+                      const TreeArgs &tr, SolveArgs sa, hipStream_t st);
+template <typename T>
+void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
+                      const TreeArgs &tr, SolveArgs sa, hipStream_t st);
+void launch_scatter_x(double *x, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa, const double *xg,
+                      int64_t ng, hipStream_t st);
+// border glue: rhs of the Schur system and the border values for the backward pass
+void launch_schur_rhs(const double *b, int64_t ntot, int64_t nA, SolveArgs sa, int64_t Ns, int64_t uoff_border,
+                      double *bh, hipStream_t st);
+void launch_border_values(const double *xg, SolveArgs sa, int64_t nA, int64_t Ns, hipStream_t st);
+
+// dense Schur: assembly, factor steps reuse launch_step, triangular solves
+void launch_schur_prefix(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
+                         double *prefix, hipStream_t st);
+void launch_schur_assemble(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
+                           const double *prefix, const double *corner, double *S, double *tau_s, double eps,
+                           double *amax_s, int mirror, hipStream_t st);
+void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t nb, int precision,
+                      double *out, hipStream_t st);
+void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st);
+void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st);
+
+// ---- residual ------------------------------------------------------------------
+struct ResidualArgs {
+    int64_t N, nA, Ns, ntot, nrhs;
+    const double *A;           // [N][nnz]
+    int64_t nnz;
+    const int64_t *rp;         // full symmetric CSR of the pattern (old order)
+    const int32_t *ci;
+    const int64_t *vi;         // value index into the lower CSC of each CSR entry
+    const int64_t *c1tp, *c0tp;   // C_1^T, C_0^T by A column: (s, k)
+    const int32_t *c1ts, *c0ts;
+    const int64_t *c1tk, *c0tk;
+    const int64_t *c0p, *c1p;  // C_0 / C_1 CSR
+    const int32_t *c0i, *c1i;
+    const double *C0v, *C1v;
+    const double *corner;      // [ng] or null
+    double dw, dc;
+    int64_t n_primal;
+};
+// r = b - K x, plus per-rhs partial sums for ||r||_2, ||b||_2 and max omega
+void launch_residual(const ResidualArgs &ra, const double *b, const double *x, double *r, double *work,
+                     double *norms, hipStream_t st);
+void launch_axpy(double *x, const double *dx, int64_t n, hipStream_t st);
+
+}  // namespace kkt
