@@ -35,8 +35,8 @@ using namespace kkt;
 namespace {
 
 struct StepHost {
-    int k0, nf, ntrsm, ntile;
-    int64_t fl_off, pt_off, pu_off;  // offsets (int32 elements) into the task buffer
+    int kind, t0, pe, nf, ntasks;
+    int64_t fl_off, pre_off;  // offsets (int32 elements) into the task buffer
 };
 
 struct LevelPlan {
@@ -128,54 +128,61 @@ void free_ws(kkt_ctx *ctx) {
     ctx->ws_nrhs = 0;
 }
 
-// right-looking 64-column steps over a set of fronts (FrontDesc indices `fl`)
+// launch sequence of the blocked factorisation of a set of fronts
 void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl, std::vector<int32_t> &buf,
-                std::vector<StepHost> &steps) {
+                std::vector<StepHost> &steps, bool invert_panels = false) {
     int cmax = 0;
     for (int32_t f : fl) cmax = std::max(cmax, fd[f].c);
-    for (int k0 = 0; k0 < cmax; k0 += 64) {
-        StepHost s{};
-        s.k0 = k0;
+    auto add = [&](int kind, int t0, int pe) {
         std::vector<int32_t> act;
-        for (int32_t f : fl)
-            if (fd[f].c > k0) act.push_back(f);
+        std::vector<int> cnt;
+        for (int32_t f : fl) {
+            if (fd[f].c <= t0) continue;
+            int k = step_tasks(kind, t0, pe, fd[f].c, fd[f].m);
+            if (k <= 0) continue;
+            act.push_back(f);
+            cnt.push_back(k);
+        }
+        if (act.empty()) return;
+        StepHost s{};
+        s.kind = kind;
+        s.t0 = t0;
+        s.pe = pe;
         s.nf = (int)act.size();
         s.fl_off = (int64_t)buf.size();
         buf.insert(buf.end(), act.begin(), act.end());
-        s.pt_off = (int64_t)buf.size();
+        s.pre_off = (int64_t)buf.size();
         int acc = 0;
-        for (int32_t f : act) {
-            buf.push_back(acc);
-            int nb = std::min(64, fd[f].c - k0);
-            int rows = fd[f].m - k0 - nb;
-            acc += rows > 0 ? (rows + 255) / 256 : 0;
-        }
+        for (int k : cnt) { buf.push_back(acc); acc += k; }
         buf.push_back(acc);
-        s.ntrsm = acc;
-        s.pu_off = (int64_t)buf.size();
-        acc = 0;
-        for (int32_t f : act) {
-            buf.push_back(acc);
-            int nb = std::min(64, fd[f].c - k0);
-            int rows = fd[f].m - k0 - nb;
-            int T = rows > 0 ? (rows + 63) / 64 : 0;
-            acc += T * (T + 1) / 2;
-        }
-        buf.push_back(acc);
-        s.ntile = acc;
+        s.ntasks = acc;
         steps.push_back(s);
+    };
+    for (int k = 0; k < cmax; k += OUTER_W) {
+        const int pe = k + OUTER_W;
+        for (int j0 = k; j0 < std::min(pe, cmax); j0 += 64) {
+            add(0, j0, pe);
+            add(1, j0, pe);
+            add(2, j0, pe);
+        }
+        // large trailing matrices take the 128x128 tile kernel
+        int big = 0;
+        for (int32_t f : fl)
+            if (fd[f].c > k && fd[f].m - std::min(pe, fd[f].c) >= 512) big = 1;
+        add(big ? 4 : 3, k, pe);
+        if (invert_panels) add(5, k, pe);  // inverse of the panel's diagonal block (dense Schur solves)
     }
 }
 
 StepDev step_dev(const StepHost &s, const int32_t *base) {
     StepDev d;
-    d.k0 = s.k0;
+    d.kind = s.kind;
+    d.t0 = s.t0;
+    d.pe = s.pe;
     d.nf = s.nf;
     d.fl = base + s.fl_off;
-    d.pre_trsm = base + s.pt_off;
-    d.pre_tile = base + s.pu_off;
-    d.ntrsm = s.ntrsm;
-    d.ntile = s.ntile;
+    d.pre = base + s.pre_off;
+    d.ntasks = s.ntasks;
     return d;
 }
 
@@ -264,7 +271,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = upload(ctx, &ctx->d_sdS, sdS))) return rc;
         std::vector<int32_t> sbuf;
         ctx->ssteps.clear();
-        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps);
+        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true);
         if ((rc = upload(ctx, &ctx->d_stasks, sbuf))) return rc;
     }
     // residual: full symmetric CSR of the pattern (caller order) and C^T by column
@@ -373,7 +380,7 @@ int ensure_ws(kkt_ctx *ctx, int64_t nrhs) {
     if ((rc = get(&ctx->d_res, ctx->ntot * nrhs))) return rc;
     if ((rc = get(&ctx->d_dx, ctx->ntot * nrhs))) return rc;
     if ((rc = get(&ctx->d_norms, 4 * nrhs + 8))) return rc;
-    if ((rc = get(&ctx->d_work, ctx->N * S.Ns * nrhs + 2 * 512 * nrhs + 8))) return rc;
+    if ((rc = get(&ctx->d_work, residual_work(ctx->N, S.nA, S.Ns, nrhs)))) return rc;
     ctx->ws_nrhs = nrhs;
     return KKT_OK;
 }
@@ -709,9 +716,12 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
         // improve the solution further
         if (omega <= 4.0 * 2.220446049250313e-16) { status = KKT_WARN_REFINE; break; }
         if (it >= ctx->opt.refine_max) { status = KKT_WARN_REFINE; break; }
+        // stagnation: near the rounding floor one step without a 2x gain ends
+        // refinement; above it, two consecutive such steps
         size_t h = hist.size();
-        if (h >= 4 && hist[h - 1] > 0.5 * hist[h - 3] && hist[h - 2] > 0.5 * hist[h - 4]) {
-            status = KKT_WARN_REFINE;  // stagnation
+        if (h >= 2 && hist[h - 1] < 1e-6 && hist[h - 1] > 0.5 * hist[h - 2]) { status = KKT_WARN_REFINE; break; }
+        if (h >= 3 && hist[h - 1] > 0.5 * hist[h - 2] && hist[h - 2] > 0.5 * hist[h - 3]) {
+            status = KKT_WARN_REFINE;
             break;
         }
         rc = mixed ? solve_once<float>(ctx, ctx->d_res, ctx->d_dx, nrhs)

@@ -56,7 +56,8 @@ inline DevPlan make_plan(const Symbolic &Sy, int64_t N, int precision, int64_t n
     int64_t ntot = N * Sy.nA + ng;
     p.res = align_up(8 * ntot * nrhs);
     p.dx = align_up(8 * ntot * nrhs);
-    p.norms = align_up(8 * 4 * nrhs + 64);
+    p.norms = align_up(8 * 4 * nrhs + 64) +
+              align_up(8 * (N * Sy.Ns * nrhs + 2 * 512 * nrhs + ((Sy.nA + 255) / 256) * N * nrhs + 8));
     return p;
 }
 

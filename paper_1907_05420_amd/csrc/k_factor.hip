@@ -8,6 +8,8 @@
 // right-looking in 64-column steps (pivot block in LDS, row-parallel
 // triangular solve, trailing update on MFMA), grouped over all large fronts of
 // one tree level.
+#include <type_traits>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -21,26 +23,43 @@ constexpr int LDT = 65;     // LDS leading dimension of a 64x64 tile
 // static pivoting rule (oracle's reading): |d| <= tau -> sign(d) * tau,
 // inertia from the computed pivot before perturbation.
 // --------------------------------------------------------------------------
-__device__ inline double pivot_rule(double raw, double tau_k, double amax, double eps, int sgn, int64_t *cnt) {
-    double t = tau_k > 0.0 ? tau_k : eps * amax;
-    if (raw > 0.0) atomicAdd((unsigned long long *)(cnt + 0), 1ull);
-    else if (raw < 0.0) atomicAdd((unsigned long long *)(cnt + 1), 1ull);
-    else atomicAdd((unsigned long long *)(cnt + 2), 1ull);
+__device__ inline double pivot_rule(double raw, double t, int sgn, int &cls, int &pert) {
+    cls = raw > 0.0 ? 0 : (raw < 0.0 ? 1 : 2);
+    pert = 0;
     if (!(fabs(raw) > t)) {  // also catches NaN
         double s = raw > 0.0 ? 1.0 : (raw < 0.0 ? -1.0 : (double)sgn);
         double mag = t > 0.0 ? t : 1e-300;
-        atomicAdd((unsigned long long *)(cnt + 3), 1ull);
+        pert = 1;
         return s * mag;
     }
     return raw;
 }
 
+// per-thread tallies of pivot signs, flushed with one atomic per counter
+struct PivTally {
+    int c[4] = {0, 0, 0, 0};
+    __device__ void add(int cls, int pert) { c[cls]++; c[3] += pert; }
+};
+
 template <typename T>
-__device__ inline T do_pivot(const FactorArgs<T> &fa, int n, int gpiv, T raw) {
-    int sgn = fa.sign ? (int)fa.sign[gpiv] : -1;
-    double v = pivot_rule((double)raw, fa.tau[(int64_t)n * fa.tstride + gpiv], fa.amax[n], fa.eps, sgn,
-                          fa.cnt + 4 * n);
+__device__ inline T do_pivot(const FactorArgs<T> &fa, int n, int gpiv, T raw, double tau_k, PivTally &tl) {
+    const int sgn = fa.sign ? (int)fa.sign[gpiv] : -1;
+    const double t = tau_k > 0.0 ? tau_k : fa.eps * fa.amax[n];
+    int cls, pert;
+    const double v = pivot_rule((double)raw, t, sgn, cls, pert);
+    tl.add(cls, pert);
     return (T)v;
+}
+
+// block-wide sum of the tallies, one atomic per counter
+__device__ inline void flush_tally(PivTally &tl, int64_t *cnt) {
+    __shared__ int tot[4];
+    if (threadIdx.x < 4) tot[threadIdx.x] = 0;
+    __syncthreads();
+    for (int k = 0; k < 4; ++k)
+        if (tl.c[k]) atomicAdd(&tot[k], tl.c[k]);
+    __syncthreads();
+    if (threadIdx.x < 4 && tot[threadIdx.x]) atomicAdd((unsigned long long *)(cnt + threadIdx.x), (unsigned long long)tot[threadIdx.x]);
 }
 
 // --------------------------------------------------------------------------
@@ -129,9 +148,13 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
         }
         __syncthreads();
     }
+    PivTally tl;
+    __shared__ double taus[SMALL_M];
+    if (tid < c) taus[tid] = fa.tau[(int64_t)n * fa.tstride + d.piv0 + tid];
+    __syncthreads();
     for (int j = 0; j < c; ++j) {
         if (tid == 0) {
-            T v = do_pivot(fa, n, d.piv0 + j, F[j + j * LDT]);
+            T v = do_pivot(fa, n, d.piv0 + j, F[j + j * LDT], taus[j], tl);
             F[j + j * LDT] = v;
             piv = v;
         }
@@ -147,6 +170,21 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
                 F[i + q * LDT] -= F[i + j * LDT] * dj * F[q + j * LDT];
             }
         }
+        __syncthreads();
+    }
+    flush_tally(tl, fa.cnt + 4 * n);
+    // inverse of the unit lower pivot block in place, column by column from
+    // the right: X[i][q] = -(L[i][q] + sum_{q<t<i} X[i][t] L[t][q])
+    for (int q = c - 2; q >= 0; --q) {
+        T x = T(0);
+        const int i = tid;
+        if (i > q && i < c) {
+            x = F[i + q * LDT];
+            for (int t = q + 1; t < i; ++t) x += F[i + t * LDT] * F[t + q * LDT];
+            x = -x;
+        }
+        __syncthreads();
+        if (i > q && i < c) F[i + q * LDT] = x;
         __syncthreads();
     }
     for (int idx = tid; idx < m * c; idx += 64) {
@@ -207,45 +245,72 @@ __global__ __launch_bounds__(256) void k_extend_add(FactorArgs<T> fa, const Fron
     }
 }
 
-// LDL^T of the 64x64 (or smaller) pivot block at column k0 of every listed front.
+// Pivot block at column t0 of every listed front (one wavefront per front and
+// period, row i of the block in lane i's registers): LDL^T with the static
+// pivot rule, then the inverse of the unit lower triangle, row by row. The
+// block keeps D on its diagonal and L^-1 below it; the solves and the
+// row-block kernel use the inverse instead of a serial substitution.
+// Four waves: lane i holds row i, wave w holds columns [16w, 16w+16) of both
+// the block F and X = L^-1, built alongside the elimination (the row
+// operations of step j applied to the identity).
 template <typename T>
-__global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int k0) {
-    __shared__ T F[NB * LDT];
+__global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int t0) {
+    __shared__ T col[NB];
     __shared__ T piv;
     const FrontDesc d = sd[fl[blockIdx.x]];
-    const int n = blockIdx.y, tid = threadIdx.x;
-    const int nb = min(NB, d.c - k0);
-    const int m = d.m;
+    const int n = blockIdx.y, i = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nb = min(NB, d.c - t0), m = d.m;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
-    for (int idx = tid; idx < nb * nb; idx += 256) {
-        int r = idx % nb, q = idx / nb;
-        if (r >= q) F[r + q * LDT] = P[(k0 + r) + (int64_t)(k0 + q) * m];
+    T R[16], X[16];
+    PivTally tl;
+    const double my_tau = (i < nb) ? fa.tau[(int64_t)n * fa.tstride + d.piv0 + t0 + i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int q = 16 * w + k;
+        R[k] = (i < nb && q <= i) ? P[(t0 + i) + (int64_t)(t0 + q) * m] : T(0);
+        X[k] = (q == i) ? T(1) : T(0);
     }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-            T v = do_pivot(fa, n, d.piv0 + k0 + j, F[j + j * LDT]);
-            F[j + j * LDT] = v;
-            piv = v;
-        }
-        __syncthreads();
-        const T dj = piv;
-        for (int i = j + 1 + tid; i < nb; i += 256) F[i + j * LDT] /= dj;
-        __syncthreads();
-        const int nt = nb - j - 1;
-        for (int idx = tid; idx < nt * nt; idx += 256) {
-            int ii = idx % nt, qq = idx / nt;
-            if (ii >= qq) {
-                int i = j + 1 + ii, q = j + 1 + qq;
-                F[i + q * LDT] -= F[i + j * LDT] * dj * F[q + j * LDT];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j >= nb) break;
+        const int wj = j >> 4, kj = j & 15;
+        const double tj = __shfl(my_tau, j, 64);
+        if (w == wj) {
+            if (i == j) {
+                T v = do_pivot(fa, n, d.piv0 + t0 + j, R[kj], tj, tl);
+                R[kj] = v;
+                piv = v;
             }
         }
         __syncthreads();
+        const T dj = piv;
+        if (w == wj) {
+            const T l = (i > j && i < nb) ? R[kj] / dj : T(0);
+            if (i > j) R[kj] = l;
+            col[i] = l;
+        }
+        __syncthreads();
+        const T li = col[i];
+        const T ld = li * dj;
+        // row j of X for this wave's columns (lane j of the same wave)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int q = 16 * w + k;
+            const T xj = __shfl(X[k], j, 64);
+            if (q > j) R[k] -= ld * col[q];
+            if (q <= j && i > j) X[k] -= li * xj;
+        }
+        __syncthreads();
     }
-    for (int idx = tid; idx < nb * nb; idx += 256) {
-        int r = idx % nb, q = idx / nb;
-        if (r >= q) P[(k0 + r) + (int64_t)(k0 + q) * m] = F[r + q * LDT];
+    if (i < nb) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int q = 16 * w + k;
+            if (q < i) P[(t0 + i) + (int64_t)(t0 + q) * m] = X[k];
+            else if (q == i) P[(t0 + i) + (int64_t)(t0 + q) * m] = R[k];
+        }
     }
+    flush_tally(tl, fa.cnt + 4 * n);
 }
 
 // Locate the front of a flattened task index through per-step prefix sums.
@@ -255,111 +320,374 @@ __device__ inline int find_front(const int32_t *pre, int nf, int b) {
     return lo;
 }
 
-// Rows below the pivot block: X = F21 L11^-T, then L21 = X D^-1 (one row per thread).
+// 64x64 MFMA tile product acc(r, q) = sum_k sA[k][r] sB[k][q] (k-major LDS
+// tiles of ld LDS_LD); each of the four waves owns a 32x32 quadrant.
+constexpr int LDS_LD = 68;
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
-                                              const int32_t *pre, int nf, int k0) {
-    __shared__ T Ls[NB * LDT];
-    __shared__ T Ds[NB];
-    const int fi = find_front(pre, nf, blockIdx.x);
-    const FrontDesc d = sd[fl[fi]];
-    const int n = blockIdx.y, tid = threadIdx.x;
-    const int nb = min(NB, d.c - k0), m = d.m;
-    const int r = k0 + nb + (blockIdx.x - pre[fi]) * 256 + tid;
-    T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        int i = idx % NB, q = idx / NB;
-        T v = T(0);
-        if (i < nb && q < nb && i > q) v = P[(k0 + i) + (int64_t)(k0 + q) * m];
-        Ls[i + q * LDT] = v;
-    }
-    if (tid < NB) Ds[tid] = tid < nb ? P[(k0 + tid) + (int64_t)(k0 + tid) * m] : T(1);
-    __syncthreads();
-    if (r >= m) return;
-    T x[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) x[j] = j < nb ? P[r + (int64_t)(k0 + j) * m] : T(0);
-#pragma unroll
-    for (int j = 1; j < NB; ++j) {
-        T acc = x[j];
-#pragma unroll
-        for (int q = 0; q < j; ++q) acc -= x[q] * Ls[j + q * LDT];
-        x[j] = acc;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-        if (j < nb) P[r + (int64_t)(k0 + j) * m] = x[j] / Ds[j];
-}
-
-// Trailing update of every listed front after the pivot block at k0:
-// F(r, q) -= sum_k L(r, k) d_k L(q, k) for r >= q >= k0 + nb, one 64x64 tile
-// per workgroup, FP64/FP32 MFMA 16x16x4, four waves of 32x32.
-template <typename T>
-__global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
-                                                const int32_t *pre, int nf, int k0) {
-    typedef typename Acc<T>::type acc_t;
-    constexpr int LDS = 68;
-    __shared__ T sA[NB * LDS];
-    __shared__ T sB[NB * LDS];
-    const int fi = find_front(pre, nf, blockIdx.x);
-    const FrontDesc d = sd[fl[fi]];
-    const int n = blockIdx.y, tid = threadIdx.x;
-    const int nb = min(NB, d.c - k0), m = d.m, c = d.c;
-    const int r0 = k0 + nb;
-    // triangular decode of the tile index
-    const int t = blockIdx.x - pre[fi];
-    int ti = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-    while (ti * (ti + 1) / 2 > t) --ti;
-    const int tj = t - ti * (ti + 1) / 2;
-    const int R0 = r0 + 64 * ti, Q0 = r0 + 64 * tj;
-    T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
-    T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
-    {
-        const int row = tid & 63, kk = tid >> 6;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k = kk + 4 * j;
-            T a = T(0), b = T(0);
-            if (k < nb) {
-                const T dk = P[(k0 + k) + (int64_t)(k0 + k) * m];
-                if (R0 + row < m) a = P[(R0 + row) + (int64_t)(k0 + k) * m] * dk;
-                if (Q0 + row < m) b = P[(Q0 + row) + (int64_t)(k0 + k) * m];
-            }
-            sA[k * LDS + row] = a;
-            sB[k * LDS + row] = b;
-        }
-    }
-    __syncthreads();
-    const int lane = tid & 63, w = tid >> 6;
+__device__ inline void tile_mma(const T *sA, const T *sB, typename Acc<T>::type (&acc)[2][2], int lane, int w) {
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    acc_t acc[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll 4
     for (int k = 0; k < NB; k += 4) {
-        T a0 = sA[(k + lk) * LDS + wr + li];
-        T a1 = sA[(k + lk) * LDS + wr + 16 + li];
-        T b0 = sB[(k + lk) * LDS + wc + li];
-        T b1 = sB[(k + lk) * LDS + wc + 16 + li];
+        const T a0 = sA[(k + lk) * LDS_LD + wr + li];
+        const T a1 = sA[(k + lk) * LDS_LD + wr + 16 + li];
+        const T b0 = sB[(k + lk) * LDS_LD + wc + li];
+        const T b1 = sB[(k + lk) * LDS_LD + wc + 16 + li];
         acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
         acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
         acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
         acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
     }
+}
+
+// accumulators of the 4 waves -> LDS tile sC[row + col*65]
+template <typename T>
+__device__ inline void tile_stage(T *sC, typename Acc<T>::type (&acc)[2][2], int lane, int w) {
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int r = R0 + wr + bi * 16 + mfma_row(T(0), lk, rr);
-                const int q = Q0 + wc + bj * 16 + li;
-                if (r < m && q <= r) *front_addr(P, Ub, m, c, r, q) -= acc[bi][bj][rr];
+            for (int rr = 0; rr < 4; ++rr)
+                sC[(wr + bi * 16 + mfma_row(T(0), lk, rr)) + (wc + bj * 16 + li) * LDT] = acc[bi][bj][rr];
+}
+
+// Rows below the pivot block: L21 = F21 (L11^-1)^T D^-1 as one MFMA product
+// per 64-row tile (L11^-1 is stored in the pivot block).
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
+                                              const int32_t *pre, int nf, int t0) {
+    typedef typename Acc<T>::type acc_t;
+    __shared__ T sA[NB * LDS_LD];
+    __shared__ T sB[NB * LDS_LD];
+    __shared__ T Ds[NB];
+    const int fi = find_front(pre, nf, blockIdx.x);
+    const FrontDesc d = sd[fl[fi]];
+    const int n = blockIdx.y, tid = threadIdx.x;
+    const int nb = min(NB, d.c - t0), m = d.m;
+    const int R0 = t0 + nb + (blockIdx.x - pre[fi]) * 64;
+    T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
+    {
+        const int row = tid & 63, kk = tid >> 6;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = kk + 4 * j;
+            sA[k * LDS_LD + row] = (k < nb && R0 + row < m) ? P[(R0 + row) + (int64_t)(t0 + k) * m] : T(0);
+            // B[q = row][k] = (L11^-1)[row][k]
+            T b = T(0);
+            if (row < nb && k < nb) b = k < row ? P[(t0 + row) + (int64_t)(t0 + k) * m] : (k == row ? T(1) : T(0));
+            sB[k * LDS_LD + row] = b;
+        }
+        if (tid < NB) Ds[tid] = tid < nb ? P[(t0 + tid) + (int64_t)(t0 + tid) * m] : T(1);
+    }
+    __syncthreads();
+    const int lane = tid & 63, w = tid >> 6;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+    tile_mma<T>(sA, sB, acc, lane, w);
+    __syncthreads();
+    T *sC = sA;
+    tile_stage<T>(sC, acc, lane, w);
+    __syncthreads();
+    const int row = tid & 63;
+    const int r = R0 + row;
+    if (r < m)
+        for (int q = tid >> 6; q < nb; q += 4) P[r + (int64_t)(t0 + q) * m] = sC[row + q * LDT] / Ds[q];
+}
+
+// Geometry of an update after the pivot columns [t0, t0+K): target rows and
+// columns start at lo; columns end at qhi. kind 2: inside the outer panel
+// ending at pe; kind 3: the trailing matrix after that panel.
+struct UpdGeom {
+    int lo, qhi, K;
+};
+__host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int m) {
+    const int cend = pe < c ? pe : c;
+    UpdGeom g;
+    if (kind == 2) {
+        g.K = (c - t0) < NB ? (c - t0) : NB;
+        g.lo = t0 + g.K;
+        g.qhi = cend;
+    } else {
+        g.K = cend - t0;
+        g.lo = cend;
+        g.qhi = m;
+    }
+    return g;
+}
+
+// F(r, q) -= sum_k L(r, k) d_k L(q, k) for r >= q in the region of upd_geom:
+// one 64x64 tile per workgroup, K in chunks of 64, FP64/FP32 MFMA 16x16x4,
+// coalesced read-modify-write of the target through an LDS stage.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
+                                                const int32_t *pre, int nf, int kind, int t0, int pe) {
+    typedef typename Acc<T>::type acc_t;
+    __shared__ T sA[NB * LDS_LD];
+    __shared__ T sB[NB * LDS_LD];
+    const int fi = find_front(pre, nf, blockIdx.x);
+    const FrontDesc d = sd[fl[fi]];
+    const int n = blockIdx.y, tid = threadIdx.x;
+    const int m = d.m, c = d.c;
+    const UpdGeom g = upd_geom(kind, t0, pe, c, m);
+    // trapezoid decode: column tiles tj < Tc, row tiles ti in [tj, Tr)
+    const int Tr = (m - g.lo + 63) / 64;
+    int t = blockIdx.x - pre[fi];
+    int tj = (int)floor(((2.0 * Tr + 1.0) - sqrt((2.0 * Tr + 1.0) * (2.0 * Tr + 1.0) - 8.0 * t)) * 0.5);
+    if (tj < 0) tj = 0;
+    while (tj > 0 && tj * Tr - tj * (tj - 1) / 2 > t) --tj;
+    while ((tj + 1) * Tr - (tj + 1) * tj / 2 <= t) ++tj;
+    const int ti = tj + (t - (tj * Tr - tj * (tj - 1) / 2));
+    const int R0 = g.lo + 64 * ti, Q0 = g.lo + 64 * tj;
+    T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
+    T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
+    const int lane = tid & 63, w = tid >> 6;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+    const int row = tid & 63, kk = tid >> 6;
+    const bool arow = R0 + row < m, brow = Q0 + row < m;
+    const T *Pa = P + min(R0 + row, m - 1), *Pb = P + min(Q0 + row, m - 1);
+    for (int kc = 0; kc < g.K; kc += NB) {
+        const int kn = min(NB, g.K - kc);
+        T ra[16], rb[16], rd[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = min(kk + 4 * j, kn - 1);
+            const int col = t0 + kc + k;
+            ra[j] = Pa[(int64_t)col * m];
+            rb[j] = Pb[(int64_t)col * m];
+            rd[j] = P[col + (int64_t)col * m];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = kk + 4 * j;
+            const bool ok = k < kn;
+            sA[k * LDS_LD + row] = (ok && arow) ? ra[j] * rd[j] : T(0);
+            sB[k * LDS_LD + row] = (ok && brow) ? rb[j] : T(0);
+        }
+        __syncthreads();
+        tile_mma<T>(sA, sB, acc, lane, w);
+        __syncthreads();
+    }
+    T *sC = sA;
+    tile_stage<T>(sC, acc, lane, w);
+    __syncthreads();
+    const int r = R0 + row;
+    if (r < m)
+        for (int j = kk; j < 64; j += 4) {
+            const int q = Q0 + j;
+            if (q <= r && q < g.qhi) *front_addr(P, Ub, m, c, r, q) -= sC[row + j * LDT];
+        }
+}
+
+// Trailing update after an outer panel (kind 3) on 128x128 tiles: four waves
+// of 64x64 (4x4 MFMA 16x16x4 blocks each), K in chunks of 16 staged through
+// double-buffered LDS (one barrier per chunk), epilogue through LDS in two
+// 64-column halves for a coalesced read-modify-write of the target.
+constexpr int BT = 128;      // tile edge
+constexpr int KC = 16;       // K chunk
+constexpr int LD2 = BT + 16; // LDS leading dimension (bank spread)
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
+                                                       const int32_t *pre, int nf, int t0, int pe) {
+    typedef typename Acc<T>::type acc_t;
+    __shared__ T smem[2 * 2 * KC * LD2];
+    const int fi = find_front(pre, nf, blockIdx.x);
+    const FrontDesc d = sd[fl[fi]];
+    const int n = blockIdx.y, tid = threadIdx.x;
+    const int m = d.m, c = d.c;
+    const UpdGeom g = upd_geom(3, t0, pe, c, m);
+    const int Tr = (m - g.lo + BT - 1) / BT;
+    const int t = blockIdx.x - pre[fi];
+    int tj = (int)floor(((2.0 * Tr + 1.0) - sqrt((2.0 * Tr + 1.0) * (2.0 * Tr + 1.0) - 8.0 * t)) * 0.5);
+    if (tj < 0) tj = 0;
+    while (tj > 0 && tj * Tr - tj * (tj - 1) / 2 > t) --tj;
+    while ((tj + 1) * Tr - (tj + 1) * tj / 2 <= t) ++tj;
+    const int ti = tj + (t - (tj * Tr - tj * (tj - 1) / 2));
+    const int R0 = g.lo + BT * ti, Q0 = g.lo + BT * tj;
+    T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
+    T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    const int li = lane & 15, lk = lane >> 4;
+    acc_t acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+    // pivots D of the K range, staged once (K <= OUTER_W)
+    __shared__ T sD[OUTER_W];
+    for (int k = tid; k < g.K; k += 256) sD[k] = P[(t0 + k) + (int64_t)(t0 + k) * m];
+    // loader: row = tid % 128, k = tid / 128 + 2 j (j < 8); clamped addresses,
+    // no arithmetic on the loaded values until they are stored to LDS, so the
+    // loads of the next chunk stay in flight during the MFMA loop
+    const int lrow = tid & (BT - 1), lkk = tid >> 7;
+    const bool arow = R0 + lrow < m, brow = Q0 + lrow < m;
+    const T *Pa = P + min(R0 + lrow, m - 1), *Pb = P + min(Q0 + lrow, m - 1);
+    T ra[KC / 2], rb[KC / 2];
+    auto gload = [&](int kc) {
+#pragma unroll
+        for (int j = 0; j < KC / 2; ++j) {
+            const int k = min(kc + lkk + 2 * j, g.K - 1);
+            const int64_t col = (int64_t)(t0 + k) * m;
+            ra[j] = Pa[col];
+            rb[j] = Pb[col];
+        }
+    };
+    auto sstore = [&](int buf, int kc) {
+        T *sA = smem + buf * 2 * KC * LD2, *sB = sA + KC * LD2;
+#pragma unroll
+        for (int j = 0; j < KC / 2; ++j) {
+            const int k = kc + lkk + 2 * j;
+            const bool ok = k < g.K;
+            sA[(lkk + 2 * j) * LD2 + lrow] = (ok && arow) ? ra[j] * sD[ok ? k : 0] : T(0);
+            sB[(lkk + 2 * j) * LD2 + lrow] = (ok && brow) ? rb[j] : T(0);
+        }
+    };
+    const int nch = (g.K + KC - 1) / KC;
+    gload(0);
+    __syncthreads();  // sD
+    sstore(0, 0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) gload((ch + 1) * KC);
+        const T *sA = smem + (ch & 1) * 2 * KC * LD2, *sB = sA + KC * LD2;
+#pragma unroll
+        for (int k = 0; k < KC; k += 4) {
+            T a[4], b[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                a[x] = sA[(k + lk) * LD2 + wr + 16 * x + li];
+                b[x] = sB[(k + lk) * LD2 + wc + 16 * x + li];
             }
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16x16x4(a[bi], b[bj], acc[bi][bj]);
+        }
+        if (ch + 1 < nch) sstore((ch + 1) & 1, (ch + 1) * KC);
+        __syncthreads();
+    }
+    // epilogue: two 64-column halves through LDS (128 x 64 stage, ld 129)
+    T *sC = smem;
+    for (int half = 0; half < 2; ++half) {
+        if ((w & 1) == half) {
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        sC[(wr + 16 * bi + mfma_row(T(0), lk, rr)) + (16 * bj + li) * (BT + 1)] = acc[bi][bj][rr];
+        }
+        __syncthreads();
+        const int r = R0 + lrow;
+        if (r < m)
+            for (int j = lkk; j < 64; j += 2) {
+                const int q = Q0 + 64 * half + j;
+                if (q <= r && q < g.qhi) *front_addr(P, Ub, m, c, r, q) -= sC[lrow + j * (BT + 1)];
+            }
+        __syncthreads();
+    }
+}
+
+// In-place inverse of the unit lower 256x256 diagonal block of a dense
+// factor (FP64, after its outer panel is complete), from the inverses of its
+// 64x64 diagonal sub-blocks: for every sub-block column j and row i > j,
+//   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj     (X_jj unit lower, stored below
+// its diagonal), processed column by column so that every L_ik still needed
+// is intact. Products on MFMA through the 64x64 tile helpers.
+__global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl,
+                                                int j0) {
+    typedef Acc<double>::type acc_t;
+    __shared__ double sA[NB * LDS_LD];
+    __shared__ double sB[NB * LDS_LD];
+    const FrontDesc d = sd[fl[blockIdx.x]];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m = d.m;
+    const int nbw = min(OUTER_W, d.c - j0);
+    const int nsb = (nbw + 63) / 64;
+    double *P = fa.L + d.Loff;
+    const int row = tid & 63, kk = tid >> 6;
+    // load a 64x64 sub-block (rows r0.., cols c0..) as sX[k][r] = M[r][k]
+    // (transposed, "A" operand) or sX[k][q] = M[k][q] ("B" operand); unit
+    // lower when diag.
+    auto load = [&](double *sX, int r0, int c0, bool asA, bool diag) {
+        for (int j = 0; j < 16; ++j) {
+            const int k = kk + 4 * j;
+            // element M[a][b] with a = row index, b = column index
+            const int a = asA ? row : k, b = asA ? k : row;
+            double v = 0.0;
+            const int ra = r0 + a, cb = c0 + b;
+            if (ra < j0 + nbw && cb < j0 + nbw) {
+                if (!diag) v = P[(int64_t)(ra) + (int64_t)cb * m];
+                else v = a > b ? P[(int64_t)ra + (int64_t)cb * m] : (a == b ? 1.0 : 0.0);
+            }
+            sX[k * LDS_LD + row] = v;
+        }
+    };
+    acc_t acc[2][2];
+    for (int j = 0; j + 1 < nsb; ++j) {
+        for (int i = j + 1; i < nsb; ++i) {
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+            for (int k = j; k < i; ++k) {
+                __syncthreads();
+                load(sA, j0 + 64 * i, j0 + 64 * k, true, false);        // L_ik
+                load(sB, j0 + 64 * k, j0 + 64 * j, false, k == j);      // X_kj
+                __syncthreads();
+                tile_mma<double>(sA, sB, acc, lane, w);
+            }
+            // T -> sB as a "B" operand (sB[k][q] = T[k][q]), X_ii -> sA
+            __syncthreads();
+            double *sC = sB;
+            {
+                const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+                const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr)
+                            sC[(wr + bi * 16 + mfma_row(0.0, lk, rr)) * LDS_LD + (wc + bj * 16 + li)] = acc[bi][bj][rr];
+            }
+            load(sA, j0 + 64 * i, j0 + 64 * i, true, true);             // X_ii
+            __syncthreads();
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+            tile_mma<double>(sA, sB, acc, lane, w);
+            __syncthreads();
+            tile_stage<double>(sA, acc, lane, w);
+            __syncthreads();
+            const int r = j0 + 64 * i + row;
+            if (r < j0 + nbw)
+                for (int q = kk; q < 64; q += 4) {
+                    const int cq = j0 + 64 * j + q;
+                    P[(int64_t)r + (int64_t)cq * m] = -sA[row + q * LDT];
+                }
+        }
+    }
+}
+
+int step_tasks_big(int t0, int pe, int c, int m) {
+    const UpdGeom g = upd_geom(3, t0, pe, c, m);
+    if (g.K <= 0 || g.qhi <= g.lo) return 0;
+    const int Tr = (m - g.lo + BT - 1) / BT;
+    return Tr * (Tr + 1) / 2;
 }
 
 // --------------------------------------------------------------------------
@@ -408,14 +736,43 @@ void launch_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const RowTask *tas
 
 template <typename T>
 void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_t N, hipStream_t st) {
-    if (s.nf <= 0) return;
-    hipLaunchKernelGGL(k_diag<T>, dim3(s.nf, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.k0);
-    if (s.ntrsm > 0)
-        hipLaunchKernelGGL(k_trsm<T>, dim3(s.ntrsm, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre_trsm,
-                           s.nf, s.k0);
-    if (s.ntile > 0)
-        hipLaunchKernelGGL(k_update<T>, dim3(s.ntile, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre_tile,
-                           s.nf, s.k0);
+    if (s.nf <= 0 || (s.kind != 0 && s.ntasks <= 0)) return;
+    switch (s.kind) {
+        case 0:
+            hipLaunchKernelGGL(k_diag<T>, dim3(s.nf, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.t0);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_trsm<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre, s.nf,
+                               s.t0);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_update_big<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
+                               s.nf, s.t0, s.pe);
+            break;
+        case 5:
+            if constexpr (std::is_same<T, double>::value)
+                hipLaunchKernelGGL(k_inv256, dim3(s.nf, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.t0);
+            break;
+        default:
+            hipLaunchKernelGGL(k_update<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
+                               s.nf, s.kind, s.t0, s.pe);
+    }
+}
+
+// host mirror of the per-front task counts of a step
+int step_tasks(int kind, int t0, int pe, int c, int m) {
+    if (kind == 4) return step_tasks_big(t0, pe, c, m);
+    if (kind == 5) return c > t0 ? 1 : 0;
+    if (kind == 0) return c > t0 ? 1 : 0;
+    if (kind == 1) {
+        const int nb = std::min(NB, c - t0);
+        const int rows = m - t0 - nb;
+        return rows > 0 ? (rows + 63) / 64 : 0;
+    }
+    const UpdGeom g = upd_geom(kind, t0, pe, c, m);
+    if (g.K <= 0 || g.qhi <= g.lo) return 0;
+    const int Tr = (m - g.lo + 63) / 64, Tc = (g.qhi - g.lo + 63) / 64;
+    return Tc * Tr - Tc * (Tc - 1) / 2;
 }
 
 #define KKT_INST(T)                                                                                        \

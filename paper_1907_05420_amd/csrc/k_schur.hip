@@ -36,33 +36,25 @@ __global__ __launch_bounds__(256) void k_schur_assemble(const T *U, int64_t Ustr
                                                         int64_t Ns, const double *prefix, const double *corner,
                                                         double *S, double *tau_s, double eps, double *amax_s,
                                                         int mirror) {
-    __shared__ double red[256];
     const int64_t ng = N * Ns, nb = 2 * Ns;
     const int64_t R = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t Q = blockIdx.y;
-    double a = 0.0;
-    if (R < ng && (R >= Q || mirror)) {
-        const int64_t r = R >= Q ? R : Q, q = R >= Q ? Q : R;
-        const int64_t m = r / Ns, i = r % Ns, mp = q / Ns, j = q % Ns;
-        double v;
-        if (m == mp) {
-            v = sbar_at(U + m * Ustride + uoff, nb, i, j) + prefix[m * Ns * Ns + i + j * Ns];
-            if (i == j && corner) v += corner[r];
-        } else {
-            v = sbar_at(U + mp * Ustride + uoff, nb, Ns + i, j) + prefix[mp * Ns * Ns + i + j * Ns];
-        }
-        S[R + Q * ng] = v;
-        if (R >= Q) a = fabs(v);
-        if (R == Q && tau_s) tau_s[R] = eps * fabs(v);
+    if (R >= ng || (R < Q && !mirror)) return;
+    const int64_t r = R >= Q ? R : Q, q = R >= Q ? Q : R;
+    const int64_t m = r / Ns, i = r % Ns, mp = q / Ns, j = q % Ns;
+    double v;
+    if (m == mp) {
+        v = sbar_at(U + m * Ustride + uoff, nb, i, j) + prefix[m * Ns * Ns + i + j * Ns];
+        if (i == j && corner) v += corner[r];
+    } else {
+        v = sbar_at(U + mp * Ustride + uoff, nb, Ns + i, j) + prefix[mp * Ns * Ns + i + j * Ns];
     }
-    if (!amax_s) return;
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
+    S[R + Q * ng] = v;
+    if (R == Q) {
+        // the diagonal sets the thresholds; for a definite S max|s_ij| = max|s_ii|
+        if (tau_s) tau_s[R] = eps * fabs(v);
+        if (amax_s) atomic_max_nonneg(amax_s, fabs(v));
     }
-    if (threadIdx.x == 0) atomic_max_nonneg(amax_s, red[0]);
 }
 
 template <typename T>

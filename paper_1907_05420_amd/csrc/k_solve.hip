@@ -23,56 +23,89 @@ __global__ void k_gather_rhs(const double *b, int64_t ntot, int64_t nA, const in
     sa.xp[((int64_t)n * sa.nrhs + k) * sa.nv + q] = v;
 }
 
+// Up to RB right-hand sides go through a front together (the factor is read
+// once per pass); v[i * RB + r] holds row i of right-hand side r.
+constexpr int RB = 4;
+
+constexpr int SNT = 512;  // threads of a front solve
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_fwd(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks,
-                                             TreeArgs tr, SolveArgs sa) {
-    extern __shared__ double v[];
+__global__ __launch_bounds__(SNT) void k_fwd(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks,
+                                             TreeArgs tr, SolveArgs sa, int rb) {
+    extern __shared__ double smem[];
+    double *Lt = smem;             // 64 x 65 staging tile
+    double *v = smem + 64 * 65;
     const int s = tasks[blockIdx.x];
     const int n = blockIdx.y, tid = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
     const int32_t *R = tr.rows + tr.rowptr[s];
-    for (int k = 0; k < sa.nrhs; ++k) {
-        double *x = sa.xp + ((int64_t)n * sa.nrhs + k) * sa.nv;
-        double *U = sa.uv + ((int64_t)n * sa.nrhs + k) * sa.usz;
-        for (int i = tid; i < m; i += 256) v[i] = i < c ? x[R[i]] : 0.0;
+    for (int k0r = 0; k0r < sa.nrhs; k0r += rb) {
+        const int nr = min(rb, (int)sa.nrhs - k0r);
+        double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
+        for (int idx = tid; idx < m * rb; idx += SNT) {
+            const int i = idx / rb, r = idx % rb;
+            v[idx] = (r < nr && i < c) ? x0[(int64_t)r * sa.nv + R[i]] : 0.0;
+        }
         __syncthreads();
         for (int q = tr.cptr[s]; q < tr.cptr[s + 1]; ++q) {
             const int ch = tr.clist[q];
             const int uc = sd[ch].m - sd[ch].c;
             const int32_t *rl = tr.rel + tr.relptr[ch];
-            const double *uch = U + tr.relptr[ch];
-            for (int i = tid; i < uc; i += 256) v[rl[i]] += uch[i];
+            for (int idx = tid; idx < uc * nr; idx += SNT) {
+                const int i = idx / nr, r = idx % nr;
+                v[rl[i] * rb + r] += U0[(int64_t)r * sa.usz + tr.relptr[ch] + i];
+            }
             __syncthreads();
         }
         for (int k0 = 0; k0 < c; k0 += 64) {
             const int nb = min(64, c - k0);
-            for (int j = 0; j < nb; ++j) {
-                const double yj = v[k0 + j];
-                const int i = k0 + j + 1 + tid;
-                if (i < k0 + nb) v[i] -= (double)P[i + (int64_t)(k0 + j) * m] * yj;
-                __syncthreads();
+            const int i = tid & 63, r = tid >> 6;
+            for (int idx = tid; idx < 64 * 64; idx += SNT) {
+                const int a = idx & 63, q = idx >> 6;
+                Lt[a + q * 65] = (q < a && a < nb) ? (double)P[(k0 + a) + (int64_t)(k0 + q) * m] : 0.0;
             }
-            for (int i = k0 + nb + tid; i < m; i += 256) {
-                double acc = 0.0;
-                for (int j = 0; j < nb; ++j) acc += (double)P[i + (int64_t)(k0 + j) * m] * v[k0 + j];
-                v[i] -= acc;
+            __syncthreads();
+            double yv = 0.0;
+            if (i < nb && r < nr) {
+                yv = v[(k0 + i) * rb + r];
+                for (int q = 0; q < i; ++q) yv += Lt[i + q * 65] * v[(k0 + q) * rb + r];
+            }
+            __syncthreads();
+            if (i < nb && r < nr) v[(k0 + i) * rb + r] = yv;
+            __syncthreads();
+            for (int i2 = k0 + nb + tid; i2 < m; i2 += SNT) {
+                double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+                for (int q = 0; q < nb; ++q) {
+                    const double l = (double)P[i2 + (int64_t)(k0 + q) * m];
+#pragma unroll
+                    for (int rr = 0; rr < RB; ++rr)
+                        if (rr < nr) acc[rr] += l * v[(k0 + q) * rb + rr];
+                }
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr)
+                    if (rr < nr) v[i2 * rb + rr] -= acc[rr];
             }
             __syncthreads();
         }
-        for (int i = tid; i < m; i += 256) {
-            if (i < c) x[R[i]] = v[i];
-            else U[tr.relptr[s] + (i - c)] = v[i];
+        for (int idx = tid; idx < m * nr; idx += SNT) {
+            const int i = idx / nr, r = idx % nr;
+            if (i < c) x0[(int64_t)r * sa.nv + R[i]] = v[i * rb + r];
+            else U0[(int64_t)r * sa.usz + tr.relptr[s] + (i - c)] = v[i * rb + r];
         }
         __syncthreads();
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_bwd(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks,
-                                             TreeArgs tr, SolveArgs sa) {
-    extern __shared__ double v[];
+__global__ __launch_bounds__(SNT) void k_bwd(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks,
+                                             TreeArgs tr, SolveArgs sa, int rb) {
+    extern __shared__ double smem[];
+    double *Lt = smem;             // 64 x 65 staging tile
+    double *v = smem + 64 * 65;
     const int s = tasks[blockIdx.x];
     const int n = blockIdx.y, tid = threadIdx.x;
     const FrontDesc d = sd[s];
@@ -80,34 +113,71 @@ __global__ __launch_bounds__(256) void k_bwd(const T *L, int64_t Lstride, const 
     if (c == 0) return;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
     const int32_t *R = tr.rows + tr.rowptr[s];
-    for (int k = 0; k < sa.nrhs; ++k) {
-        double *x = sa.xp + ((int64_t)n * sa.nrhs + k) * sa.nv;
-        for (int i = tid; i < m; i += 256) v[i] = i < c ? x[R[i]] / (double)P[i + (int64_t)i * m] : x[R[i]];
+    for (int k0r = 0; k0r < sa.nrhs; k0r += rb) {
+        const int nr = min(rb, (int)sa.nrhs - k0r);
+        double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        for (int idx = tid; idx < m * rb; idx += SNT) {
+            const int i = idx / rb, r = idx % rb;
+            double val = 0.0;
+            if (r < nr) {
+                val = x0[(int64_t)r * sa.nv + R[i]];
+                if (i < c) val /= (double)P[i + (int64_t)i * m];
+            }
+            v[idx] = val;
+        }
         __syncthreads();
-        for (int q = tid; q < c; q += 256) {
-            double acc = 0.0;
+        // contributions of the update rows (ancestors' final values)
+        for (int q = tid; q < c; q += SNT) {
+            double acc[RB] = {0.0, 0.0, 0.0, 0.0};
             const T *col = P + (int64_t)q * m;
-            for (int i = c; i < m; ++i) acc += (double)col[i] * v[i];
-            v[q] -= acc;
+#pragma unroll 8
+            for (int i = c; i < m; ++i) {
+                const double l = (double)col[i];
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr)
+                    if (rr < nr) acc[rr] += l * v[i * rb + rr];
+            }
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr)
+                if (rr < nr) v[q * rb + rr] -= acc[rr];
         }
         __syncthreads();
         for (int kb = ((c - 1) / 64) * 64; kb >= 0; kb -= 64) {
             const int nb = min(64, c - kb);
-            for (int j = nb - 1; j >= 0; --j) {
-                const double xj = v[kb + j];
-                const int q = kb + tid;
-                if (q < kb + j) v[q] -= (double)P[(kb + j) + (int64_t)q * m] * xj;
-                __syncthreads();
+            const int q = tid & 63, r = tid >> 6;
+            for (int idx = tid; idx < 64 * 64; idx += SNT) {
+                const int a = idx & 63, qq = idx >> 6;
+                Lt[a + qq * 65] = (qq < a && a < nb) ? (double)P[(kb + a) + (int64_t)(kb + qq) * m] : 0.0;
             }
-            for (int q = tid; q < kb; q += 256) {
-                double acc = 0.0;
-                const T *col = P + (int64_t)q * m;
-                for (int j = 0; j < nb; ++j) acc += (double)col[kb + j] * v[kb + j];
-                v[q] -= acc;
+            __syncthreads();
+            double xv = 0.0;
+            if (q < nb && r < nr) {
+                xv = v[(kb + q) * rb + r];
+                for (int i = q + 1; i < nb; ++i) xv += Lt[i + q * 65] * v[(kb + i) * rb + r];
+            }
+            __syncthreads();
+            if (q < nb && r < nr) v[(kb + q) * rb + r] = xv;
+            __syncthreads();
+            for (int q2 = tid; q2 < kb; q2 += SNT) {
+                double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+                const T *col = P + (int64_t)q2 * m + kb;
+#pragma unroll 8
+                for (int i = 0; i < nb; ++i) {
+                    const double l = (double)col[i];
+#pragma unroll
+                    for (int rr = 0; rr < RB; ++rr)
+                        if (rr < nr) acc[rr] += l * v[(kb + i) * rb + rr];
+                }
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr)
+                    if (rr < nr) v[q2 * rb + rr] -= acc[rr];
             }
             __syncthreads();
         }
-        for (int i = tid; i < c; i += 256) x[R[i]] = v[i];
+        for (int idx = tid; idx < c * nr; idx += SNT) {
+            const int i = idx / nr, r = idx % nr;
+            x0[(int64_t)r * sa.nv + R[i]] = v[i * rb + r];
+        }
         __syncthreads();
     }
 }
@@ -152,43 +222,90 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
     }
 }
 
-// ---- dense Schur factor solves (unit lower L, D on the diagonal) ------------
-constexpr int DNB = 64;
+// ---- dense Schur factor solves ----------------------------------------------
+// The factor of S keeps D on its diagonal, L^-1 of every 64x64 diagonal block
+// below the diagonal of that block, and L elsewhere below the diagonal. Steps
+// go over 256-row blocks; every workgroup of a step redoes the small in-block
+// solve and then updates its own 256 rows (forward) or columns (backward).
+constexpr int DBW = 256;
 
-// forward step for rows [j0, j0+nb): every workgroup solves the block
-// redundantly, workgroup 0 stores it; each workgroup then updates 256 rows below.
-__global__ __launch_bounds__(256) void k_dense_fwd(const double *S, int64_t ng, double *v, double *y, int nrhs,
-                                                   int64_t j0) {
-    __shared__ double Lb[DNB * 65];
-    __shared__ double yb[DNB * 4];
+// The factor of S keeps L^-1 of every 256x256 diagonal block below that
+// block's diagonal. y[j0:j0+nbw) = X v[j0:j0+nbw) with X unit lower: 16 rows
+// per workgroup, 16 partial sums per row.
+__global__ __launch_bounds__(256) void k_dense_yblk(const double *S, int64_t ng, const double *v, double *y, int nrhs,
+                                                    int64_t j0) {
+    __shared__ double vb[DBW * RB];
+    __shared__ double red[16 * 16 * RB];
     const int tid = threadIdx.x;
-    const int nb = (int)min((int64_t)DNB, ng - j0);
-    for (int idx = tid; idx < nb * nb; idx += 256) {
-        int i = idx % nb, q = idx / nb;
-        Lb[i + q * 65] = S[(j0 + i) + (j0 + q) * ng];
-    }
-    for (int idx = tid; idx < nb * nrhs; idx += 256) {
-        int i = idx % nb, k = idx / nb;
-        yb[i + k * DNB] = v[(int64_t)k * ng + j0 + i];
-    }
-    __syncthreads();
-    if (tid < nrhs) {
-        double *yy = yb + tid * DNB;
-        for (int j = 0; j < nb; ++j)
-            for (int i = j + 1; i < nb; ++i) yy[i] -= Lb[i + j * 65] * yy[j];
-    }
-    __syncthreads();
-    if (blockIdx.x == 0)
-        for (int idx = tid; idx < nb * nrhs; idx += 256) {
-            int i = idx % nb, k = idx / nb;
-            y[(int64_t)k * ng + j0 + i] = yb[i + k * DNB];
+    const int nbw = (int)min((int64_t)DBW, ng - j0);
+    const int rl = tid & 15, g = tid >> 4;          // row in tile, column group
+    const int i = blockIdx.x * 16 + rl;             // row in block
+    for (int k0r = 0; k0r < nrhs; k0r += RB) {
+        const int nr = min(RB, nrhs - k0r);
+        for (int idx = tid; idx < nbw * RB; idx += 256) {
+            const int q = idx / RB, r = idx % RB;
+            vb[idx] = r < nr ? v[(int64_t)(k0r + r) * ng + j0 + q] : 0.0;
         }
-    const int64_t i = j0 + nb + (int64_t)blockIdx.x * 256 + tid;
-    if (i >= ng) return;
-    for (int k = 0; k < nrhs; ++k) {
-        double acc = 0.0;
-        for (int j = 0; j < nb; ++j) acc += S[i + (j0 + j) * ng] * yb[j + k * DNB];
-        v[(int64_t)k * ng + i] -= acc;
+        __syncthreads();
+        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+        if (i < nbw) {
+            const double *row = S + (j0 + i);
+            for (int q = g; q < i; q += 16) {
+                const double l = row[(j0 + q) * ng];
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * vb[q * RB + rr];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) red[(g * 16 + rl) * RB + rr] = acc[rr];
+        __syncthreads();
+        if (g == 0 && i < nbw)
+            for (int rr = 0; rr < nr; ++rr) {
+                double t = vb[i * RB + rr];
+                for (int gg = 0; gg < 16; ++gg) t += red[(gg * 16 + rl) * RB + rr];
+                y[(int64_t)(k0r + rr) * ng + j0 + i] = t;
+            }
+        __syncthreads();
+    }
+}
+
+// rows below the block: v[i] -= L[i, j0:j0+nbw] y[j0:j0+nbw], 64 rows per
+// workgroup, four partial sums per row
+__global__ __launch_bounds__(256) void k_dense_rows_fwd(const double *S, int64_t ng, double *v, const double *y,
+                                                        int nrhs, int64_t j0) {
+    __shared__ double yb[DBW * RB];
+    __shared__ double red[4 * 64 * RB];
+    const int tid = threadIdx.x;
+    const int nbw = (int)min((int64_t)DBW, ng - j0);
+    const int row = tid & 63, g = tid >> 6;
+    const int64_t i = j0 + nbw + (int64_t)blockIdx.x * 64 + row;
+    for (int k0r = 0; k0r < nrhs; k0r += RB) {
+        const int nr = min(RB, nrhs - k0r);
+        for (int idx = tid; idx < nbw * RB; idx += 256) {
+            const int q = idx / RB, r = idx % RB;
+            yb[idx] = r < nr ? y[(int64_t)(k0r + r) * ng + j0 + q] : 0.0;
+        }
+        __syncthreads();
+        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+        if (i < ng) {
+            const int qlo = 64 * g, qhi = min(nbw, qlo + 64);
+#pragma unroll 8
+            for (int q = qlo; q < qhi; ++q) {
+                const double l = S[i + (j0 + q) * ng];
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * yb[q * RB + rr];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) red[(g * 64 + row) * RB + rr] = acc[rr];
+        __syncthreads();
+        if (g == 0 && i < ng)
+            for (int rr = 0; rr < nr; ++rr) {
+                const double t = red[(0 * 64 + row) * RB + rr] + red[(1 * 64 + row) * RB + rr] +
+                                 red[(2 * 64 + row) * RB + rr] + red[(3 * 64 + row) * RB + rr];
+                v[(int64_t)(k0r + rr) * ng + i] -= t;
+            }
+        __syncthreads();
     }
 }
 
@@ -199,40 +316,82 @@ __global__ void k_div_diag(const double *S, int64_t ng, const double *y, double 
     for (int k = 0; k < nrhs; ++k) z[(int64_t)k * ng + i] = y[(int64_t)k * ng + i] / dd;
 }
 
-// backward step for rows [j0, j0+nb): solve L_jj^T x_j = z_j redundantly,
-// then each workgroup updates z of 256 columns q < j0.
-__global__ __launch_bounds__(256) void k_dense_bwd(const double *S, int64_t ng, double *z, double *x, int nrhs,
-                                                   int64_t j0) {
-    __shared__ double Lb[DNB * 65];
-    __shared__ double xb[DNB * 4];
+// x[j0:j0+nbw) = X^T z[j0:j0+nbw): 16 columns per workgroup, 16 partial sums
+__global__ __launch_bounds__(256) void k_dense_xblk(const double *S, int64_t ng, const double *z, double *x, int nrhs,
+                                                    int64_t j0) {
+    __shared__ double zb[DBW * RB];
+    __shared__ double red[16 * 16 * RB];
     const int tid = threadIdx.x;
-    const int nb = (int)min((int64_t)DNB, ng - j0);
-    for (int idx = tid; idx < nb * nb; idx += 256) {
-        int i = idx % nb, q = idx / nb;
-        Lb[i + q * 65] = S[(j0 + i) + (j0 + q) * ng];
-    }
-    for (int idx = tid; idx < nb * nrhs; idx += 256) {
-        int i = idx % nb, k = idx / nb;
-        xb[i + k * DNB] = z[(int64_t)k * ng + j0 + i];
-    }
-    __syncthreads();
-    if (tid < nrhs) {
-        double *xx = xb + tid * DNB;
-        for (int j = nb - 1; j >= 0; --j)
-            for (int q = 0; q < j; ++q) xx[q] -= Lb[j + q * 65] * xx[j];
-    }
-    __syncthreads();
-    if (blockIdx.x == 0)
-        for (int idx = tid; idx < nb * nrhs; idx += 256) {
-            int i = idx % nb, k = idx / nb;
-            x[(int64_t)k * ng + j0 + i] = xb[i + k * DNB];
+    const int nbw = (int)min((int64_t)DBW, ng - j0);
+    const int cl = tid & 15, g = tid >> 4;
+    const int q = blockIdx.x * 16 + cl;
+    for (int k0r = 0; k0r < nrhs; k0r += RB) {
+        const int nr = min(RB, nrhs - k0r);
+        for (int idx = tid; idx < nbw * RB; idx += 256) {
+            const int i = idx / RB, r = idx % RB;
+            zb[idx] = r < nr ? z[(int64_t)(k0r + r) * ng + j0 + i] : 0.0;
         }
-    const int64_t q = (int64_t)blockIdx.x * 256 + tid;
-    if (q >= j0) return;
-    for (int k = 0; k < nrhs; ++k) {
-        double acc = 0.0;
-        for (int j = 0; j < nb; ++j) acc += S[(j0 + j) + q * ng] * xb[j + k * DNB];
-        z[(int64_t)k * ng + q] -= acc;
+        __syncthreads();
+        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+        if (q < nbw) {
+            const double *col = S + j0 + (j0 + q) * ng;
+            for (int i = q + 1 + g; i < nbw; i += 16) {
+                const double l = col[i];
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * zb[i * RB + rr];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) red[(g * 16 + cl) * RB + rr] = acc[rr];
+        __syncthreads();
+        if (g == 0 && q < nbw)
+            for (int rr = 0; rr < nr; ++rr) {
+                double t = zb[q * RB + rr];
+                for (int gg = 0; gg < 16; ++gg) t += red[(gg * 16 + cl) * RB + rr];
+                x[(int64_t)(k0r + rr) * ng + j0 + q] = t;
+            }
+        __syncthreads();
+    }
+}
+
+// columns before the block: z[q] -= L[j0:j0+nbw, q]^T x[j0:j0+nbw], 64
+// columns per workgroup, four partial sums per column
+__global__ __launch_bounds__(256) void k_dense_cols_bwd(const double *S, int64_t ng, double *z, const double *x,
+                                                        int nrhs, int64_t j0) {
+    __shared__ double xb[DBW * RB];
+    __shared__ double red[4 * 64 * RB];
+    const int tid = threadIdx.x;
+    const int nbw = (int)min((int64_t)DBW, ng - j0);
+    const int cl = tid & 63, g = tid >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 64 + cl;
+    for (int k0r = 0; k0r < nrhs; k0r += RB) {
+        const int nr = min(RB, nrhs - k0r);
+        for (int idx = tid; idx < nbw * RB; idx += 256) {
+            const int i = idx / RB, r = idx % RB;
+            xb[idx] = r < nr ? x[(int64_t)(k0r + r) * ng + j0 + i] : 0.0;
+        }
+        __syncthreads();
+        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+        if (q < j0) {
+            const int ilo = 64 * g, ihi = min(nbw, ilo + 64);
+            const double *col = S + j0 + q * ng;
+#pragma unroll 8
+            for (int i = ilo; i < ihi; ++i) {
+                const double l = col[i];
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * xb[i * RB + rr];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) red[(g * 64 + cl) * RB + rr] = acc[rr];
+        __syncthreads();
+        if (g == 0 && q < j0)
+            for (int rr = 0; rr < nr; ++rr) {
+                const double t = red[(0 * 64 + cl) * RB + rr] + red[(1 * 64 + cl) * RB + rr] +
+                                 red[(2 * 64 + cl) * RB + rr] + red[(3 * 64 + cl) * RB + rr];
+                z[(int64_t)(k0r + rr) * ng + q] -= t;
+            }
+        __syncthreads();
     }
 }
 
@@ -244,20 +403,31 @@ void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t 
                        dim3(256), 0, st, b, ntot, nA, perm, sa);
 }
 
+static int rhs_block(int64_t nrhs, int maxm) {
+    int rb = (int)std::min<int64_t>(nrhs, RB);
+    while (rb > 1 && (int64_t)maxm * rb * 8 > 96 * 1024) --rb;
+    return rb;
+}
+static size_t front_lds(int maxm, int rb) { return sizeof(double) * ((size_t)maxm * rb + 64 * 65); }
+
 template <typename T>
 void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
                       const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_fwd<T>, dim3(ntasks, (unsigned)sa.N), dim3(256), sizeof(double) * maxm, st, L, Lstride,
-                       sd, tasks, tr, sa);
+    const int rb = rhs_block(sa.nrhs, maxm);
+    const size_t lds = front_lds(maxm, rb);
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_fwd<T>, dim3(ntasks, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, tasks, tr, sa, rb);
 }
 
 template <typename T>
 void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
                       const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_bwd<T>, dim3(ntasks, (unsigned)sa.N), dim3(256), sizeof(double) * maxm, st, L, Lstride,
-                       sd, tasks, tr, sa);
+    const int rb = rhs_block(sa.nrhs, maxm);
+    const size_t lds = front_lds(maxm, rb);
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_bwd<T>, dim3(ntasks, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, tasks, tr, sa, rb);
 }
 
 void launch_scatter_x(double *x, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa, const double *xg,
@@ -279,18 +449,26 @@ void launch_border_values(const double *xg, SolveArgs sa, int64_t nA, int64_t Ns
 }
 
 void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st) {
-    for (int64_t j0 = 0; j0 < ng; j0 += DNB) {
-        int64_t below = ng - j0 - DNB;
-        unsigned g = below > 0 ? (unsigned)((below + 255) / 256) : 1u;
-        hipLaunchKernelGGL(k_dense_fwd, dim3(g), dim3(256), 0, st, S, ng, v, y, (int)nrhs, j0);
+    for (int64_t j0 = 0; j0 < ng; j0 += DBW) {
+        const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
+        hipLaunchKernelGGL(k_dense_yblk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, v, y, (int)nrhs,
+                           j0);
+        const int64_t below = ng - j0 - DBW;
+        if (below > 0)
+            hipLaunchKernelGGL(k_dense_rows_fwd, dim3((unsigned)((below + 63) / 64)), dim3(256), 0, st, S, ng, v, y,
+                               (int)nrhs, j0);
     }
 }
 
 void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st) {
     hipLaunchKernelGGL(k_div_diag, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, S, ng, z, z, (int)nrhs);
-    for (int64_t j0 = ((ng - 1) / DNB) * DNB; j0 >= 0; j0 -= DNB) {
-        unsigned g = j0 > 0 ? (unsigned)((j0 + 255) / 256) : 1u;
-        hipLaunchKernelGGL(k_dense_bwd, dim3(g), dim3(256), 0, st, S, ng, z, x, (int)nrhs, j0);
+    for (int64_t j0 = ((ng - 1) / DBW) * DBW; j0 >= 0; j0 -= DBW) {
+        const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
+        hipLaunchKernelGGL(k_dense_xblk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, z, x, (int)nrhs,
+                           j0);
+        if (j0 > 0)
+            hipLaunchKernelGGL(k_dense_cols_bwd, dim3((unsigned)((j0 + 63) / 64)), dim3(256), 0, st, S, ng, z, x,
+                               (int)nrhs, j0);
     }
 }
 

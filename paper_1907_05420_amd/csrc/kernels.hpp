@@ -27,14 +27,23 @@ struct TreeArgs {
     const int64_t *rowptr;
 };
 
-// one right-looking step over a group of large fronts
+// One launch of the blocked right-looking factorisation over a group of large
+// fronts. Pivot columns go in 64-wide blocks inside outer panels of OUTER_W
+// columns: per block the pivot block (kind 0), the rows below it (kind 1) and
+// the rest of the outer panel (kind 2); after each outer panel one trailing
+// update of rank <= OUTER_W (kind 3 on 64x64 tiles, kind 4 on 128x128 tiles
+// for large trailing matrices); for the dense Schur factor also the inverse of
+// each OUTER_W diagonal block (kind 5).
+constexpr int OUTER_W = 256;
 struct StepDev {
-    int k0;
-    int nf;                 // fronts with pivots left at k0
+    int kind;
+    int t0, pe;             // first column of the block (kinds 0-2) or panel (3); panel end
+    int nf;                 // fronts in this launch
     const int32_t *fl;      // their FrontDesc indices
-    const int32_t *pre_trsm, *pre_tile;  // prefix sums of row chunks / tiles
-    int ntrsm, ntile;
+    const int32_t *pre;     // prefix sums of the per-front task counts (kinds 1-3)
+    int ntasks;
 };
+int step_tasks(int kind, int t0, int pe, int c, int m);
 
 template <typename T> void launch_zero(T *p, int64_t n, hipStream_t st);
 void launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st);
@@ -101,7 +110,9 @@ struct ResidualArgs {
     double dw, dc;
     int64_t n_primal;
 };
-// r = b - K x, plus per-rhs partial sums for ||r||_2, ||b||_2 and max omega
+// r = b - K x, plus per-rhs partial sums for ||r||_2, ||b||_2 and max omega;
+// `work` holds residual_work(...) doubles
+int64_t residual_work(int64_t N, int64_t nA, int64_t Ns, int64_t nrhs);
 void launch_residual(const ResidualArgs &ra, const double *b, const double *x, double *r, double *work,
                      double *norms, hipStream_t st);
 void launch_axpy(double *x, const double *dx, int64_t n, hipStream_t st);
