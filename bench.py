@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--refine", default="fgmres", choices=["fgmres", "classic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     args = ap.parse_args()
@@ -94,7 +95,8 @@ def main():
     prec = pk.KKT_MIXED if args.precision == "mixed" else pk.KKT_FP64
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s = pk.Solver(inst, precision=prec)
+    s = pk.Solver(inst, precision=prec,
+                  refine_method=pk.KKT_REFINE_CLASSIC if args.refine == "classic" else pk.KKT_REFINE_FGMRES)
     t_analyze = time.perf_counter() - t0
     st = s.stats()
     log(f"analyze {t_analyze*1e3:.1f} ms; stats {st}")
@@ -149,7 +151,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "mesh2000_N96", "buses": 2000, "lines": 3000, "generators": 400,
                    "storage": 200, "periods": 96, "block_rows": inst.n_A, "schur_dim": ng, "nrhs": 4,
-                   "barrier_range": [1e-8, 1e8], "precision": args.precision},
+                   "barrier_range": [1e-8, 1e8], "precision": args.precision, "refine": args.refine},
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "rel_res": max(i["rel_res"] for i in infos),

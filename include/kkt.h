@@ -70,7 +70,12 @@ typedef struct kkt_options {
     double refine_tol;  /* target max_k ||b_k - K x_k||_2 / ||b_k||_2, 1e-10   */
     int refine_max;     /* refinement steps at most (default 20)              */
     int verbose;        /* 0 quiet                                            */
+    int refine_method;  /* KKT_REFINE_FGMRES (default) or KKT_REFINE_CLASSIC   */
 } kkt_options;
+
+#define KKT_REFINE_FGMRES 0  /* flexible GMRES on K, right-preconditioned by the */
+                             /* factorisation; CGS2 orthogonalisation            */
+#define KKT_REFINE_CLASSIC 1 /* x += solve(b - K x)                              */
 
 /* Fill *opt with the defaults above. */
 void kkt_default_options(kkt_options *opt);
@@ -164,7 +169,10 @@ int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals,
 
 /* kkt_solve: x = K^-1 b for nrhs right-hand sides (Eqs. SCsolve, SCsolve1)
  * with FP64 iterative refinement on the unscaled K until rel_res <=
- * refine_tol or refine_max steps (section 2.1).
+ * refine_tol or refine_max steps (section 2.1): by default flexible GMRES
+ * preconditioned with the factorisation, restarted with the true residual;
+ * refinement also stops when the residual stagnates at its rounding floor or
+ * the componentwise backward error reaches the FP64 rounding level.
  *   b, x  device [nrhs][N*nA + N*Ns] FP64, column-major in u order; b != x.
  *   info  optional (host). The refinement loop reads one scalar per step
  *         from the device (a stream synchronisation per step).

@@ -19,7 +19,7 @@ import numpy as np
 from . import _abi
 from ._abi import (KKT_OK, KKT_ERR_ARG, KKT_ERR_NOMEM, KKT_ERR_ORDER, KKT_ERR_STRUCT, KKT_ERR_HIP,
                    KKT_ERR_NONFINITE, KKT_WARN_PERTURBED, KKT_WARN_INERTIA, KKT_WARN_REFINE, KKT_FP64,
-                   KKT_MIXED)
+                   KKT_MIXED, KKT_REFINE_FGMRES, KKT_REFINE_CLASSIC)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkt.so")
 _lib = None
@@ -86,10 +86,12 @@ def kkt_plan(nA, n_primal, N, Ns, colptr, rowind, C0p=None, C0i=None, C1p=None, 
     return {f: getattr(st, f) for f, _ in st._fields_}, perm
 
 
-def kkt_create(stream=None, precision=KKT_FP64, refine_tol=1e-10, refine_max=20, pivot_eps=0.0, verbose=0):
+def kkt_create(stream=None, precision=KKT_FP64, refine_tol=1e-10, refine_max=20, pivot_eps=0.0, verbose=0,
+               refine_method=KKT_REFINE_FGMRES):
     lib = load_library()
     o = kkt_default_options()
     o.precision, o.refine_tol, o.refine_max, o.pivot_eps, o.verbose = precision, refine_tol, refine_max, pivot_eps, verbose
+    o.refine_method = refine_method
     h = C.c_void_p()
     if stream is None:
         import torch
@@ -172,9 +174,9 @@ class Solver:
     n_primal, N, ns, colptr, rowind, C0_/C1_rowptr/colind)."""
 
     def __init__(self, inst, precision=KKT_FP64, stream=None, refine_tol=1e-10, refine_max=20, pivot_eps=0.0,
-                 verbose=0):
+                 verbose=0, refine_method=KKT_REFINE_FGMRES):
         self.inst = inst
-        self.ctx = kkt_create(stream, precision, refine_tol, refine_max, pivot_eps, verbose)
+        self.ctx = kkt_create(stream, precision, refine_tol, refine_max, pivot_eps, verbose, refine_method)
         kkt_analyze(self.ctx, inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind,
                     inst.C0_rowptr, inst.C0_colind, inst.C1_rowptr, inst.C1_colind)
 

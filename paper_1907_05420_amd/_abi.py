@@ -13,11 +13,13 @@ KKT_WARN_INERTIA = 2
 KKT_WARN_REFINE = 3
 KKT_FP64 = 0
 KKT_MIXED = 1
+KKT_REFINE_FGMRES = 0
+KKT_REFINE_CLASSIC = 1
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("pivot_eps", C.c_double), ("refine_tol", C.c_double),
-                ("refine_max", C.c_int), ("verbose", C.c_int)]
+                ("refine_max", C.c_int), ("verbose", C.c_int), ("refine_method", C.c_int)]
 
 
 class Structure(C.Structure):

@@ -18,7 +18,7 @@
 
 namespace kkt {
 SymbolicInput make_input(const kkt_structure *s);
-void fill_stats(const Symbolic &S, int64_t N, int precision, int64_t nrhs_max, kkt_symbolic_stats *st);
+void fill_stats(const Symbolic &S, int64_t N, const kkt_options &o, int64_t nrhs_max, kkt_symbolic_stats *st);
 }
 
 using namespace kkt;
@@ -34,8 +34,13 @@ using namespace kkt;
 
 namespace {
 
+// kind 0-5: launches (see StepDev); SYNC_TO_SIDE: the side stream waits for
+// the main stream's work so far; SYNC_TO_MAIN: the main stream waits for the
+// side stream's work so far.
+constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101;
 struct StepHost {
-    int kind, t0, pe, nf, ntasks;
+    int kind, win, t0, pe, nf, ntasks;
+    int side;                 // 1: enqueued on the side stream
     int64_t fl_off, pre_off;  // offsets (int32 elements) into the task buffer
 };
 
@@ -88,6 +93,13 @@ struct kkt_ctx {
     std::vector<void *> ws;
     double *d_xp = nullptr, *d_uv = nullptr, *d_bh = nullptr, *d_y = nullptr, *d_xg = nullptr, *d_res = nullptr,
            *d_dx = nullptr, *d_norms = nullptr, *d_work = nullptr;
+    // flexible GMRES: bases V (KRYLOV_M + 1 blocks) and Z (KRYLOV_M blocks) of
+    // [nrhs][ntot]; coefficients h1, h2 ([nrhs][ldh] each), norms [nrhs], y
+    // [nrhs][ldh] on the device with a pinned host mirror; reduction partials
+    double *d_V = nullptr, *d_Z = nullptr, *d_h = nullptr, *d_kpart = nullptr, *h_pin = nullptr;
+    // side stream and events of the lookahead
+    hipStream_t side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr;
     // timing
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -124,21 +136,32 @@ void free_static(kkt_ctx *ctx) {
 void free_ws(kkt_ctx *ctx) {
     for (void *p : ctx->ws) (void)hipFree(p);
     ctx->ws.clear();
+    if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
+    ctx->h_pin = nullptr;
+    ctx->d_V = ctx->d_Z = ctx->d_h = ctx->d_kpart = nullptr;
     ctx->bytes_ws = 0;
     ctx->ws_nrhs = 0;
 }
 
 // launch sequence of the blocked factorisation of a set of fronts
+// With lookahead (dense Schur), each trailing update is split: the next
+// panel's columns on the main stream, the rest on the side stream, so that the
+// latency-bound factorisation of the next panel overlaps the large update.
 void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl, std::vector<int32_t> &buf,
-                std::vector<StepHost> &steps, bool invert_panels = false) {
+                std::vector<StepHost> &steps, bool lookahead = false) {
     int cmax = 0;
     for (int32_t f : fl) cmax = std::max(cmax, fd[f].c);
-    auto add = [&](int kind, int t0, int pe) {
+    auto sync = [&](int kind) {
+        StepHost s{};
+        s.kind = kind;
+        steps.push_back(s);
+    };
+    auto add = [&](int kind, int t0, int pe, int win = 0, int side = 0) {
         std::vector<int32_t> act;
         std::vector<int> cnt;
         for (int32_t f : fl) {
             if (fd[f].c <= t0) continue;
-            int k = step_tasks(kind, t0, pe, fd[f].c, fd[f].m);
+            int k = step_tasks(kind, t0, pe, fd[f].c, fd[f].m, win);
             if (k <= 0) continue;
             act.push_back(f);
             cnt.push_back(k);
@@ -146,6 +169,8 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
         if (act.empty()) return;
         StepHost s{};
         s.kind = kind;
+        s.win = win;
+        s.side = side;
         s.t0 = t0;
         s.pe = pe;
         s.nf = (int)act.size();
@@ -160,6 +185,7 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
     };
     for (int k = 0; k < cmax; k += OUTER_W) {
         const int pe = k + OUTER_W;
+        if (lookahead && k > 0) sync(SYNC_TO_MAIN);  // this panel's columns: side update of panel k-1 done
         for (int j0 = k; j0 < std::min(pe, cmax); j0 += 64) {
             add(0, j0, pe);
             add(1, j0, pe);
@@ -169,14 +195,22 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
         int big = 0;
         for (int32_t f : fl)
             if (fd[f].c > k && fd[f].m - std::min(pe, fd[f].c) >= 512) big = 1;
-        add(big ? 4 : 3, k, pe);
-        if (invert_panels) add(5, k, pe);  // inverse of the panel's diagonal block (dense Schur solves)
+        if (!lookahead) {
+            add(big ? 4 : 3, k, pe);
+            continue;
+        }
+        add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
+        sync(SYNC_TO_SIDE);
+        add(5, k, pe, 0, 1);            // inverse of the panel's diagonal block (dense solves)
+        add(big ? 4 : 3, k, pe, 2, 1);  // the rest, side stream
     }
+    if (lookahead) sync(SYNC_TO_MAIN);
 }
 
 StepDev step_dev(const StepHost &s, const int32_t *base) {
     StepDev d;
     d.kind = s.kind;
+    d.win = s.win;
     d.t0 = s.t0;
     d.pe = s.pe;
     d.nf = s.nf;
@@ -381,6 +415,17 @@ int ensure_ws(kkt_ctx *ctx, int64_t nrhs) {
     if ((rc = get(&ctx->d_dx, ctx->ntot * nrhs))) return rc;
     if ((rc = get(&ctx->d_norms, 4 * nrhs + 8))) return rc;
     if ((rc = get(&ctx->d_work, residual_work(ctx->N, S.nA, S.Ns, nrhs)))) return rc;
+    if (uses_krylov(ctx->opt)) {
+        const int64_t ldh = KRYLOV_M + 1;
+        if ((rc = get(&ctx->d_V, (KRYLOV_M + 1) * ctx->ntot * nrhs))) return rc;
+        if ((rc = get(&ctx->d_Z, KRYLOV_M * ctx->ntot * nrhs))) return rc;
+        if ((rc = get(&ctx->d_h, 3 * ldh * nrhs + nrhs))) return rc;
+        if ((rc = get(&ctx->d_kpart, (int64_t)KRYLOV_PART * ldh * nrhs))) return rc;
+        if (hipHostMalloc((void **)&ctx->h_pin, 8 * (3 * ldh * nrhs + nrhs), hipHostMallocDefault) != hipSuccess) {
+            ctx->h_pin = nullptr;
+            return KKT_ERR_NOMEM;
+        }
+    }
     ctx->ws_nrhs = nrhs;
     return KKT_OK;
 }
@@ -469,7 +514,17 @@ int factor_schur(kkt_ctx *ctx) {
                           ctx->d_amaxS, 0, st);
     mark(ctx, 2);
     FactorArgs<double> fa = schur_args(ctx);
-    for (const StepHost &s : ctx->ssteps) launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, st);
+    for (const StepHost &s : ctx->ssteps) {
+        if (s.kind == SYNC_TO_SIDE) {
+            HIPCHK(hipEventRecord(ctx->ev_main, st));
+            HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_main, 0));
+        } else if (s.kind == SYNC_TO_MAIN) {
+            HIPCHK(hipEventRecord(ctx->ev_side, ctx->side));
+            HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
+        } else {
+            launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, s.side ? ctx->side : st);
+        }
+    }
     return KKT_OK;
 }
 
@@ -562,6 +617,12 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     ctx->eps = ctx->opt.pivot_eps > 0 ? ctx->opt.pivot_eps : (ctx->opt.precision == KKT_MIXED ? 1e-10 : 1e-20);
     ctx->stream = (hipStream_t)stream;
     if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return KKT_ERR_HIP; }
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming) != hipSuccess) {
+        kkt_destroy(ctx);
+        return KKT_ERR_HIP;
+    }
     for (auto &e : ctx->ev)
         if (hipEventCreate(&e) != hipSuccess) { delete ctx; return KKT_ERR_HIP; }
     *out = ctx;
@@ -607,7 +668,7 @@ extern "C" int kkt_footprint(const kkt_ctx *ctx, size_t *bytes) {
 extern "C" int kkt_stats(const kkt_ctx *ctx, kkt_symbolic_stats *st) {
     if (!ctx || !st) return KKT_ERR_ARG;
     if (!ctx->analyzed) return KKT_ERR_ORDER;
-    fill_stats(ctx->sy, ctx->N, ctx->opt.precision, std::max<int64_t>(ctx->ws_nrhs, 1), st);
+    fill_stats(ctx->sy, ctx->N, ctx->opt, std::max<int64_t>(ctx->ws_nrhs, 1), st);
     st->device_bytes = (int64_t)(ctx->bytes_static + ctx->bytes_ws);
     return KKT_OK;
 }
@@ -680,6 +741,159 @@ extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_v
     return KKT_OK;
 }
 
+namespace {
+
+constexpr double EPS64 = 2.220446049250313e-16;
+
+struct RefineState {
+    int it = 0, status = KKT_OK;
+    double rel = 0.0, omega = 0.0;
+};
+
+// true residual r = b - K x with its norms; returns false on a HIP error
+int true_residual(kkt_ctx *ctx, const ResidualArgs &ra, const double *b, const double *x, double *r, int64_t nrhs,
+                  std::vector<double> &nh, RefineState &rs) {
+    hipStream_t st = ctx->stream;
+    launch_residual(ra, b, x, r, ctx->d_work, ctx->d_norms, st);
+    HIPCHK(hipMemcpyAsync(nh.data(), ctx->d_norms, 8 * 4 * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    rs.rel = 0.0;
+    rs.omega = 0.0;
+    for (int64_t k = 0; k < nrhs; ++k) {
+        double rb = nh[4 * k + 1] > 0 ? nh[4 * k + 0] / nh[4 * k + 1] : nh[4 * k + 0];
+        rs.rel = std::max(rs.rel, rb);
+        rs.omega = std::max(rs.omega, nh[4 * k + 2]);
+    }
+    if (ctx->opt.verbose)
+        std::fprintf(stderr, "kkt_solve: step %d rel_res %.3e omega %.3e\n", rs.it, rs.rel, rs.omega);
+    return KKT_OK;
+}
+
+// common stopping tests on a true residual; true = stop
+bool refine_done(kkt_ctx *ctx, RefineState &rs) {
+    if (!std::isfinite(rs.rel)) { rs.status = KKT_WARN_REFINE; return true; }
+    if (rs.rel <= ctx->opt.refine_tol) return true;
+    // componentwise backward error at the FP64 rounding level: no step can
+    // improve the solution further
+    if (rs.omega <= 4.0 * EPS64) { rs.status = KKT_WARN_REFINE; return true; }
+    if (rs.it >= ctx->opt.refine_max) { rs.status = KKT_WARN_REFINE; return true; }
+    return false;
+}
+
+// classic refinement: x += M^-1 (b - K x)
+template <typename T>
+int refine_classic(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, RefineState &rs) {
+    ResidualArgs ra = residual_args(ctx, nrhs);
+    std::vector<double> nh(4 * nrhs), hist;
+    int rc;
+    while (true) {
+        if ((rc = true_residual(ctx, ra, b, x, ctx->d_res, nrhs, nh, rs))) return rc;
+        if (refine_done(ctx, rs)) break;
+        hist.push_back(rs.rel);
+        // stagnation: near the rounding floor one step without a 2x gain ends
+        // refinement; above it, two consecutive such steps
+        size_t h = hist.size();
+        if (h >= 2 && hist[h - 1] < 1e-6 && hist[h - 1] > 0.5 * hist[h - 2]) { rs.status = KKT_WARN_REFINE; break; }
+        if (h >= 3 && hist[h - 1] > 0.5 * hist[h - 2] && hist[h - 2] > 0.5 * hist[h - 3]) {
+            rs.status = KKT_WARN_REFINE;
+            break;
+        }
+        if ((rc = solve_once<T>(ctx, ctx->d_res, ctx->d_dx, nrhs))) return rc;
+        launch_axpy(x, ctx->d_dx, ctx->ntot * nrhs, ctx->stream);
+        ++rs.it;
+    }
+    return KKT_OK;
+}
+
+// Flexible GMRES on K x = b with the factorisation M as right
+// preconditioner (z_j = M^-1 v_j, x = x0 + Z y), classical Gram-Schmidt with
+// one reorthogonalisation, Givens rotations for the small least-squares
+// problem on the host, restarted from the true FP64 residual every
+// KRYLOV_M steps or once the estimated residual falls below half the target.
+// The right-hand sides run side by side, each with its own Hessenberg matrix.
+template <typename T>
+int refine_fgmres(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, RefineState &rs) {
+    hipStream_t st = ctx->stream;
+    ResidualArgs ra = residual_args(ctx, nrhs);
+    const int64_t n = ctx->ntot, blk = n * nrhs;
+    constexpr int M = KRYLOV_M, ldh = KRYLOV_M + 1;
+    double *V = ctx->d_V, *Z = ctx->d_Z;
+    double *h1 = ctx->d_h, *h2 = h1 + ldh * nrhs, *nrm = h2 + ldh * nrhs, *yd = nrm + nrhs;
+    const double *hh1 = ctx->h_pin, *hh2 = hh1 + ldh * nrhs, *hnrm = hh2 + ldh * nrhs;
+    double *hy = ctx->h_pin + (yd - h1);
+    std::vector<double> nh(4 * nrhs), bnorm(nrhs), H((size_t)nrhs * M * ldh), g((size_t)nrhs * ldh),
+        cs((size_t)nrhs * M), sn((size_t)nrhs * M);
+    double prev_cycle = INFINITY;
+    int rc;
+    while (true) {
+        if ((rc = true_residual(ctx, ra, b, x, V, nrhs, nh, rs))) return rc;
+        if (refine_done(ctx, rs)) break;
+        // a restart that did not halve the residual ends refinement
+        if (rs.rel > 0.5 * prev_cycle) { rs.status = KKT_WARN_REFINE; break; }
+        prev_cycle = rs.rel;
+        launch_norm(V, nrhs, n, ctx->d_kpart, nrm, 1, st);
+        std::fill(g.begin(), g.end(), 0.0);
+        for (int64_t k = 0; k < nrhs; ++k) {
+            bnorm[k] = nh[4 * k + 1] > 0 ? nh[4 * k + 1] : 1.0;
+            g[k * ldh] = nh[4 * k + 0];
+        }
+        int j = 0;
+        while (j < M && rs.it < ctx->opt.refine_max) {
+            double *Vj = V + j * blk, *Zj = Z + j * blk, *W = V + (j + 1) * blk;
+            if ((rc = solve_once<T>(ctx, Vj, Zj, nrhs))) return rc;
+            launch_matvec(ra, Zj, W, ctx->d_work, st);
+            launch_dots(W, V, j + 1, nrhs, n, ctx->d_kpart, h1, ldh, st);
+            launch_combine(W, V, j + 1, nrhs, n, h1, ldh, -1.0, st);
+            launch_dots(W, V, j + 1, nrhs, n, ctx->d_kpart, h2, ldh, st);
+            launch_combine(W, V, j + 1, nrhs, n, h2, ldh, -1.0, st);
+            launch_norm(W, nrhs, n, ctx->d_kpart, nrm, 1, st);
+            HIPCHK(hipMemcpyAsync(ctx->h_pin, h1, 8 * (2 * ldh * nrhs + nrhs), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            ++rs.it;
+            double est = 0.0;
+            for (int64_t k = 0; k < nrhs; ++k) {
+                double *col = &H[((size_t)k * M + j) * ldh];
+                double *c = &cs[(size_t)k * M], *s = &sn[(size_t)k * M], *gk = &g[(size_t)k * ldh];
+                for (int i = 0; i <= j; ++i) col[i] = hh1[k * ldh + i] + hh2[k * ldh + i];
+                col[j + 1] = hnrm[k];
+                for (int i = 0; i < j; ++i) {
+                    const double t = c[i] * col[i] + s[i] * col[i + 1];
+                    col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
+                    col[i] = t;
+                }
+                const double r = std::hypot(col[j], col[j + 1]);
+                c[j] = r > 0 ? col[j] / r : 1.0;
+                s[j] = r > 0 ? col[j + 1] / r : 0.0;
+                col[j] = r;
+                col[j + 1] = 0.0;
+                gk[j + 1] = -s[j] * gk[j];
+                gk[j] = c[j] * gk[j];
+                est = std::max(est, std::fabs(gk[j + 1]) / bnorm[k]);
+            }
+            ++j;
+            if (ctx->opt.verbose) std::fprintf(stderr, "kkt_solve:   fgmres %d estimate %.3e\n", rs.it, est);
+            if (!std::isfinite(est)) break;
+            if (est <= 0.5 * ctx->opt.refine_tol) break;
+        }
+        // y = R^-1 g (upper triangular R in the rotated H), x += Z y
+        for (int64_t k = 0; k < nrhs; ++k) {
+            const double *gk = &g[(size_t)k * ldh];
+            double *y = hy + k * ldh;
+            for (int i = j - 1; i >= 0; --i) {
+                double a = gk[i];
+                for (int l = i + 1; l < j; ++l) a -= H[((size_t)k * M + l) * ldh + i] * y[l];
+                const double d = H[((size_t)k * M + i) * ldh + i];
+                y[i] = d != 0.0 && std::isfinite(a) ? a / d : 0.0;
+            }
+        }
+        HIPCHK(hipMemcpyAsync(yd, hy, 8 * ldh * nrhs, hipMemcpyHostToDevice, st));
+        launch_combine(x, Z, j, nrhs, n, yd, ldh, 1.0, st);
+    }
+    return KKT_OK;
+}
+
+}  // namespace
+
 extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, kkt_solve_info *info) {
     if (!ctx) return KKT_ERR_ARG;
     if (!ctx->analyzed || !ctx->factored) return KKT_ERR_ORDER;
@@ -691,45 +905,12 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
     mark(ctx, 4);
     rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
     if (rc) return rc;
-    ResidualArgs ra = residual_args(ctx, nrhs);
-    std::vector<double> nh(4 * nrhs);
-    double rel = 0.0, omega = 0.0;
-    int it = 0, status = KKT_OK;
-    std::vector<double> hist;
-    while (true) {
-        launch_residual(ra, b, x, ctx->d_res, ctx->d_work, ctx->d_norms, st);
-        HIPCHK(hipMemcpyAsync(nh.data(), ctx->d_norms, 8 * 4 * nrhs, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        rel = 0.0;
-        omega = 0.0;
-        for (int64_t k = 0; k < nrhs; ++k) {
-            double rb = nh[4 * k + 1] > 0 ? nh[4 * k + 0] / nh[4 * k + 1] : nh[4 * k + 0];
-            rel = std::max(rel, rb);
-            omega = std::max(omega, nh[4 * k + 2]);
-        }
-        if (ctx->opt.verbose)
-            std::fprintf(stderr, "kkt_solve: refinement step %d rel_res %.3e omega %.3e\n", it, rel, omega);
-        if (!std::isfinite(rel)) { status = KKT_WARN_REFINE; break; }
-        hist.push_back(rel);
-        if (rel <= ctx->opt.refine_tol) break;
-        // componentwise backward error at the FP64 rounding level: no step can
-        // improve the solution further
-        if (omega <= 4.0 * 2.220446049250313e-16) { status = KKT_WARN_REFINE; break; }
-        if (it >= ctx->opt.refine_max) { status = KKT_WARN_REFINE; break; }
-        // stagnation: near the rounding floor one step without a 2x gain ends
-        // refinement; above it, two consecutive such steps
-        size_t h = hist.size();
-        if (h >= 2 && hist[h - 1] < 1e-6 && hist[h - 1] > 0.5 * hist[h - 2]) { status = KKT_WARN_REFINE; break; }
-        if (h >= 3 && hist[h - 1] > 0.5 * hist[h - 2] && hist[h - 2] > 0.5 * hist[h - 3]) {
-            status = KKT_WARN_REFINE;
-            break;
-        }
-        rc = mixed ? solve_once<float>(ctx, ctx->d_res, ctx->d_dx, nrhs)
-                   : solve_once<double>(ctx, ctx->d_res, ctx->d_dx, nrhs);
-        if (rc) return rc;
-        launch_axpy(x, ctx->d_dx, ctx->ntot * nrhs, st);
-        ++it;
-    }
+    RefineState rs;
+    if (uses_krylov(ctx->opt))
+        rc = mixed ? refine_fgmres<float>(ctx, b, x, nrhs, rs) : refine_fgmres<double>(ctx, b, x, nrhs, rs);
+    else
+        rc = mixed ? refine_classic<float>(ctx, b, x, nrhs, rs) : refine_classic<double>(ctx, b, x, nrhs, rs);
+    if (rc) return rc;
     mark(ctx, 5);
     HIPCHK(hipGetLastError());
     if (ctx->timing) {
@@ -737,12 +918,12 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
         ctx->times[3] = elapsed(ctx, 4, 5);
     }
     if (info) {
-        info->refine_iters = it;
-        info->rel_res = rel;
-        info->omega = omega;
+        info->refine_iters = rs.it;
+        info->rel_res = rs.rel;
+        info->omega = rs.omega;
         info->fallback_used = 0;
     }
-    return status;
+    return rs.status;
 }
 
 extern "C" int kkt_schur(kkt_ctx *ctx, double *S_out) {
@@ -785,7 +966,11 @@ extern "C" void kkt_destroy(kkt_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     free_ws(ctx);
     free_static(ctx);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->ev_main) (void)hipEventDestroy(ctx->ev_main);
+    if (ctx->ev_side) (void)hipEventDestroy(ctx->ev_side);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }

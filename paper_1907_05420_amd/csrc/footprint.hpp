@@ -4,11 +4,17 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/kkt.h"
 #include "symbolic.hpp"
 
 namespace kkt {
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// restart length of the flexible GMRES refinement
+constexpr int KRYLOV_M = 8;
+constexpr int KRYLOV_PART = 512;  // partial sums per Krylov reduction
+inline bool uses_krylov(const kkt_options &o) { return o.refine_method == KKT_REFINE_FGMRES && o.refine_max > 0; }
 
 struct DevPlan {
     // symbolic maps
@@ -18,14 +24,15 @@ struct DevPlan {
     size_t S, prefix;          // dense Schur + running sums of S_00
     // solve workspace for nrhs right-hand sides
     size_t xperm, uvec, r, xg, res, dx, norms;
+    size_t krylov;             // V, Z bases, coefficients and reduction partials (FGMRES only)
     size_t total_static() const {
         return amap + adiag + c0map + c1map + rows + rowptr + snmeta + rel + relptr + perm + pivsign + child +
                L + U + tau + counters + amax + S + prefix;
     }
-    size_t total_solve() const { return xperm + uvec + r + xg + res + dx + norms; }
+    size_t total_solve() const { return xperm + uvec + r + xg + res + dx + norms + krylov; }
 };
 
-inline DevPlan make_plan(const Symbolic &Sy, int64_t N, int precision, int64_t nrhs) {
+inline DevPlan make_plan(const Symbolic &Sy, int64_t N, int precision, int64_t nrhs, bool krylov) {
     DevPlan p{};
     const size_t w = precision == 1 ? 4 : 8;  // factor word size (KKT_MIXED = 1)
     const int64_t ng = N * Sy.Ns, nb = Sy.nbord;
@@ -58,11 +65,15 @@ inline DevPlan make_plan(const Symbolic &Sy, int64_t N, int precision, int64_t n
     p.dx = align_up(8 * ntot * nrhs);
     p.norms = align_up(8 * 4 * nrhs + 64) +
               align_up(8 * (N * Sy.Ns * nrhs + 2 * 512 * nrhs + ((Sy.nA + 255) / 256) * N * nrhs + 8));
+    const int ldh = KRYLOV_M + 1;
+    p.krylov = krylov ? align_up(8 * (2 * KRYLOV_M + 1) * ntot * nrhs) + align_up(8 * 3 * ldh * nrhs + 8 * nrhs) +
+                            align_up(8 * (int64_t)KRYLOV_PART * ldh * nrhs)
+                      : 0;
     return p;
 }
 
-inline size_t device_bytes(const Symbolic &Sy, int64_t N, int precision, int64_t nrhs) {
-    DevPlan p = make_plan(Sy, N, precision, nrhs);
+inline size_t device_bytes(const Symbolic &Sy, int64_t N, int precision, int64_t nrhs, bool krylov) {
+    DevPlan p = make_plan(Sy, N, precision, nrhs, krylov);
     return p.total_static() + p.total_solve();
 }
 

@@ -406,7 +406,9 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
 struct UpdGeom {
     int lo, qhi, K;
 };
-__host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int m) {
+// win (trailing updates only): 0 the whole trailing matrix; 1 the columns of
+// the next outer panel; 2 everything right of the next outer panel.
+__host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int m, int win = 0) {
     const int cend = pe < c ? pe : c;
     UpdGeom g;
     if (kind == 2) {
@@ -417,8 +419,21 @@ __host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int
         g.K = cend - t0;
         g.lo = cend;
         g.qhi = m;
+        const int nxt = pe + OUTER_W < m ? pe + OUTER_W : m;
+        if (win == 1) g.qhi = nxt;
+        else if (win == 2) g.lo = nxt;
     }
     return g;
+}
+
+// tile (ti, tj) of a trapezoid: column tiles tj < Tc, row tiles ti in [tj, Tr)
+__device__ inline void trap_decode(int t, int Tr, int &ti, int &tj) {
+    int j = (int)floor(((2.0 * Tr + 1.0) - sqrt((2.0 * Tr + 1.0) * (2.0 * Tr + 1.0) - 8.0 * t)) * 0.5);
+    if (j < 0) j = 0;
+    while (j > 0 && j * Tr - j * (j - 1) / 2 > t) --j;
+    while ((j + 1) * Tr - (j + 1) * j / 2 <= t) ++j;
+    tj = j;
+    ti = j + (t - (j * Tr - j * (j - 1) / 2));
 }
 
 // F(r, q) -= sum_k L(r, k) d_k L(q, k) for r >= q in the region of upd_geom:
@@ -426,7 +441,7 @@ __host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int
 // coalesced read-modify-write of the target through an LDS stage.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
-                                                const int32_t *pre, int nf, int kind, int t0, int pe) {
+                                                const int32_t *pre, int nf, int kind, int t0, int pe, int win) {
     typedef typename Acc<T>::type acc_t;
     __shared__ T sA[NB * LDS_LD];
     __shared__ T sB[NB * LDS_LD];
@@ -434,15 +449,10 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
     const FrontDesc d = sd[fl[fi]];
     const int n = blockIdx.y, tid = threadIdx.x;
     const int m = d.m, c = d.c;
-    const UpdGeom g = upd_geom(kind, t0, pe, c, m);
-    // trapezoid decode: column tiles tj < Tc, row tiles ti in [tj, Tr)
+    const UpdGeom g = upd_geom(kind, t0, pe, c, m, win);
     const int Tr = (m - g.lo + 63) / 64;
-    int t = blockIdx.x - pre[fi];
-    int tj = (int)floor(((2.0 * Tr + 1.0) - sqrt((2.0 * Tr + 1.0) * (2.0 * Tr + 1.0) - 8.0 * t)) * 0.5);
-    if (tj < 0) tj = 0;
-    while (tj > 0 && tj * Tr - tj * (tj - 1) / 2 > t) --tj;
-    while ((tj + 1) * Tr - (tj + 1) * tj / 2 <= t) ++tj;
-    const int ti = tj + (t - (tj * Tr - tj * (tj - 1) / 2));
+    int ti, tj;
+    trap_decode(blockIdx.x - pre[fi], Tr, ti, tj);
     const int R0 = g.lo + 64 * ti, Q0 = g.lo + 64 * tj;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
@@ -498,21 +508,17 @@ constexpr int LD2 = BT + 16; // LDS leading dimension (bank spread)
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
-                                                       const int32_t *pre, int nf, int t0, int pe) {
+                                                       const int32_t *pre, int nf, int t0, int pe, int win) {
     typedef typename Acc<T>::type acc_t;
     __shared__ T smem[2 * 2 * KC * LD2];
     const int fi = find_front(pre, nf, blockIdx.x);
     const FrontDesc d = sd[fl[fi]];
     const int n = blockIdx.y, tid = threadIdx.x;
     const int m = d.m, c = d.c;
-    const UpdGeom g = upd_geom(3, t0, pe, c, m);
+    const UpdGeom g = upd_geom(3, t0, pe, c, m, win);
     const int Tr = (m - g.lo + BT - 1) / BT;
-    const int t = blockIdx.x - pre[fi];
-    int tj = (int)floor(((2.0 * Tr + 1.0) - sqrt((2.0 * Tr + 1.0) * (2.0 * Tr + 1.0) - 8.0 * t)) * 0.5);
-    if (tj < 0) tj = 0;
-    while (tj > 0 && tj * Tr - tj * (tj - 1) / 2 > t) --tj;
-    while ((tj + 1) * Tr - (tj + 1) * tj / 2 <= t) ++tj;
-    const int ti = tj + (t - (tj * Tr - tj * (tj - 1) / 2));
+    int ti, tj;
+    trap_decode(blockIdx.x - pre[fi], Tr, ti, tj);
     const int R0 = g.lo + BT * ti, Q0 = g.lo + BT * tj;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
@@ -683,11 +689,11 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
     }
 }
 
-int step_tasks_big(int t0, int pe, int c, int m) {
-    const UpdGeom g = upd_geom(3, t0, pe, c, m);
+int step_tasks_big(int t0, int pe, int c, int m, int win) {
+    const UpdGeom g = upd_geom(3, t0, pe, c, m, win);
     if (g.K <= 0 || g.qhi <= g.lo) return 0;
-    const int Tr = (m - g.lo + BT - 1) / BT;
-    return Tr * (Tr + 1) / 2;
+    const int Tr = (m - g.lo + BT - 1) / BT, Tc = (g.qhi - g.lo + BT - 1) / BT;
+    return Tc * Tr - Tc * (Tc - 1) / 2;
 }
 
 // --------------------------------------------------------------------------
@@ -747,7 +753,7 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
             break;
         case 4:
             hipLaunchKernelGGL(k_update_big<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
-                               s.nf, s.t0, s.pe);
+                               s.nf, s.t0, s.pe, s.win);
             break;
         case 5:
             if constexpr (std::is_same<T, double>::value)
@@ -755,13 +761,13 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
             break;
         default:
             hipLaunchKernelGGL(k_update<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
-                               s.nf, s.kind, s.t0, s.pe);
+                               s.nf, s.kind, s.t0, s.pe, s.win);
     }
 }
 
 // host mirror of the per-front task counts of a step
-int step_tasks(int kind, int t0, int pe, int c, int m) {
-    if (kind == 4) return step_tasks_big(t0, pe, c, m);
+int step_tasks(int kind, int t0, int pe, int c, int m, int win) {
+    if (kind == 4) return step_tasks_big(t0, pe, c, m, win);
     if (kind == 5) return c > t0 ? 1 : 0;
     if (kind == 0) return c > t0 ? 1 : 0;
     if (kind == 1) {
@@ -769,7 +775,7 @@ int step_tasks(int kind, int t0, int pe, int c, int m) {
         const int rows = m - t0 - nb;
         return rows > 0 ? (rows + 63) / 64 : 0;
     }
-    const UpdGeom g = upd_geom(kind, t0, pe, c, m);
+    const UpdGeom g = upd_geom(kind, t0, pe, c, m, win);
     if (g.K <= 0 || g.qhi <= g.lo) return 0;
     const int Tr = (m - g.lo + 63) / 64, Tc = (g.qhi - g.lo + 63) / 64;
     return Tc * Tr - Tc * (Tc - 1) / 2;

@@ -19,7 +19,7 @@ __global__ void k_res_border(ResidualArgs ra, const double *b, const double *x, 
     for (int64_t m = 0; m < ra.N; ++m) {
         const int64_t g = m * ra.Ns + s;
         const double *xm = xk + m * ra.nA;
-        double bc = b[(int64_t)k * ra.ntot + ra.N * ra.nA + g];
+        double bc = b ? b[(int64_t)k * ra.ntot + ra.N * ra.nA + g] : 0.0;
         double acc = bc, ab = fabs(bc);
         if (ra.corner) { double t = ra.corner[g] * xg[g]; acc -= t; ab += fabs(t); }
         for (int64_t e = ra.c1p[s]; e < ra.c1p[s + 1]; ++e) {
@@ -29,7 +29,7 @@ __global__ void k_res_border(ResidualArgs ra, const double *b, const double *x, 
         }
         acc -= acc0;
         ab += abs0;
-        r[(int64_t)k * ra.ntot + ra.N * ra.nA + g] = acc;
+        r[(int64_t)k * ra.ntot + ra.N * ra.nA + g] = b ? acc : -acc;
         if (ab > 0.0) wmax = fmax(wmax, fabs(acc) / ab);
         else if (acc != 0.0) wmax = INFINITY;
         for (int64_t e = ra.c0p[s]; e < ra.c0p[s + 1]; ++e) {
@@ -43,7 +43,7 @@ __global__ void k_res_border(ResidualArgs ra, const double *b, const double *x, 
         sg[(int64_t)k * ng + n * ra.Ns + s] = acc;
         acc += xg[n * ra.Ns + s];
     }
-    atomic_max_nonneg(norms + 4 * k + 2, wmax);
+    if (norms) atomic_max_nonneg(norms + 4 * k + 2, wmax);
 }
 
 __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const double *b, const double *x, double *r,
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
             const double *xn = xk + (int64_t)n * ra.nA;
             const double *xg = xk + ra.N * ra.nA;
             const int64_t row = (int64_t)k * ra.ntot + (int64_t)n * ra.nA + i;
-            double acc = b[row], ab = fabs(acc);
+            double acc = b ? b[row] : 0.0, ab = fabs(acc);
 #pragma unroll 4
             for (int64_t e = e0; e < e1; ++e) {
                 const int32_t j = ra.ci[e];
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
                 acc -= t;
                 ab += fabs(t);
             }
-            r[row] = acc;
+            r[row] = b ? acc : -acc;
             if (ab > 0.0) w = fabs(acc) / ab;
             else if (acc != 0.0) w = INFINITY;
         }
@@ -91,7 +91,8 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
             if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
             __syncthreads();
         }
-        if (threadIdx.x == 0) wpart[(int64_t)k * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        if (threadIdx.x == 0 && wpart)
+            wpart[(int64_t)k * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
         __syncthreads();
     }
 }
@@ -176,6 +177,16 @@ void launch_residual(const ResidualArgs &ra, const double *b, const double *x, d
                        x, r, sg, wpart);
     hipLaunchKernelGGL(k_norm_partial, dim3(NPART, (unsigned)ra.nrhs), dim3(256), 0, st, r, b, ra.ntot, part);
     hipLaunchKernelGGL(k_norm_final, dim3((unsigned)ra.nrhs), dim3(256), 0, st, part, wpart, nw, norms);
+}
+
+// y = K x (no norms)
+void launch_matvec(const ResidualArgs &ra, const double *x, double *y, double *work, hipStream_t st) {
+    double *sg = work;
+    if (ra.Ns > 0)
+        hipLaunchKernelGGL(k_res_border, dim3((unsigned)((ra.Ns + 127) / 128), (unsigned)ra.nrhs), dim3(128), 0, st,
+                           ra, (const double *)nullptr, x, y, sg, (double *)nullptr);
+    hipLaunchKernelGGL(k_res_periods, dim3((unsigned)((ra.nA + 255) / 256), (unsigned)ra.N), dim3(256), 0, st, ra,
+                       (const double *)nullptr, x, y, sg, (double *)nullptr);
 }
 
 __global__ void k_axpy(double *x, const double *dx, int64_t n) {

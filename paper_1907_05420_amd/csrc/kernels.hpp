@@ -37,13 +37,14 @@ struct TreeArgs {
 constexpr int OUTER_W = 256;
 struct StepDev {
     int kind;
+    int win;                // trailing updates: 0 all, 1 next panel's columns, 2 the rest
     int t0, pe;             // first column of the block (kinds 0-2) or panel (3); panel end
     int nf;                 // fronts in this launch
     const int32_t *fl;      // their FrontDesc indices
     const int32_t *pre;     // prefix sums of the per-front task counts (kinds 1-3)
     int ntasks;
 };
-int step_tasks(int kind, int t0, int pe, int c, int m);
+int step_tasks(int kind, int t0, int pe, int c, int m, int win = 0);
 
 template <typename T> void launch_zero(T *p, int64_t n, hipStream_t st);
 void launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st);
@@ -116,5 +117,17 @@ int64_t residual_work(int64_t N, int64_t nA, int64_t Ns, int64_t nrhs);
 void launch_residual(const ResidualArgs &ra, const double *b, const double *x, double *r, double *work,
                      double *norms, hipStream_t st);
 void launch_axpy(double *x, const double *dx, int64_t n, hipStream_t st);
+void launch_matvec(const ResidualArgs &ra, const double *x, double *y, double *work, hipStream_t st);
+
+// ---- Krylov helpers (vectors are [nrhs][n] blocks; coefficient arrays on device)
+// h[k * ldh + i] = <W_k, V_i,k> for i < nv (deterministic two-stage sums;
+// part holds nrhs * nv * 512 doubles)
+void launch_dots(const double *W, const double *V, int nv, int64_t nrhs, int64_t n, double *part, double *h,
+                 int ldh, hipStream_t st);
+// W_k -= sum_i h[k * ldh + i] V_i,k   (sign = -1) or  += (sign = +1)
+void launch_combine(double *W, const double *V, int nv, int64_t nrhs, int64_t n, const double *h, int ldh,
+                    double sign, hipStream_t st);
+// nrm[k] = ||W_k||_2 ; then W_k /= nrm[k] when normalize
+void launch_norm(double *W, int64_t nrhs, int64_t n, double *part, double *nrm, int normalize, hipStream_t st);
 
 }  // namespace kkt

@@ -15,6 +15,7 @@ extern "C" void kkt_default_options(kkt_options *opt) {
     opt->refine_tol = 1e-10;
     opt->refine_max = 20;
     opt->verbose = 0;
+    opt->refine_method = KKT_REFINE_FGMRES;
 }
 
 extern "C" const char *kkt_strerror(int code) {
@@ -48,7 +49,7 @@ SymbolicInput make_input(const kkt_structure *s) {
     return in;
 }
 
-void fill_stats(const Symbolic &S, int64_t N, int precision, int64_t nrhs_max, kkt_symbolic_stats *st) {
+void fill_stats(const Symbolic &S, int64_t N, const kkt_options &o, int64_t nrhs_max, kkt_symbolic_stats *st) {
     st->n_supernodes = S.nsup;
     st->n_levels = S.nlevels;
     st->nnz_L = S.nnzL;
@@ -56,7 +57,7 @@ void fill_stats(const Symbolic &S, int64_t N, int precision, int64_t nrhs_max, k
     st->max_front = S.max_front;
     st->max_pivots = S.max_pivots;
     st->flops_factor = S.flops;
-    st->device_bytes = (int64_t)device_bytes(S, N, precision, nrhs_max);
+    st->device_bytes = (int64_t)device_bytes(S, N, o.precision, nrhs_max, uses_krylov(o));
 }
 }  // namespace kkt
 
@@ -74,7 +75,7 @@ extern "C" int kkt_plan(const kkt_structure *s, const kkt_options *opt, int64_t 
         return KKT_ERR_NOMEM;
     }
     if (!err.empty()) return KKT_ERR_STRUCT;
-    kkt::fill_stats(S, s->N, o.precision, nrhs_max, st);
+    kkt::fill_stats(S, s->N, o, nrhs_max, st);
     if (std::getenv("KKT_DEBUG_FRONTS")) {
         for (int32_t l = 0; l < S.nlevels; ++l) {
             int64_t cnt = 0, big = 0, mx = 0, sm = 0;
