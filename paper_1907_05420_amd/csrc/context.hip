@@ -45,9 +45,10 @@ struct StepHost {
 };
 
 struct LevelPlan {
-    int64_t small_off = 0, all_off = 0, ea_off = 0;  // int32 offsets into the task buffer
-    int nsmall = 0, nall = 0, nea = 0;
-    int maxm = 0;
+    int64_t small_off = 0, all_off = 0, ea_off = 0, large_off = 0;  // int32 offsets into the task buffer
+    int64_t rrow_off = 0, rcol_off = 0;                             // RowTask lists of the solve
+    int nsmall = 0, nall = 0, nea = 0, nlarge = 0, nrrow = 0, nrcol = 0;
+    int maxm = 0, maxm_large = 0, maxc_large = 0;
     int step_begin = 0, step_end = 0;
 };
 
@@ -273,7 +274,11 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             all.push_back(t);
             lp.maxm = std::max(lp.maxm, S.nrow[t]);
             if (S.nrow[t] <= 64) small.push_back(t);
-            else large.push_back(t);
+            else {
+                large.push_back(t);
+                lp.maxm_large = std::max(lp.maxm_large, S.nrow[t]);
+                lp.maxc_large = std::max(lp.maxc_large, S.ncol[t]);
+            }
         }
         lp.small_off = (int64_t)buf.size();
         lp.nsmall = (int)small.size();
@@ -281,6 +286,9 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         lp.all_off = (int64_t)buf.size();
         lp.nall = (int)all.size();
         buf.insert(buf.end(), all.begin(), all.end());
+        lp.large_off = (int64_t)buf.size();
+        lp.nlarge = (int)large.size();
+        buf.insert(buf.end(), large.begin(), large.end());
         lp.ea_off = (int64_t)buf.size();
         if (buf.size() % 2) buf.push_back(0);  // RowTask alignment (pairs of int32)
         lp.ea_off = (int64_t)buf.size();
@@ -288,6 +296,15 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         for (int32_t t : large)
             for (int r0 = 0; r0 < S.nrow[t]; r0 += 64) { buf.push_back(t); buf.push_back(r0); ++nea; }
         lp.nea = nea;
+        // solve: 64 update rows / 64 pivot columns of each large front
+        lp.rrow_off = (int64_t)buf.size();
+        for (int32_t t : large)
+            if (S.ncol[t] > 0)
+                for (int r0 = S.ncol[t]; r0 < S.nrow[t]; r0 += 64) { buf.push_back(t); buf.push_back(r0); ++lp.nrrow; }
+        lp.rcol_off = (int64_t)buf.size();
+        for (int32_t t : large)
+            if (S.nrow[t] > S.ncol[t])
+                for (int q0 = 0; q0 < S.ncol[t]; q0 += 64) { buf.push_back(t); buf.push_back(q0); ++lp.nrcol; }
         lp.step_begin = (int)ctx->steps.size();
         plan_steps(fd, large, buf, ctx->steps);
         lp.step_end = (int)ctx->steps.size();
@@ -525,6 +542,7 @@ int factor_schur(kkt_ctx *ctx) {
             launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, s.side ? ctx->side : st);
         }
     }
+    launch_mirror_lower(ctx->d_S, ctx->ng, st);
     return KKT_OK;
 }
 
@@ -544,8 +562,21 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
     TreeArgs tr = tree_args(ctx);
     const T *L = (const T *)ctx->d_L;
     launch_gather_rhs<T>(b, ctx->ntot, S.nA, ctx->d_perm, sa, st);
-    for (const LevelPlan &lp : ctx->levels)
-        launch_fwd_level<T>(L, S.Lsize, ctx->d_sd, ctx->d_tasks + lp.all_off, lp.nall, lp.maxm, tr, sa, st);
+    auto tasks_of = [&](const LevelPlan &lp) {
+        LevelTasks lt;
+        lt.small = ctx->d_tasks + lp.small_off;
+        lt.large = ctx->d_tasks + lp.large_off;
+        lt.rect_rows = (const RowTask *)(ctx->d_tasks + lp.rrow_off);
+        lt.rect_cols = (const RowTask *)(ctx->d_tasks + lp.rcol_off);
+        lt.nsmall = lp.nsmall;
+        lt.nlarge = lp.nlarge;
+        lt.nrect_rows = lp.nrrow;
+        lt.nrect_cols = lp.nrcol;
+        lt.maxm = lp.maxm_large;
+        lt.maxc = lp.maxc_large;
+        return lt;
+    };
+    for (const LevelPlan &lp : ctx->levels) launch_fwd_level<T>(L, S.Lsize, ctx->d_sd, tasks_of(lp), tr, sa, st);
     if (ctx->ng > 0) {
         launch_schur_rhs(b, ctx->ntot, S.nA, sa, S.Ns, S.relptr[S.border_sn], ctx->d_bh, st);
         launch_dense_fwd(ctx->d_S, ctx->ng, ctx->d_bh, ctx->d_y, nrhs, st);
@@ -554,7 +585,7 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
     }
     for (int l = (int)ctx->levels.size() - 1; l >= 0; --l) {
         const LevelPlan &lp = ctx->levels[l];
-        launch_bwd_level<T>(L, S.Lsize, ctx->d_sd, ctx->d_tasks + lp.all_off, lp.nall, lp.maxm, tr, sa, st);
+        launch_bwd_level<T>(L, S.Lsize, ctx->d_sd, tasks_of(lp), tr, sa, st);
     }
     launch_scatter_x(x, ctx->ntot, S.nA, ctx->d_perm, sa, ctx->d_xg, ctx->ng, st);
     return KKT_OK;

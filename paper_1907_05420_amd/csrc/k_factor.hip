@@ -41,10 +41,17 @@ struct PivTally {
     __device__ void add(int cls, int pert) { c[cls]++; c[3] += pert; }
 };
 
+// expected sign of pivot gpiv (dual pivots and the Schur complement: -1)
 template <typename T>
-__device__ inline T do_pivot(const FactorArgs<T> &fa, int n, int gpiv, T raw, double tau_k, PivTally &tl) {
-    const int sgn = fa.sign ? (int)fa.sign[gpiv] : -1;
-    const double t = tau_k > 0.0 ? tau_k : fa.eps * fa.amax[n];
+__device__ inline int pivot_sign(const FactorArgs<T> &fa, int gpiv) {
+    return fa.sign ? (int)fa.sign[gpiv] : -1;
+}
+
+// raw pivot -> stored pivot; tau_k the pivot's own threshold, tfb the
+// threshold used where tau_k is zero (eps * max|A| of the block)
+template <typename T>
+__device__ inline T do_pivot(T raw, double tau_k, int sgn, double tfb, PivTally &tl) {
+    const double t = tau_k > 0.0 ? tau_k : tfb;
     int cls, pert;
     const double v = pivot_rule((double)raw, t, sgn, cls, pert);
     tl.add(cls, pert);
@@ -131,30 +138,51 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c, u = m - c;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
-    for (int idx = tid; idx < m * m; idx += 64) {
-        int r = idx % m, q = idx / m;
-        if (r >= q) F[r + q * LDT] = q < c ? P[r + (int64_t)q * m] : T(0);
+    // lane r owns row r; loads in batches of 8 from clamped addresses
+    const int rc = min(tid, m - 1);
+    for (int q0 = 0; q0 < m; q0 += 8) {
+        T v[8];
+#pragma unroll
+        for (int u2 = 0; u2 < 8; ++u2) v[u2] = c > 0 ? P[rc + (int64_t)min(q0 + u2, c - 1) * m] : T(0);
+#pragma unroll
+        for (int u2 = 0; u2 < 8; ++u2) {
+            const int q = q0 + u2;
+            if (tid < m && q <= tid) F[tid + q * LDT] = q < c ? v[u2] : T(0);
+        }
     }
     __syncthreads();
     for (int k = cptr[s]; k < cptr[s + 1]; ++k) {
         const int ch = clist[k];
         const FrontDesc dc = sd[ch];
-        const int uc = dc.m - dc.c;
+        const int uc = dc.m - dc.c;   // at most m: the child's update rows are rows of this front
         const T *Uc = fa.U + (int64_t)n * fa.Ustride + dc.Uoff;
-        const int32_t *rl = rel + relptr[ch];
-        for (int idx = tid; idx < uc * uc; idx += 64) {
-            int i = idx % uc, j = idx / uc;
-            if (i >= j) F[rl[i] + rl[j] * LDT] += Uc[i + (int64_t)j * uc];
+        const int ri = tid < uc ? rel[relptr[ch] + tid] : 0;
+        const T *Ui = Uc + min(tid, uc - 1);
+        for (int j0 = 0; j0 < uc; j0 += 8) {
+            T v[8];
+#pragma unroll
+            for (int u2 = 0; u2 < 8; ++u2) v[u2] = Ui[(int64_t)min(j0 + u2, uc - 1) * uc];
+#pragma unroll
+            for (int u2 = 0; u2 < 8; ++u2) {
+                const int j = j0 + u2;
+                const int rj = __shfl(ri, min(j, 63), 64);
+                if (tid < uc && j <= tid) F[ri + rj * LDT] += v[u2];
+            }
         }
         __syncthreads();
     }
     PivTally tl;
     __shared__ double taus[SMALL_M];
-    if (tid < c) taus[tid] = fa.tau[(int64_t)n * fa.tstride + d.piv0 + tid];
+    __shared__ int sgns[SMALL_M];
+    if (tid < c) {
+        taus[tid] = fa.tau[(int64_t)n * fa.tstride + d.piv0 + tid];
+        sgns[tid] = pivot_sign(fa, d.piv0 + tid);
+    }
+    const double tfb = fa.eps * fa.amax[n];
     __syncthreads();
     for (int j = 0; j < c; ++j) {
         if (tid == 0) {
-            T v = do_pivot(fa, n, d.piv0 + j, F[j + j * LDT], taus[j], tl);
+            T v = do_pivot(F[j + j * LDT], taus[j], sgns[j], tfb, tl);
             F[j + j * LDT] = v;
             piv = v;
         }
@@ -201,6 +229,8 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
 // --------------------------------------------------------------------------
 // large fronts
 // --------------------------------------------------------------------------
+constexpr int EA_RL = 1024;  // staged target columns of an extend-add tile
+
 template <typename T>
 __device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q) {
     return q < c ? P + r + (int64_t)q * m : Ub + (r - c) + (int64_t)(q - c) * (m - c);
@@ -214,6 +244,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const RowTask *tasks,
                                                     const int32_t *cptr, const int32_t *clist,
                                                     const int64_t *relptr, const int32_t *rel) {
+    __shared__ int32_t rls[EA_RL];
     const RowTask tk = tasks[blockIdx.x];
     const int n = blockIdx.y;
     const FrontDesc d = sd[tk.f];
@@ -227,18 +258,40 @@ __global__ __launch_bounds__(256) void k_extend_add(FactorArgs<T> fa, const Fron
         const int uc = dc.m - dc.c;
         const T *Uc = fa.U + (int64_t)n * fa.Ustride + dc.Uoff;
         const int32_t *rl = rel + relptr[ch];
-        int lo = 0, hi = uc;  // first child row with rl >= r0
+        // the child rows landing in [r0, r1) (binary search; rl increases)
+        int lo = 0, hi = uc;
         while (lo < hi) { int mid = (lo + hi) >> 1; if (rl[mid] < r0) lo = mid + 1; else hi = mid; }
         const int i_lo = lo;
-        hi = uc;
+        hi = min(uc, i_lo + 64);
         while (lo < hi) { int mid = (lo + hi) >> 1; if (rl[mid] < r1) lo = mid + 1; else hi = mid; }
         const int i_hi = lo;
-        const int i = i_lo + lane;
-        if (i < i_hi) {
-            const int R = rl[i];
-            for (int j = wv; j <= i; j += 4) {
-                const int Q = rl[j];
-                *front_addr(P, Ub, d.m, d.c, R, Q) += Uc[i + (int64_t)j * uc];
+        // the columns j <= i_hi - 1 of those rows, target column indices staged
+        for (int j0 = 0; j0 < i_hi; j0 += EA_RL) {
+            const int jn = min(EA_RL, i_hi - j0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < jn; t += 256) rls[t] = rl[j0 + t];
+            __syncthreads();
+            const int i = i_lo + lane;
+            if (i < i_hi) {
+                const int R = rl[i];
+                const T *Ui = Uc + i;
+                const int jend = min(jn, i - j0 + 1);
+                for (int jj = wv; jj < jend; jj += 32) {
+                    T v[8];
+                    T *ad[8];
+#pragma unroll
+                    for (int u2 = 0; u2 < 8; ++u2) {
+                        const int jc = min(jj + 4 * u2, jend - 1);
+                        v[u2] = Ui[(int64_t)(j0 + jc) * uc];
+                        ad[u2] = front_addr(P, Ub, d.m, d.c, R, rls[jc]);
+                    }
+                    T o[8];
+#pragma unroll
+                    for (int u2 = 0; u2 < 8; ++u2) o[u2] = *ad[u2];
+#pragma unroll
+                    for (int u2 = 0; u2 < 8; ++u2)
+                        if (jj + 4 * u2 < jend) *ad[u2] = o[u2] + v[u2];
+                }
             }
         }
         __syncthreads();
@@ -253,6 +306,17 @@ __global__ __launch_bounds__(256) void k_extend_add(FactorArgs<T> fa, const Fron
 // Four waves: lane i holds row i, wave w holds columns [16w, 16w+16) of both
 // the block F and X = L^-1, built alongside the elimination (the row
 // operations of step j applied to the identity).
+// value of v in lane `lane` (wave-uniform) of the calling wavefront
+__device__ inline double lane_value(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_value(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ inline int lane_value(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int t0) {
     __shared__ T col[NB];
@@ -264,43 +328,57 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
     T R[16], X[16];
     PivTally tl;
     const double my_tau = (i < nb) ? fa.tau[(int64_t)n * fa.tstride + d.piv0 + t0 + i] : 0.0;
+    const int my_sgn = (i < nb) ? pivot_sign(fa, d.piv0 + t0 + i) : -1;
+    const double tfb = fa.eps * fa.amax[n];
+    {
+        const T *Pi = P + (t0 + min(i, nb - 1)) + (int64_t)(t0 + 16 * w) * m;
+        T v[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int q = 16 * w + k;
-        R[k] = (i < nb && q <= i) ? P[(t0 + i) + (int64_t)(t0 + q) * m] : T(0);
-        X[k] = (q == i) ? T(1) : T(0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        if (j >= nb) break;
-        const int wj = j >> 4, kj = j & 15;
-        const double tj = __shfl(my_tau, j, 64);
-        if (w == wj) {
-            if (i == j) {
-                T v = do_pivot(fa, n, d.piv0 + t0 + j, R[kj], tj, tl);
-                R[kj] = v;
-                piv = v;
-            }
-        }
-        __syncthreads();
-        const T dj = piv;
-        if (w == wj) {
-            const T l = (i > j && i < nb) ? R[kj] / dj : T(0);
-            if (i > j) R[kj] = l;
-            col[i] = l;
-        }
-        __syncthreads();
-        const T li = col[i];
-        const T ld = li * dj;
-        // row j of X for this wave's columns (lane j of the same wave)
+        for (int k = 0; k < 16; ++k) v[k] = Pi[(int64_t)min(16 * w + k, nb - 1) * m - (int64_t)(16 * w) * m];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int q = 16 * w + k;
-            const T xj = __shfl(X[k], j, 64);
-            if (q > j) R[k] -= ld * col[q];
-            if (q <= j && i > j) X[k] -= li * xj;
+            R[k] = (i < nb && q <= i) ? v[k] : T(0);
+            X[k] = (q == i) ? T(1) : T(0);
         }
-        __syncthreads();
+    }
+    // step j: the pivot in lane j of wave j/16, the multipliers of column j
+    // through LDS, then the rank-1 update of F and the row operation on X
+    // (branch-free so that the LDS reads of a step are issued together)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+        for (int kj = 0; kj < 16; ++kj) {
+            const int j = 16 * jb + kj;
+            if (j >= nb) break;
+            const double tj = lane_value(my_tau, j);
+            const int sj = lane_value(my_sgn, j);
+            if (w == jb && i == j) {
+                const T v = do_pivot(R[kj], tj, sj, tfb, tl);
+                R[kj] = v;
+                piv = v;
+            }
+            __syncthreads();
+            const T dj = piv;
+            if (w == jb) {
+                const T l = (i > j && i < nb) ? R[kj] / dj : T(0);
+                if (i > j) R[kj] = l;
+                col[i] = l;
+            }
+            __syncthreads();
+            const T li = col[i];
+            const T ld = li * dj;
+            T cq[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) cq[k] = col[16 * w + k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int q = 16 * w + k;
+                const T xj = lane_value(X[k], j);
+                R[k] = q > j ? R[k] - ld * cq[k] : R[k];
+                X[k] = (q <= j && i > j) ? X[k] - li * xj : X[k];
+            }
+        }
     }
     if (i < nb) {
 #pragma unroll
@@ -628,16 +706,22 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
     // (transposed, "A" operand) or sX[k][q] = M[k][q] ("B" operand); unit
     // lower when diag.
     auto load = [&](double *sX, int r0, int c0, bool asA, bool diag) {
+        // clamped addresses, all 16 loads issued before the first use
+        const int lim = j0 + nbw - 1;
+        double val[16];
+#pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int k = kk + 4 * j;
-            // element M[a][b] with a = row index, b = column index
             const int a = asA ? row : k, b = asA ? k : row;
-            double v = 0.0;
-            const int ra = r0 + a, cb = c0 + b;
-            if (ra < j0 + nbw && cb < j0 + nbw) {
-                if (!diag) v = P[(int64_t)(ra) + (int64_t)cb * m];
-                else v = a > b ? P[(int64_t)ra + (int64_t)cb * m] : (a == b ? 1.0 : 0.0);
-            }
+            val[j] = P[(int64_t)min(r0 + a, lim) + (int64_t)min(c0 + b, lim) * m];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k = kk + 4 * j;
+            const int a = asA ? row : k, b = asA ? k : row;
+            const bool in = r0 + a <= lim && c0 + b <= lim;
+            double v = in ? val[j] : 0.0;
+            if (diag) v = a > b ? v : (a == b ? 1.0 : 0.0);
             sX[k * LDS_LD + row] = v;
         }
     };

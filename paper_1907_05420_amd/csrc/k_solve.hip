@@ -24,88 +24,262 @@ __global__ void k_gather_rhs(const double *b, int64_t ntot, int64_t nA, const in
 }
 
 // Up to RB right-hand sides go through a front together (the factor is read
-// once per pass); v[i * RB + r] holds row i of right-hand side r.
+// once per pass); v[i * RBT + r] holds row i of right-hand side r, with zeros
+// for the right-hand sides beyond the last.
 constexpr int RB = 4;
 
-constexpr int SNT = 512;  // threads of a front solve
+constexpr int SNT = 512;  // threads of a front's triangular solve
 
-template <typename T>
-__global__ __launch_bounds__(SNT) void k_fwd(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks,
-                                             TreeArgs tr, SolveArgs sa, int rb) {
+// Inner loops load their factor entries in batches of LB from clamped,
+// always-valid addresses and mask the surplus entries to zero afterwards, so
+// that the loads of a batch are in flight together.
+constexpr int LB = 16;
+constexpr int SLB = 8;   // batch of the one-wavefront kernels of small fronts
+
+// Stage a ROWS x 64 tile of a front (column-major, leading dimension m) into
+// LDS as Lt[a + q * (ROWS + 1)]: rows r0 + a (a < nrow), columns c0 + q
+// (q < ncol), and only q < a when `strict`; everything else is zero.
+// nrow, ncol >= 1.
+template <typename T, int NT, int ROWS = 64>
+__device__ inline void stage_tile(double *Lt, const T *P, int m, int r0, int c0, int nrow, int ncol, bool strict,
+                                  int tid) {
+    constexpr int PER = ROWS * 64 / NT;
+    T val[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NT, a = idx % ROWS, q = idx / ROWS;
+        val[u] = P[(r0 + min(a, nrow - 1)) + (int64_t)(c0 + min(q, ncol - 1)) * m];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NT, a = idx % ROWS, q = idx / ROWS;
+        const bool ok = a < nrow && q < ncol && (!strict || q < a);
+        Lt[a + q * (ROWS + 1)] = ok ? (double)val[u] : 0.0;
+    }
+}
+
+// acc[r] += sum_{q < nq} P[q * m] * w[q * RBT + r] for one row (P points at
+// the row's entry in the first column); w is in LDS.
+template <typename T, int RBT, int NB = LB>
+__device__ inline void row_dot(const T *P, int64_t m, int nq, const double *w, double *acc) {
+    for (int q0 = 0; q0 < nq; q0 += NB) {
+        T l[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) l[u] = P[(int64_t)min(q0 + u, nq - 1) * m];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int q = min(q0 + u, nq - 1);
+            const double x = q0 + u < nq ? (double)l[u] : 0.0;
+#pragma unroll
+            for (int r = 0; r < RBT; ++r) acc[r] += x * w[q * RBT + r];
+        }
+    }
+}
+
+// Forward pass of a front larger than 64 rows, pivot part: extend-add of the
+// children's update vectors, then y = L11^-1 v over 64-column blocks with the
+// stored inverses of the pivot blocks. Rows below the pivots leave with the
+// children's contributions only; k_fwd_rect subtracts L21 y from them.
+template <typename T, int RBT>
+__global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
+                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
     extern __shared__ double smem[];
-    double *Lt = smem;             // 64 x 65 staging tile
-    double *v = smem + 64 * 65;
+    double *Lt = smem;                          // 64 x 65 staging tile, then 8 x 64 x RBT partial sums
+    double *v = smem + 64 * 65 + 8 * 64 * RBT;  // m x RBT
     const int s = tasks[blockIdx.x];
     const int n = blockIdx.y, tid = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
     const int32_t *R = tr.rows + tr.rowptr[s];
-    for (int k0r = 0; k0r < sa.nrhs; k0r += rb) {
-        const int nr = min(rb, (int)sa.nrhs - k0r);
+    const int64_t ro = tr.relptr[s];
+    for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
+        const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
         double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
-        for (int idx = tid; idx < m * rb; idx += SNT) {
-            const int i = idx / rb, r = idx % rb;
+        for (int idx = tid; idx < m * RBT; idx += SNT) {
+            const int i = idx / RBT, r = idx % RBT;
             v[idx] = (r < nr && i < c) ? x0[(int64_t)r * sa.nv + R[i]] : 0.0;
         }
         __syncthreads();
-        for (int q = tr.cptr[s]; q < tr.cptr[s + 1]; ++q) {
-            const int ch = tr.clist[q];
+        for (int qc = tr.cptr[s]; qc < tr.cptr[s + 1]; ++qc) {
+            const int ch = tr.clist[qc];
             const int uc = sd[ch].m - sd[ch].c;
             const int32_t *rl = tr.rel + tr.relptr[ch];
             for (int idx = tid; idx < uc * nr; idx += SNT) {
                 const int i = idx / nr, r = idx % nr;
-                v[rl[i] * rb + r] += U0[(int64_t)r * sa.usz + tr.relptr[ch] + i];
+                v[rl[i] * RBT + r] += U0[(int64_t)r * sa.usz + tr.relptr[ch] + i];
             }
             __syncthreads();
         }
+        // left-looking over 64-column blocks: v_b -= L[b, 0:k0] y[0:k0] (eight
+        // column groups of 32-column batches, reduced through LDS), then
+        // y_b = X_b v_b with the staged inverse of the pivot block
+        const int a = tid & 63, g = tid >> 6;
         for (int k0 = 0; k0 < c; k0 += 64) {
             const int nb = min(64, c - k0);
-            const int i = tid & 63, r = tid >> 6;
-            for (int idx = tid; idx < 64 * 64; idx += SNT) {
-                const int a = idx & 63, q = idx >> 6;
-                Lt[a + q * 65] = (q < a && a < nb) ? (double)P[(k0 + a) + (int64_t)(k0 + q) * m] : 0.0;
+            double acc[RBT];
+#pragma unroll
+            for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
+            const T *rowp = P + k0 + min(a, nb - 1);
+            for (int q0 = 32 * g; q0 < k0; q0 += 256) {
+                T l[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) l[u] = rowp[(int64_t)(q0 + u) * m];
+#pragma unroll
+                for (int u = 0; u < 32; ++u)
+#pragma unroll
+                    for (int rr = 0; rr < RBT; ++rr) acc[rr] += (double)l[u] * v[(q0 + u) * RBT + rr];
+            }
+#pragma unroll
+            for (int rr = 0; rr < RBT; ++rr) Lt[64 * 65 + (g * 64 + a) * RBT + rr] = acc[rr];
+            stage_tile<T, SNT>(Lt, P, m, k0, k0, nb, nb, true, tid);
+            __syncthreads();
+            if (g < nr && a < nb) {
+                double t = 0.0;
+#pragma unroll
+                for (int gg = 0; gg < 8; ++gg) t += Lt[64 * 65 + (gg * 64 + a) * RBT + g];
+                v[(k0 + a) * RBT + g] -= t;
             }
             __syncthreads();
             double yv = 0.0;
-            if (i < nb && r < nr) {
-                yv = v[(k0 + i) * rb + r];
-                for (int q = 0; q < i; ++q) yv += Lt[i + q * 65] * v[(k0 + q) * rb + r];
+            if (g < nr && a < nb) {
+                yv = v[(k0 + a) * RBT + g];
+                for (int q = 0; q < a; ++q) yv += Lt[a + q * 65] * v[(k0 + q) * RBT + g];
             }
             __syncthreads();
-            if (i < nb && r < nr) v[(k0 + i) * rb + r] = yv;
-            __syncthreads();
-            for (int i2 = k0 + nb + tid; i2 < m; i2 += SNT) {
-                double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-                for (int q = 0; q < nb; ++q) {
-                    const double l = (double)P[i2 + (int64_t)(k0 + q) * m];
-#pragma unroll
-                    for (int rr = 0; rr < RB; ++rr)
-                        if (rr < nr) acc[rr] += l * v[(k0 + q) * rb + rr];
-                }
-#pragma unroll
-                for (int rr = 0; rr < RB; ++rr)
-                    if (rr < nr) v[i2 * rb + rr] -= acc[rr];
-            }
+            if (g < nr && a < nb) v[(k0 + a) * RBT + g] = yv;
             __syncthreads();
         }
         for (int idx = tid; idx < m * nr; idx += SNT) {
             const int i = idx / nr, r = idx % nr;
-            if (i < c) x0[(int64_t)r * sa.nv + R[i]] = v[i * rb + r];
-            else U0[(int64_t)r * sa.usz + tr.relptr[s] + (i - c)] = v[i * rb + r];
+            if (i < c) x0[(int64_t)r * sa.nv + R[i]] = v[i * RBT + r];
+            else U0[(int64_t)r * sa.usz + ro + (i - c)] = v[i * RBT + r];
         }
         __syncthreads();
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(SNT) void k_bwd(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks,
-                                             TreeArgs tr, SolveArgs sa, int rb) {
+// Forward pass, rows below the pivots: u -= L21 y for 64 update rows of a
+// front per workgroup (four column groups, reduced at the end).
+template <typename T, int RBT>
+__global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd,
+                                                  const RowTask *tasks, TreeArgs tr, SolveArgs sa) {
+    __shared__ double yb[256 * RBT];
+    __shared__ double red[4 * 64 * RBT];
+    const RowTask tk = tasks[blockIdx.x];
+    const int s = tk.f, i0 = tk.r0;
+    const int n = blockIdx.y, tid = threadIdx.x;
+    const FrontDesc d = sd[s];
+    const int m = d.m, c = d.c;
+    const T *P = L + (int64_t)n * Lstride + d.Loff;
+    const int32_t *R = tr.rows + tr.rowptr[s];
+    const int64_t ro = tr.relptr[s];
+    const int a = tid & 63, g = tid >> 6;
+    const int i = i0 + a;
+    const T *rowp = P + min(i, m - 1);
+    for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
+        const int nr = min(RBT, (int)sa.nrhs - k0r);
+        const double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
+        double acc[RBT];
+#pragma unroll
+        for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
+        for (int q0 = 0; q0 < c; q0 += 256) {
+            const int nq = min(256, c - q0);
+            for (int idx = tid; idx < 256 * RBT; idx += 256) {
+                const int q = idx / RBT, r = idx % RBT;
+                yb[idx] = (q < nq && r < nr) ? x0[(int64_t)r * sa.nv + R[q0 + q]] : 0.0;
+            }
+            __syncthreads();
+            const int qa = 64 * g;
+            if (qa < nq) row_dot<T, RBT>(rowp + (int64_t)(q0 + qa) * m, m, min(64, nq - qa), yb + qa * RBT, acc);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int rr = 0; rr < RBT; ++rr) red[(g * 64 + a) * RBT + rr] = acc[rr];
+        __syncthreads();
+        if (g == 0 && i < m) {
+            for (int rr = 0; rr < nr; ++rr) {
+                const double t = red[(0 * 64 + a) * RBT + rr] + red[(1 * 64 + a) * RBT + rr] +
+                                 red[(2 * 64 + a) * RBT + rr] + red[(3 * 64 + a) * RBT + rr];
+                U0[(int64_t)rr * sa.usz + ro + (i - c)] -= t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Backward pass, rows below the pivots: for 64 pivot columns per workgroup,
+// z = D^-1 v - L21^T x_below with x_below the ancestors' final values (L
+// tiles staged through LDS so that global reads run down the columns). z
+// replaces v in place; k_bwd_tri finishes with L11^T.
+template <typename T, int RBT>
+__global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd,
+                                                  const RowTask *tasks, TreeArgs tr, SolveArgs sa) {
+    __shared__ double Lt[64 * 65];
+    __shared__ double xb[64 * RBT];
+    __shared__ double red[4 * 64 * RBT];
+    const RowTask tk = tasks[blockIdx.x];
+    const int s = tk.f, q0 = tk.r0;
+    const int n = blockIdx.y, tid = threadIdx.x;
+    const FrontDesc d = sd[s];
+    const int m = d.m, c = d.c;
+    if (m == c) return;
+    const T *P = L + (int64_t)n * Lstride + d.Loff;
+    const int32_t *R = tr.rows + tr.rowptr[s];
+    const int q = tid & 63, g = tid >> 6;
+    const int ncol = min(64, c - q0);
+    for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
+        const int nr = min(RBT, (int)sa.nrhs - k0r);
+        double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        double acc[RBT];
+#pragma unroll
+        for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
+        for (int ib = c; ib < m; ib += 64) {
+            const int nrow = min(64, m - ib);
+            stage_tile<T, 256>(Lt, P, m, ib, q0, nrow, ncol, false, tid);
+            for (int idx = tid; idx < 64 * RBT; idx += 256) {
+                const int a = idx / RBT, r = idx % RBT;
+                xb[idx] = (a < nrow && r < nr) ? x0[(int64_t)r * sa.nv + R[ib + a]] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 16 * g; a < 16 * g + 16; ++a) {
+                const double l = Lt[a + q * 65];
+#pragma unroll
+                for (int rr = 0; rr < RBT; ++rr) acc[rr] += l * xb[a * RBT + rr];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int rr = 0; rr < RBT; ++rr) red[(g * 64 + q) * RBT + rr] = acc[rr];
+        __syncthreads();
+        if (g == 0 && q < ncol) {
+            const double dq = (double)P[(q0 + q) + (int64_t)(q0 + q) * m];
+            for (int rr = 0; rr < nr; ++rr) {
+                const double t = red[(0 * 64 + q) * RBT + rr] + red[(1 * 64 + q) * RBT + rr] +
+                                 red[(2 * 64 + q) * RBT + rr] + red[(3 * 64 + q) * RBT + rr];
+                double *xp = x0 + (int64_t)rr * sa.nv + R[q0 + q];
+                *xp = *xp / dq - t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Backward pass of a front larger than 64 rows, pivot part: left-looking over
+// 64-column blocks from the last, z_b -= L[below b, b]^T x (rows < c only),
+// then x_b = X_b^T z_b with X_b the stored inverse of the pivot block. The
+// division by D and the rows below the pivots were applied by k_bwd_rect,
+// except for fronts without such rows.
+template <typename T, int RBT>
+__global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
+                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
     extern __shared__ double smem[];
-    double *Lt = smem;             // 64 x 65 staging tile
-    double *v = smem + 64 * 65;
+    double *Lt = smem;                 // 128 x 64 staging tile (ld 129)
+    double *red = smem + 129 * 64;     // 8 groups x 64 columns x RBT partial sums
+    double *v = red + 8 * 64 * RBT;    // c x RBT
     const int s = tasks[blockIdx.x];
     const int n = blockIdx.y, tid = threadIdx.x;
     const FrontDesc d = sd[s];
@@ -113,70 +287,199 @@ __global__ __launch_bounds__(SNT) void k_bwd(const T *L, int64_t Lstride, const 
     if (c == 0) return;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
     const int32_t *R = tr.rows + tr.rowptr[s];
-    for (int k0r = 0; k0r < sa.nrhs; k0r += rb) {
-        const int nr = min(rb, (int)sa.nrhs - k0r);
+    const int q = tid & 63, g = tid >> 6;
+    const bool divide = m == c;
+    for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
+        const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
-        for (int idx = tid; idx < m * rb; idx += SNT) {
-            const int i = idx / rb, r = idx % rb;
+        for (int idx = tid; idx < c * RBT; idx += SNT) {
+            const int i = idx / RBT, r = idx % RBT;
             double val = 0.0;
             if (r < nr) {
                 val = x0[(int64_t)r * sa.nv + R[i]];
-                if (i < c) val /= (double)P[i + (int64_t)i * m];
+                if (divide) val /= (double)P[i + (int64_t)i * m];
             }
             v[idx] = val;
         }
         __syncthreads();
-        // contributions of the update rows (ancestors' final values)
-        for (int q = tid; q < c; q += SNT) {
-            double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-            const T *col = P + (int64_t)q * m;
-#pragma unroll 8
-            for (int i = c; i < m; ++i) {
-                const double l = (double)col[i];
-#pragma unroll
-                for (int rr = 0; rr < RB; ++rr)
-                    if (rr < nr) acc[rr] += l * v[i * rb + rr];
-            }
-#pragma unroll
-            for (int rr = 0; rr < RB; ++rr)
-                if (rr < nr) v[q * rb + rr] -= acc[rr];
-        }
-        __syncthreads();
         for (int kb = ((c - 1) / 64) * 64; kb >= 0; kb -= 64) {
             const int nb = min(64, c - kb);
-            const int q = tid & 63, r = tid >> 6;
-            for (int idx = tid; idx < 64 * 64; idx += SNT) {
-                const int a = idx & 63, qq = idx >> 6;
-                Lt[a + qq * 65] = (qq < a && a < nb) ? (double)P[(kb + a) + (int64_t)(kb + qq) * m] : 0.0;
+            double acc[RBT];
+#pragma unroll
+            for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
+            for (int ib = kb + nb; ib < c; ib += 128) {
+                const int nrow = min(128, c - ib);
+                stage_tile<T, SNT, 128>(Lt, P, m, ib, kb, nrow, nb, false, tid);
+                __syncthreads();
+                const int a1 = min(16 * g + 16, nrow);
+                for (int a = 16 * g; a < a1; ++a) {
+                    const double l = Lt[a + q * 129];
+#pragma unroll
+                    for (int rr = 0; rr < RBT; ++rr) acc[rr] += l * v[(ib + a) * RBT + rr];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int rr = 0; rr < RBT; ++rr) red[(g * 64 + q) * RBT + rr] = acc[rr];
+            stage_tile<T, SNT>(Lt, P, m, kb, kb, nb, nb, true, tid);
+            __syncthreads();
+            if (g < nr && q < nb) {
+                double t = 0.0;
+#pragma unroll
+                for (int gg = 0; gg < 8; ++gg) t += red[(gg * 64 + q) * RBT + g];
+                v[(kb + q) * RBT + g] -= t;
             }
             __syncthreads();
             double xv = 0.0;
-            if (q < nb && r < nr) {
-                xv = v[(kb + q) * rb + r];
-                for (int i = q + 1; i < nb; ++i) xv += Lt[i + q * 65] * v[(kb + i) * rb + r];
+            if (g < nr && q < nb) {
+                xv = v[(kb + q) * RBT + g];
+                for (int i = q + 1; i < nb; ++i) xv += Lt[i + q * 65] * v[(kb + i) * RBT + g];
             }
             __syncthreads();
-            if (q < nb && r < nr) v[(kb + q) * rb + r] = xv;
-            __syncthreads();
-            for (int q2 = tid; q2 < kb; q2 += SNT) {
-                double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-                const T *col = P + (int64_t)q2 * m + kb;
-#pragma unroll 8
-                for (int i = 0; i < nb; ++i) {
-                    const double l = (double)col[i];
-#pragma unroll
-                    for (int rr = 0; rr < RB; ++rr)
-                        if (rr < nr) acc[rr] += l * v[(kb + i) * rb + rr];
-                }
-#pragma unroll
-                for (int rr = 0; rr < RB; ++rr)
-                    if (rr < nr) v[q2 * rb + rr] -= acc[rr];
-            }
+            if (g < nr && q < nb) v[(kb + q) * RBT + g] = xv;
             __syncthreads();
         }
         for (int idx = tid; idx < c * nr; idx += SNT) {
             const int i = idx / nr, r = idx % nr;
-            x0[(int64_t)r * sa.nv + R[i]] = v[i * rb + r];
+            x0[(int64_t)r * sa.nv + R[i]] = v[i * RBT + r];
+        }
+        __syncthreads();
+    }
+}
+
+// Fronts of at most 64 rows: one wavefront per front, lane i owns row i
+// (forward) or pivot column i (backward).
+template <typename T>
+__global__ __launch_bounds__(64) void k_fwd_small(const T *L, int64_t Lstride, const FrontDesc *sd,
+                                                  const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
+    __shared__ double vs[64 * RB];
+    const int s = tasks[blockIdx.x];
+    const int n = blockIdx.y, i = threadIdx.x;
+    const FrontDesc d = sd[s];
+    const int m = d.m, c = d.c;
+    const T *P = L + (int64_t)n * Lstride + d.Loff;
+    const T *rowp = P + min(i, m - 1);
+    const int32_t *R = tr.rows + tr.rowptr[s];
+    const int64_t ro = tr.relptr[s];
+    for (int k0r = 0; k0r < sa.nrhs; k0r += RB) {
+        const int nr = min(RB, (int)sa.nrhs - k0r);
+        double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
+        const int32_t Ri = i < c ? R[i] : 0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) vs[i * RB + r] = (i < c && r < nr) ? x0[(int64_t)r * sa.nv + Ri] : 0.0;
+        __syncthreads();
+        for (int qc = tr.cptr[s]; qc < tr.cptr[s + 1]; ++qc) {
+            const int ch = tr.clist[qc];
+            const int uc = sd[ch].m - sd[ch].c;
+            if (i < uc) {
+                const int row = tr.rel[tr.relptr[ch] + i];
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (r < nr) vs[row * RB + r] += U0[(int64_t)r * sa.usz + tr.relptr[ch] + i];
+            }
+            __syncthreads();
+        }
+        // y = X v on the pivot rows (X[i][q] for q < i)
+        double y[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) y[r] = vs[i * RB + r];
+        for (int q0 = 0; q0 < c; q0 += SLB) {
+            T l[SLB];
+#pragma unroll
+            for (int u = 0; u < SLB; ++u) l[u] = rowp[(int64_t)min(q0 + u, c - 1) * m];
+#pragma unroll
+            for (int u = 0; u < SLB; ++u) {
+                const int q = min(q0 + u, c - 1);
+                const double x = (q0 + u < i && i < c) ? (double)l[u] : 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) y[r] += x * vs[q * RB + r];
+            }
+        }
+        __syncthreads();
+        if (i < c) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) vs[i * RB + r] = y[r];
+        }
+        __syncthreads();
+        // update rows: u -= L21 y
+        if (i >= c) {
+            double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+            row_dot<T, RB, SLB>(rowp, m, c, vs, acc);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) y[r] -= acc[r];
+        }
+        if (i < m) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if (r >= nr) continue;
+                if (i < c) x0[(int64_t)r * sa.nv + Ri] = y[r];
+                else U0[(int64_t)r * sa.usz + ro + (i - c)] = y[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_bwd_small(const T *L, int64_t Lstride, const FrontDesc *sd,
+                                                  const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
+    __shared__ double vs[64 * RB];
+    const int s = tasks[blockIdx.x];
+    const int n = blockIdx.y, i = threadIdx.x;
+    const FrontDesc d = sd[s];
+    const int m = d.m, c = d.c;
+    if (c == 0) return;
+    const T *P = L + (int64_t)n * Lstride + d.Loff;
+    const T *col = P + (int64_t)min(i, c - 1) * m;   // pivot column of lane i
+    const int32_t *R = tr.rows + tr.rowptr[s];
+    for (int k0r = 0; k0r < sa.nrhs; k0r += RB) {
+        const int nr = min(RB, (int)sa.nrhs - k0r);
+        double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        const int32_t Ri = i < m ? R[i] : 0;
+        const double dd = i < c ? (double)P[i + (int64_t)i * m] : 1.0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) vs[i * RB + r] = (i < m && r < nr) ? x0[(int64_t)r * sa.nv + Ri] / dd : 0.0;
+        __syncthreads();
+        // z = D^-1 v - L21^T x_below
+        double z[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) z[r] = vs[i * RB + r];
+        for (int j0 = c; j0 < m; j0 += SLB) {
+            T l[SLB];
+#pragma unroll
+            for (int u = 0; u < SLB; ++u) l[u] = col[min(j0 + u, m - 1)];
+#pragma unroll
+            for (int u = 0; u < SLB; ++u) {
+                const int j = min(j0 + u, m - 1);
+                const double x = j0 + u < m ? (double)l[u] : 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) z[r] -= x * vs[j * RB + r];
+            }
+        }
+        __syncthreads();
+        if (i < c) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) vs[i * RB + r] = z[r];
+        }
+        __syncthreads();
+        // x = X^T z on the pivot block (X[j][i] for j > i)
+        for (int j0 = 0; j0 < c; j0 += SLB) {
+            T l[SLB];
+#pragma unroll
+            for (int u = 0; u < SLB; ++u) l[u] = col[min(j0 + u, c - 1)];
+#pragma unroll
+            for (int u = 0; u < SLB; ++u) {
+                const int j = min(j0 + u, c - 1);
+                const double x = (j0 + u > i && j0 + u < c) ? (double)l[u] : 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) z[r] += x * vs[j * RB + r];
+            }
+        }
+        if (i < c) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (r < nr) x0[(int64_t)r * sa.nv + Ri] = z[r];
         }
         __syncthreads();
     }
@@ -223,38 +526,97 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
 }
 
 // ---- dense Schur factor solves ----------------------------------------------
-// The factor of S keeps D on its diagonal, L^-1 of every 64x64 diagonal block
-// below the diagonal of that block, and L elsewhere below the diagonal. Steps
-// go over 256-row blocks; every workgroup of a step redoes the small in-block
-// solve and then updates its own 256 rows (forward) or columns (backward).
+// The factor of S (column-major, ld ng) keeps D on its diagonal, the inverse
+// X_J of every unit lower 256x256 diagonal block J strictly below that
+// block's diagonal, and L elsewhere strictly below the diagonal; after the
+// factorisation the strict lower triangle is mirrored into the strict upper
+// one, so that both L (forward) and L^T (backward) are read down columns.
+// Steps go over 256-wide blocks: forward y_J = X_J v_J then v_below -=
+// L[below, J] y_J; backward x_J = X_J^T z_J then z_above -= L[J, above]^T x_J.
 constexpr int DBW = 256;
 
-// The factor of S keeps L^-1 of every 256x256 diagonal block below that
-// block's diagonal. y[j0:j0+nbw) = X v[j0:j0+nbw) with X unit lower: 16 rows
-// per workgroup, 16 partial sums per row.
-__global__ __launch_bounds__(256) void k_dense_yblk(const double *S, int64_t ng, const double *v, double *y, int nrhs,
-                                                    int64_t j0) {
+// out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow:
+// 64 rows per workgroup, four groups of 64 columns, reduced at the end. All
+// global loads of a workgroup are issued before the first use.
+__global__ __launch_bounds__(256) void k_dense_gemv(const double *S, int64_t ng, int64_t row0, int64_t nrow,
+                                                    int64_t col0, int ncol, const double *w, double *out, int nrhs) {
+    __shared__ double wb[DBW * RB];
+    __shared__ double red[4 * 64 * RB];
+    const int tid = threadIdx.x;
+    const int a = tid & 63, g = tid >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + a;
+    const int qa = 64 * g;
+    const int ncq = max(1, min(64, ncol - qa));
+    const double *rowp = S + row0 + min(i, nrow - 1) + (col0 + qa) * ng;
+    double l[64];
+#pragma unroll
+    for (int u = 0; u < 64; ++u) l[u] = rowp[(int64_t)min(u, ncq - 1) * ng];
+    for (int k0r = 0; k0r < nrhs; k0r += RB) {
+        const int nr = min(RB, nrhs - k0r);
+        double o[RB] = {0.0, 0.0, 0.0, 0.0};
+        if (g == 0 && i < nrow)
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr)
+                if (rr < nr) o[rr] = out[(int64_t)(k0r + rr) * ng + row0 + i];
+        for (int idx = tid; idx < DBW * RB; idx += 256) {
+            const int q = idx / RB, r = idx % RB;
+            wb[idx] = (q < ncol && r < nr) ? w[(int64_t)(k0r + r) * ng + q] : 0.0;
+        }
+        __syncthreads();
+        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
+        if (qa < ncol) {
+#pragma unroll
+            for (int u = 0; u < 64; ++u) {
+                const double x = u < ncq ? l[u] : 0.0;
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) acc[rr] += x * wb[(qa + min(u, ncq - 1)) * RB + rr];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) red[(g * 64 + a) * RB + rr] = acc[rr];
+        __syncthreads();
+        if (g == 0 && i < nrow)
+            for (int rr = 0; rr < nr; ++rr) {
+                const double t = red[(0 * 64 + a) * RB + rr] + red[(1 * 64 + a) * RB + rr] +
+                                 red[(2 * 64 + a) * RB + rr] + red[(3 * 64 + a) * RB + rr];
+                out[(int64_t)(k0r + rr) * ng + row0 + i] = o[rr] - t;
+            }
+        __syncthreads();
+    }
+}
+
+// In-block product with the stored inverse of diagonal block [j0, j0 + nbw):
+// out[j0 + i] = in[j0 + i] + sum_q M[i][q] in[j0 + q] with M = X_J (lower,
+// q < i) or X_J^T read from the mirrored upper triangle (upper, q > i).
+// 16 rows per workgroup, 16 groups of 16 columns.
+__global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, int64_t j0, const double *in,
+                                                   double *out, int nrhs, int upper) {
     __shared__ double vb[DBW * RB];
     __shared__ double red[16 * 16 * RB];
     const int tid = threadIdx.x;
     const int nbw = (int)min((int64_t)DBW, ng - j0);
-    const int rl = tid & 15, g = tid >> 4;          // row in tile, column group
-    const int i = blockIdx.x * 16 + rl;             // row in block
+    const int rl = tid & 15, g = tid >> 4;
+    const int i = blockIdx.x * 16 + rl;
+    const int q0 = min(16 * g, nbw - 1);
+    const double *rowp = S + j0 + min(i, nbw - 1) + (j0 + q0) * ng;
+    double l[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) l[u] = rowp[(int64_t)min(u, nbw - 1 - q0) * ng];
     for (int k0r = 0; k0r < nrhs; k0r += RB) {
         const int nr = min(RB, nrhs - k0r);
-        for (int idx = tid; idx < nbw * RB; idx += 256) {
+        for (int idx = tid; idx < DBW * RB; idx += 256) {
             const int q = idx / RB, r = idx % RB;
-            vb[idx] = r < nr ? v[(int64_t)(k0r + r) * ng + j0 + q] : 0.0;
+            vb[idx] = (q < nbw && r < nr) ? in[(int64_t)(k0r + r) * ng + j0 + q] : 0.0;
         }
         __syncthreads();
         double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-        if (i < nbw) {
-            const double *row = S + (j0 + i);
-            for (int q = g; q < i; q += 16) {
-                const double l = row[(j0 + q) * ng];
 #pragma unroll
-                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * vb[q * RB + rr];
-            }
+        for (int u = 0; u < 16; ++u) {
+            const int q = 16 * g + u;
+            const bool ok = q < nbw && (upper ? q > i : q < i);
+            const double x = ok ? l[u] : 0.0;
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) acc[rr] += x * vb[min(q, DBW - 1) * RB + rr];
         }
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) red[(g * 16 + rl) * RB + rr] = acc[rr];
@@ -262,48 +624,9 @@ __global__ __launch_bounds__(256) void k_dense_yblk(const double *S, int64_t ng,
         if (g == 0 && i < nbw)
             for (int rr = 0; rr < nr; ++rr) {
                 double t = vb[i * RB + rr];
+#pragma unroll
                 for (int gg = 0; gg < 16; ++gg) t += red[(gg * 16 + rl) * RB + rr];
-                y[(int64_t)(k0r + rr) * ng + j0 + i] = t;
-            }
-        __syncthreads();
-    }
-}
-
-// rows below the block: v[i] -= L[i, j0:j0+nbw] y[j0:j0+nbw], 64 rows per
-// workgroup, four partial sums per row
-__global__ __launch_bounds__(256) void k_dense_rows_fwd(const double *S, int64_t ng, double *v, const double *y,
-                                                        int nrhs, int64_t j0) {
-    __shared__ double yb[DBW * RB];
-    __shared__ double red[4 * 64 * RB];
-    const int tid = threadIdx.x;
-    const int nbw = (int)min((int64_t)DBW, ng - j0);
-    const int row = tid & 63, g = tid >> 6;
-    const int64_t i = j0 + nbw + (int64_t)blockIdx.x * 64 + row;
-    for (int k0r = 0; k0r < nrhs; k0r += RB) {
-        const int nr = min(RB, nrhs - k0r);
-        for (int idx = tid; idx < nbw * RB; idx += 256) {
-            const int q = idx / RB, r = idx % RB;
-            yb[idx] = r < nr ? y[(int64_t)(k0r + r) * ng + j0 + q] : 0.0;
-        }
-        __syncthreads();
-        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-        if (i < ng) {
-            const int qlo = 64 * g, qhi = min(nbw, qlo + 64);
-#pragma unroll 8
-            for (int q = qlo; q < qhi; ++q) {
-                const double l = S[i + (j0 + q) * ng];
-#pragma unroll
-                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * yb[q * RB + rr];
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) red[(g * 64 + row) * RB + rr] = acc[rr];
-        __syncthreads();
-        if (g == 0 && i < ng)
-            for (int rr = 0; rr < nr; ++rr) {
-                const double t = red[(0 * 64 + row) * RB + rr] + red[(1 * 64 + row) * RB + rr] +
-                                 red[(2 * 64 + row) * RB + rr] + red[(3 * 64 + row) * RB + rr];
-                v[(int64_t)(k0r + rr) * ng + i] -= t;
+                out[(int64_t)(k0r + rr) * ng + j0 + i] = t;
             }
         __syncthreads();
     }
@@ -316,85 +639,6 @@ __global__ void k_div_diag(const double *S, int64_t ng, const double *y, double 
     for (int k = 0; k < nrhs; ++k) z[(int64_t)k * ng + i] = y[(int64_t)k * ng + i] / dd;
 }
 
-// x[j0:j0+nbw) = X^T z[j0:j0+nbw): 16 columns per workgroup, 16 partial sums
-__global__ __launch_bounds__(256) void k_dense_xblk(const double *S, int64_t ng, const double *z, double *x, int nrhs,
-                                                    int64_t j0) {
-    __shared__ double zb[DBW * RB];
-    __shared__ double red[16 * 16 * RB];
-    const int tid = threadIdx.x;
-    const int nbw = (int)min((int64_t)DBW, ng - j0);
-    const int cl = tid & 15, g = tid >> 4;
-    const int q = blockIdx.x * 16 + cl;
-    for (int k0r = 0; k0r < nrhs; k0r += RB) {
-        const int nr = min(RB, nrhs - k0r);
-        for (int idx = tid; idx < nbw * RB; idx += 256) {
-            const int i = idx / RB, r = idx % RB;
-            zb[idx] = r < nr ? z[(int64_t)(k0r + r) * ng + j0 + i] : 0.0;
-        }
-        __syncthreads();
-        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-        if (q < nbw) {
-            const double *col = S + j0 + (j0 + q) * ng;
-            for (int i = q + 1 + g; i < nbw; i += 16) {
-                const double l = col[i];
-#pragma unroll
-                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * zb[i * RB + rr];
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) red[(g * 16 + cl) * RB + rr] = acc[rr];
-        __syncthreads();
-        if (g == 0 && q < nbw)
-            for (int rr = 0; rr < nr; ++rr) {
-                double t = zb[q * RB + rr];
-                for (int gg = 0; gg < 16; ++gg) t += red[(gg * 16 + cl) * RB + rr];
-                x[(int64_t)(k0r + rr) * ng + j0 + q] = t;
-            }
-        __syncthreads();
-    }
-}
-
-// columns before the block: z[q] -= L[j0:j0+nbw, q]^T x[j0:j0+nbw], 64
-// columns per workgroup, four partial sums per column
-__global__ __launch_bounds__(256) void k_dense_cols_bwd(const double *S, int64_t ng, double *z, const double *x,
-                                                        int nrhs, int64_t j0) {
-    __shared__ double xb[DBW * RB];
-    __shared__ double red[4 * 64 * RB];
-    const int tid = threadIdx.x;
-    const int nbw = (int)min((int64_t)DBW, ng - j0);
-    const int cl = tid & 63, g = tid >> 6;
-    const int64_t q = (int64_t)blockIdx.x * 64 + cl;
-    for (int k0r = 0; k0r < nrhs; k0r += RB) {
-        const int nr = min(RB, nrhs - k0r);
-        for (int idx = tid; idx < nbw * RB; idx += 256) {
-            const int i = idx / RB, r = idx % RB;
-            xb[idx] = r < nr ? x[(int64_t)(k0r + r) * ng + j0 + i] : 0.0;
-        }
-        __syncthreads();
-        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-        if (q < j0) {
-            const int ilo = 64 * g, ihi = min(nbw, ilo + 64);
-            const double *col = S + j0 + q * ng;
-#pragma unroll 8
-            for (int i = ilo; i < ihi; ++i) {
-                const double l = col[i];
-#pragma unroll
-                for (int rr = 0; rr < RB; ++rr) acc[rr] += l * xb[i * RB + rr];
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) red[(g * 64 + cl) * RB + rr] = acc[rr];
-        __syncthreads();
-        if (g == 0 && q < j0)
-            for (int rr = 0; rr < nr; ++rr) {
-                const double t = red[(0 * 64 + cl) * RB + rr] + red[(1 * 64 + cl) * RB + rr] +
-                                 red[(2 * 64 + cl) * RB + rr] + red[(3 * 64 + cl) * RB + rr];
-                z[(int64_t)(k0r + rr) * ng + q] -= t;
-            }
-        __syncthreads();
-    }
-}
-
 // ---- launchers ---------------------------------------------------------------
 template <typename T>
 void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa,
@@ -403,31 +647,77 @@ void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t 
                        dim3(256), 0, st, b, ntot, nA, perm, sa);
 }
 
-static int rhs_block(int64_t nrhs, int maxm) {
+// right-hand sides per pass of a kernel whose LDS holds `rows` x RBT doubles
+// beside `fixed` bytes
+static int rhs_block(int64_t nrhs, int rows, size_t fixed) {
     int rb = (int)std::min<int64_t>(nrhs, RB);
-    while (rb > 1 && (int64_t)maxm * rb * 8 > 96 * 1024) --rb;
+    if (rb == 3) rb = 4;
+    while (rb > 1 && (size_t)rows * rb * 8 + fixed > 150 * 1024) rb /= 2;
     return rb;
 }
-static size_t front_lds(int maxm, int rb) { return sizeof(double) * ((size_t)maxm * rb + 64 * 65); }
 
-template <typename T>
-void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
-                      const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
-    if (ntasks <= 0) return;
-    const int rb = rhs_block(sa.nrhs, maxm);
-    const size_t lds = front_lds(maxm, rb);
-    if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_fwd<T>, dim3(ntasks, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, tasks, tr, sa, rb);
+template <typename T, int RBT>
+static void fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *large, int nlarge, int maxm,
+                    const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+    const size_t lds = sizeof(double) * ((size_t)maxm * RBT + 64 * 65 + 8 * 64 * RBT);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_fwd_tri<T, RBT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_fwd_tri<T, RBT>), dim3(nlarge, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, large,
+                       tr, sa);
+}
+
+template <typename T, int RBT>
+static void bwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *large, int nlarge, int maxc,
+                    const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+    const size_t lds = sizeof(double) * ((size_t)maxc * RBT + 129 * 64 + 8 * 64 * RBT);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_bwd_tri<T, RBT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_bwd_tri<T, RBT>), dim3(nlarge, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, large,
+                       tr, sa);
 }
 
 template <typename T>
-void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
-                      const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
-    if (ntasks <= 0) return;
-    const int rb = rhs_block(sa.nrhs, maxm);
-    const size_t lds = front_lds(maxm, rb);
-    if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_bwd<T>, dim3(ntasks, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, tasks, tr, sa, rb);
+void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
+                      SolveArgs sa, hipStream_t st) {
+    if (lt.nsmall > 0)
+        hipLaunchKernelGGL(k_fwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
+                           tr, sa);
+    if (lt.nlarge <= 0) return;
+    const int rb = rhs_block(sa.nrhs, lt.maxm, sizeof(double) * (64 * 65 + 8 * 64 * RB));
+    if (rb == 4) fwd_tri<T, 4>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
+    else if (rb == 2) fwd_tri<T, 2>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
+    else fwd_tri<T, 1>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
+    if (lt.nrect_rows > 0) {
+        const dim3 g(lt.nrect_rows, (unsigned)sa.N);
+        if (sa.nrhs >= 3)
+            hipLaunchKernelGGL((k_fwd_rect<T, 4>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_rows, tr, sa);
+        else if (sa.nrhs >= 2)
+            hipLaunchKernelGGL((k_fwd_rect<T, 2>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_rows, tr, sa);
+        else
+            hipLaunchKernelGGL((k_fwd_rect<T, 1>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_rows, tr, sa);
+    }
+}
+
+template <typename T>
+void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
+                      SolveArgs sa, hipStream_t st) {
+    if (lt.nsmall > 0)
+        hipLaunchKernelGGL(k_bwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
+                           tr, sa);
+    if (lt.nlarge <= 0) return;
+    if (lt.nrect_cols > 0) {
+        const dim3 g(lt.nrect_cols, (unsigned)sa.N);
+        if (sa.nrhs >= 3)
+            hipLaunchKernelGGL((k_bwd_rect<T, 4>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_cols, tr, sa);
+        else if (sa.nrhs >= 2)
+            hipLaunchKernelGGL((k_bwd_rect<T, 2>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_cols, tr, sa);
+        else
+            hipLaunchKernelGGL((k_bwd_rect<T, 1>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_cols, tr, sa);
+    }
+    const int rb = rhs_block(sa.nrhs, lt.maxc, sizeof(double) * (129 * 64 + 8 * 64 * RB));
+    if (rb == 4) bwd_tri<T, 4>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, tr, sa, st);
+    else if (rb == 2) bwd_tri<T, 2>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, tr, sa, st);
+    else bwd_tri<T, 1>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, tr, sa, st);
 }
 
 void launch_scatter_x(double *x, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa, const double *xg,
@@ -451,12 +741,12 @@ void launch_border_values(const double *xg, SolveArgs sa, int64_t nA, int64_t Ns
 void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st) {
     for (int64_t j0 = 0; j0 < ng; j0 += DBW) {
         const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
-        hipLaunchKernelGGL(k_dense_yblk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, v, y, (int)nrhs,
-                           j0);
-        const int64_t below = ng - j0 - DBW;
+        hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, j0,
+                           (const double *)v, y, (int)nrhs, 0);
+        const int64_t below = ng - j0 - nbw;
         if (below > 0)
-            hipLaunchKernelGGL(k_dense_rows_fwd, dim3((unsigned)((below + 63) / 64)), dim3(256), 0, st, S, ng, v, y,
-                               (int)nrhs, j0);
+            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((below + 63) / 64)), dim3(256), 0, st, S, ng, j0 + nbw,
+                               below, j0, (int)nbw, (const double *)(y + j0), v, (int)nrhs);
     }
 }
 
@@ -464,20 +754,20 @@ void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t
     hipLaunchKernelGGL(k_div_diag, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, S, ng, z, z, (int)nrhs);
     for (int64_t j0 = ((ng - 1) / DBW) * DBW; j0 >= 0; j0 -= DBW) {
         const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
-        hipLaunchKernelGGL(k_dense_xblk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, z, x, (int)nrhs,
-                           j0);
+        hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, j0,
+                           (const double *)z, x, (int)nrhs, 1);
         if (j0 > 0)
-            hipLaunchKernelGGL(k_dense_cols_bwd, dim3((unsigned)((j0 + 63) / 64)), dim3(256), 0, st, S, ng, z, x,
-                               (int)nrhs, j0);
+            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((j0 + 63) / 64)), dim3(256), 0, st, S, ng, (int64_t)0,
+                               j0, j0, (int)nbw, (const double *)(x + j0), z, (int)nrhs);
     }
 }
 
 template void launch_gather_rhs<double>(const double *, int64_t, int64_t, const int32_t *, SolveArgs, hipStream_t);
 template void launch_gather_rhs<float>(const double *, int64_t, int64_t, const int32_t *, SolveArgs, hipStream_t);
 #define KKT_SOLVE_INST(T)                                                                                   \
-    template void launch_fwd_level<T>(const T *, int64_t, const FrontDesc *, const int32_t *, int, int,     \
+    template void launch_fwd_level<T>(const T *, int64_t, const FrontDesc *, const LevelTasks &,            \
                                       const TreeArgs &, SolveArgs, hipStream_t);                            \
-    template void launch_bwd_level<T>(const T *, int64_t, const FrontDesc *, const int32_t *, int, int,     \
+    template void launch_bwd_level<T>(const T *, int64_t, const FrontDesc *, const LevelTasks &,            \
                                       const TreeArgs &, SolveArgs, hipStream_t);
 KKT_SOLVE_INST(double)
 KKT_SOLVE_INST(float)

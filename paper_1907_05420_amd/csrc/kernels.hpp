@@ -69,12 +69,22 @@ struct SolveArgs {
 template <typename T>
 void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa,
                        hipStream_t st);
+// device task lists of one level for the solve kernels
+struct LevelTasks {
+    const int32_t *small;        // fronts of at most 64 rows
+    const int32_t *large;        // the others
+    const RowTask *rect_rows;    // (front, first row) of 64 update rows of large fronts
+    const RowTask *rect_cols;    // (front, first column) of 64 pivot columns of large fronts
+    int nsmall, nlarge, nrect_rows, nrect_cols;
+    int maxm, maxc;              // largest rows / pivots of the large fronts
+};
+
 template <typename T>
-void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
-                      const TreeArgs &tr, SolveArgs sa, hipStream_t st);
+void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
+                      SolveArgs sa, hipStream_t st);
 template <typename T>
-void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *tasks, int ntasks, int maxm,
-                      const TreeArgs &tr, SolveArgs sa, hipStream_t st);
+void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
+                      SolveArgs sa, hipStream_t st);
 void launch_scatter_x(double *x, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa, const double *xg,
                       int64_t ng, hipStream_t st);
 // border glue: rhs of the Schur system and the border values for the backward pass
@@ -90,6 +100,7 @@ void launch_schur_assemble(const void *U, int64_t Ustride, int64_t uoff, int64_t
                            double *amax_s, int mirror, hipStream_t st);
 void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t nb, int precision,
                       double *out, hipStream_t st);
+void launch_mirror_lower(double *S, int64_t ng, hipStream_t st);
 void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st);
 void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st);
 
