@@ -186,12 +186,18 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
     };
     for (int k = 0; k < cmax; k += OUTER_W) {
         const int pe = k + OUTER_W;
-        if (lookahead && k > 0) sync(SYNC_TO_MAIN);  // this panel's columns: side update of panel k-1 done
+        // the panel's columns were brought up to date by the main stream's
+        // update from the previous panel, after the side stream had finished
+        // the updates of the panels before it; the side stream's update from
+        // the previous panel (columns beyond this panel) runs meanwhile
         for (int j0 = k; j0 < std::min(pe, cmax); j0 += 64) {
             add(0, j0, pe);
             add(1, j0, pe);
             add(2, j0, pe);
         }
+        // the next panel's columns: the side stream's update from the
+        // previous panel must be done before this panel's update of them
+        if (lookahead && k > 0) sync(SYNC_TO_MAIN);
         // large trailing matrices take the 128x128 tile kernel
         int big = 0;
         for (int32_t f : fl)
