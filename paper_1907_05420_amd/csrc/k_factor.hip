@@ -232,6 +232,28 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
 constexpr int EA_RL = 1024;  // staged target columns of an extend-add tile
 
 template <typename T>
+__device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q);
+
+// Epilogue of the update kernels: F(r, qb + j) -= sC[j * ldc] for the NJ
+// columns j = j0 + js * jj of row r, restricted to q <= r, q < qhi, r < m.
+// All target loads are issued (from clamped, valid addresses) before the
+// first store.
+template <typename T, int NJ>
+__device__ inline void rmw_sub_row(T *P, T *Ub, int m, int c, int r, int qb, int j0, int js, int qhi, const T *sC,
+                                   int ldc) {
+    const int rc = min(r, m - 1);
+    const int lim = min(rc, qhi - 1);
+    T o[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) o[jj] = *front_addr(P, Ub, m, c, rc, min(qb + j0 + js * jj, lim));
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = j0 + js * jj, q = qb + j;
+        if (r < m && q <= r && q < qhi) *front_addr(P, Ub, m, c, r, q) = o[jj] - sC[j * ldc];
+    }
+}
+
+template <typename T>
 __device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q) {
     return q < c ? P + r + (int64_t)q * m : Ub + (r - c) + (int64_t)(q - c) * (m - c);
 }
@@ -448,17 +470,26 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
     const int R0 = t0 + nb + (blockIdx.x - pre[fi]) * 64;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     {
+        // clamped addresses, all loads issued before the first use
         const int row = tid & 63, kk = tid >> 6;
+        const T *Pa = P + min(R0 + row, m - 1) + (int64_t)t0 * m;
+        const T *Pb = P + (t0 + min(row, nb - 1)) + (int64_t)t0 * m;
+        T va[16], vb[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int kc = min(kk + 4 * j, nb - 1);
+            va[j] = Pa[(int64_t)kc * m];
+            vb[j] = Pb[(int64_t)kc * m];
+        }
+        const T dv = P[(t0 + min(row, nb - 1)) + (int64_t)(t0 + min(row, nb - 1)) * m];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int k = kk + 4 * j;
-            sA[k * LDS_LD + row] = (k < nb && R0 + row < m) ? P[(R0 + row) + (int64_t)(t0 + k) * m] : T(0);
+            sA[k * LDS_LD + row] = (k < nb && R0 + row < m) ? va[j] : T(0);
             // B[q = row][k] = (L11^-1)[row][k]
-            T b = T(0);
-            if (row < nb && k < nb) b = k < row ? P[(t0 + row) + (int64_t)(t0 + k) * m] : (k == row ? T(1) : T(0));
-            sB[k * LDS_LD + row] = b;
+            sB[k * LDS_LD + row] = (row < nb && k < nb) ? (k < row ? vb[j] : (k == row ? T(1) : T(0))) : T(0);
         }
-        if (tid < NB) Ds[tid] = tid < nb ? P[(t0 + tid) + (int64_t)(t0 + tid) * m] : T(1);
+        if (tid < NB) Ds[tid] = tid < nb ? dv : T(1);
     }
     __syncthreads();
     const int lane = tid & 63, w = tid >> 6;
@@ -568,12 +599,7 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
     T *sC = sA;
     tile_stage<T>(sC, acc, lane, w);
     __syncthreads();
-    const int r = R0 + row;
-    if (r < m)
-        for (int j = kk; j < 64; j += 4) {
-            const int q = Q0 + j;
-            if (q <= r && q < g.qhi) *front_addr(P, Ub, m, c, r, q) -= sC[row + j * LDT];
-        }
+    rmw_sub_row<T, 16>(P, Ub, m, c, R0 + row, Q0, kk, 4, g.qhi, sC + row, LDT);
 }
 
 // Trailing update after an outer panel (kind 3) on 128x128 tiles: four waves
@@ -674,12 +700,8 @@ __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const F
                         sC[(wr + 16 * bi + mfma_row(T(0), lk, rr)) + (16 * bj + li) * (BT + 1)] = acc[bi][bj][rr];
         }
         __syncthreads();
-        const int r = R0 + lrow;
-        if (r < m)
-            for (int j = lkk; j < 64; j += 2) {
-                const int q = Q0 + 64 * half + j;
-                if (q <= r && q < g.qhi) *front_addr(P, Ub, m, c, r, q) -= sC[lrow + j * (BT + 1)];
-            }
+        rmw_sub_row<T, 16>(P, Ub, m, c, R0 + lrow, Q0 + 64 * half, lkk, 2, g.qhi, sC + lrow, BT + 1);
+        rmw_sub_row<T, 16>(P, Ub, m, c, R0 + lrow, Q0 + 64 * half, lkk + 32, 2, g.qhi, sC + lrow, BT + 1);
         __syncthreads();
     }
 }
