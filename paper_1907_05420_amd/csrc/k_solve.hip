@@ -76,6 +76,55 @@ __device__ inline void row_dot(const T *P, int64_t m, int nq, const double *w, d
     }
 }
 
+// dst[i * RBT + r] = src[r * nv + idx[i]] for i < n, r < nr; zero for the
+// other rows i < nrows and right-hand sides. Index loads, then value loads,
+// four rows per thread at a time.
+template <int RBT, int NT>
+__device__ inline void gather_rows(double *dst, int nrows, int n, const int32_t *idx, const double *src, int64_t nv,
+                                   int nr, int tid) {
+    for (int i0 = 0; i0 < nrows; i0 += 4 * NT) {
+        int32_t ri[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ri[u] = n > 0 ? idx[min(i0 + tid + u * NT, n - 1)] : 0;
+        double val[4][RBT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RBT; ++r) val[u][r] = n > 0 ? src[(int64_t)min(r, nr - 1) * nv + ri[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + tid + u * NT;
+            if (i < nrows)
+#pragma unroll
+                for (int r = 0; r < RBT; ++r) dst[i * RBT + r] = (i < n && r < nr) ? val[u][r] : 0.0;
+        }
+    }
+}
+
+// v[rel[i] * RBT + r] += U[r * usz + i] for the uc update rows of a child
+// (rel is injective, so the rows of one child never collide)
+template <int RBT, int NT>
+__device__ inline void add_child(double *v, int uc, const int32_t *rel, const double *U, int64_t usz, int nr,
+                                 int tid) {
+    for (int i0 = 0; i0 < uc; i0 += 4 * NT) {
+        int32_t ri[4];
+        double uv[4][RBT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = min(i0 + tid + u * NT, uc - 1);
+            ri[u] = rel[i];
+#pragma unroll
+            for (int r = 0; r < RBT; ++r) uv[u][r] = U[(int64_t)min(r, nr - 1) * usz + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + tid + u * NT < uc)
+#pragma unroll
+                for (int r = 0; r < RBT; ++r)
+                    if (r < nr) v[ri[u] * RBT + r] += uv[u][r];
+    }
+}
+
 // Forward pass of a front larger than 64 rows, pivot part: extend-add of the
 // children's update vectors, then y = L11^-1 v over 64-column blocks with the
 // stored inverses of the pivot blocks. Rows below the pivots leave with the
@@ -84,8 +133,8 @@ template <typename T, int RBT>
 __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
                                                  const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
     extern __shared__ double smem[];
-    double *Lt = smem;                          // 64 x 65 staging tile, then 8 x 64 x RBT partial sums
-    double *v = smem + 64 * 65 + 8 * 64 * RBT;  // m x RBT
+    double *Lt = smem;             // 64 x 65 staging tile
+    double *v = smem + 64 * 65;    // m x RBT
     const int s = tasks[blockIdx.x];
     const int n = blockIdx.y, tid = threadIdx.x;
     const FrontDesc d = sd[s];
@@ -112,43 +161,27 @@ __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, co
             }
             __syncthreads();
         }
-        // left-looking over 64-column blocks: v_b -= L[b, 0:k0] y[0:k0] (eight
-        // column groups of 32-column batches, reduced through LDS), then
-        // y_b = X_b v_b with the staged inverse of the pivot block
-        const int a = tid & 63, g = tid >> 6;
         for (int k0 = 0; k0 < c; k0 += 64) {
             const int nb = min(64, c - k0);
-            double acc[RBT];
-#pragma unroll
-            for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
-            const T *rowp = P + k0 + min(a, nb - 1);
-            for (int q0 = 32 * g; q0 < k0; q0 += 256) {
-                T l[32];
-#pragma unroll
-                for (int u = 0; u < 32; ++u) l[u] = rowp[(int64_t)(q0 + u) * m];
-#pragma unroll
-                for (int u = 0; u < 32; ++u)
-#pragma unroll
-                    for (int rr = 0; rr < RBT; ++rr) acc[rr] += (double)l[u] * v[(q0 + u) * RBT + rr];
-            }
-#pragma unroll
-            for (int rr = 0; rr < RBT; ++rr) Lt[64 * 65 + (g * 64 + a) * RBT + rr] = acc[rr];
             stage_tile<T, SNT>(Lt, P, m, k0, k0, nb, nb, true, tid);
             __syncthreads();
-            if (g < nr && a < nb) {
-                double t = 0.0;
-#pragma unroll
-                for (int gg = 0; gg < 8; ++gg) t += Lt[64 * 65 + (gg * 64 + a) * RBT + g];
-                v[(k0 + a) * RBT + g] -= t;
-            }
-            __syncthreads();
+            const int i = tid & 63, r = tid >> 6;
             double yv = 0.0;
-            if (g < nr && a < nb) {
-                yv = v[(k0 + a) * RBT + g];
-                for (int q = 0; q < a; ++q) yv += Lt[a + q * 65] * v[(k0 + q) * RBT + g];
+            if (i < nb && r < nr) {
+                yv = v[(k0 + i) * RBT + r];
+                for (int q = 0; q < i; ++q) yv += Lt[i + q * 65] * v[(k0 + q) * RBT + r];
             }
             __syncthreads();
-            if (g < nr && a < nb) v[(k0 + a) * RBT + g] = yv;
+            if (i < nb && r < nr) v[(k0 + i) * RBT + r] = yv;
+            __syncthreads();
+            for (int i2 = k0 + nb + tid; i2 < c; i2 += SNT) {
+                double acc[RBT];
+#pragma unroll
+                for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
+                row_dot<T, RBT>(P + i2 + (int64_t)k0 * m, m, nb, v + k0 * RBT, acc);
+#pragma unroll
+                for (int rr = 0; rr < RBT; ++rr) v[i2 * RBT + rr] -= acc[rr];
+            }
             __syncthreads();
         }
         for (int idx = tid; idx < m * nr; idx += SNT) {
@@ -187,10 +220,7 @@ __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, c
         for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
         for (int q0 = 0; q0 < c; q0 += 256) {
             const int nq = min(256, c - q0);
-            for (int idx = tid; idx < 256 * RBT; idx += 256) {
-                const int q = idx / RBT, r = idx % RBT;
-                yb[idx] = (q < nq && r < nr) ? x0[(int64_t)r * sa.nv + R[q0 + q]] : 0.0;
-            }
+            gather_rows<RBT, 256>(yb, 256, nq, R + q0, x0, sa.nv, nr, tid);
             __syncthreads();
             const int qa = 64 * g;
             if (qa < nq) row_dot<T, RBT>(rowp + (int64_t)(q0 + qa) * m, m, min(64, nq - qa), yb + qa * RBT, acc);
@@ -239,10 +269,7 @@ __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, c
         for (int ib = c; ib < m; ib += 64) {
             const int nrow = min(64, m - ib);
             stage_tile<T, 256>(Lt, P, m, ib, q0, nrow, ncol, false, tid);
-            for (int idx = tid; idx < 64 * RBT; idx += 256) {
-                const int a = idx / RBT, r = idx % RBT;
-                xb[idx] = (a < nrow && r < nr) ? x0[(int64_t)r * sa.nv + R[ib + a]] : 0.0;
-            }
+            gather_rows<RBT, 256>(xb, 64, nrow, R + ib, x0, sa.nv, nr, tid);
             __syncthreads();
 #pragma unroll
             for (int a = 16 * g; a < 16 * g + 16; ++a) {
@@ -292,14 +319,14 @@ __global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, co
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
-        for (int idx = tid; idx < c * RBT; idx += SNT) {
-            const int i = idx / RBT, r = idx % RBT;
-            double val = 0.0;
-            if (r < nr) {
-                val = x0[(int64_t)r * sa.nv + R[i]];
-                if (divide) val /= (double)P[i + (int64_t)i * m];
+        gather_rows<RBT, SNT>(v, c, c, R, x0, sa.nv, nr, tid);
+        if (divide) {
+            __syncthreads();
+            for (int i = tid; i < c; i += SNT) {
+                const double dd = (double)P[i + (int64_t)i * m];
+#pragma unroll
+                for (int r = 0; r < RBT; ++r) v[i * RBT + r] /= dd;
             }
-            v[idx] = val;
         }
         __syncthreads();
         for (int kb = ((c - 1) / 64) * 64; kb >= 0; kb -= 64) {
@@ -659,7 +686,7 @@ static int rhs_block(int64_t nrhs, int rows, size_t fixed) {
 template <typename T, int RBT>
 static void fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *large, int nlarge, int maxm,
                     const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
-    const size_t lds = sizeof(double) * ((size_t)maxm * RBT + 64 * 65 + 8 * 64 * RBT);
+    const size_t lds = sizeof(double) * ((size_t)maxm * RBT + 64 * 65);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)k_fwd_tri<T, RBT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_fwd_tri<T, RBT>), dim3(nlarge, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, large,
@@ -683,7 +710,7 @@ void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const Le
         hipLaunchKernelGGL(k_fwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
                            tr, sa);
     if (lt.nlarge <= 0) return;
-    const int rb = rhs_block(sa.nrhs, lt.maxm, sizeof(double) * (64 * 65 + 8 * 64 * RB));
+    const int rb = rhs_block(sa.nrhs, lt.maxm, sizeof(double) * 64 * 65);
     if (rb == 4) fwd_tri<T, 4>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
     else if (rb == 2) fwd_tri<T, 2>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
     else fwd_tri<T, 1>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
