@@ -10,6 +10,7 @@ alternate so that every step factors new values. Symbolic analysis is done
 once, outside the timed region, and reported separately.
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|mixed]
+    python bench.py --copy-probe      (plain device copy, counter calibration)
 
 Prints one JSON line on stdout.
 """
@@ -65,34 +66,55 @@ def cpu_baseline(sample_periods=5):
                 seconds_measured=t_total)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--refine", default="fgmres", choices=["fgmres", "classic"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-baseline-only", action="store_true")
-    args = ap.parse_args()
-    if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline()))
-        return 0
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
-        return 2
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "k_update_big_mesh2000_N96_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1907_05420_amd", "csrc", "k_factor.hip")
+
+
+def git_blob_sha1(path):
+    """git's blob hash of a file (what `git hash-object` prints)."""
+    import hashlib
+    data = open(path, "rb").read()
+    return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel source changed after the counters were
+    taken (the summary records the source's blob hash)."""
+    if not os.path.exists(PROFILE_COUNTERS):
+        return None
+    vals = {}
+    for line in open(PROFILE_COUNTERS):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha1") != git_blob_sha1(KERNEL_SOURCE):
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}))
+
+
+def measure(args, inst, vals2, prec, log):
+    """Warm up, then time exactly args.steps factor+solve steps."""
     import numpy as np
     import torch
-    import kktgen
     import paper_1907_05420_amd as pk
-
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    inst = kktgen.make_workload(2)
-    rng = np.random.default_rng(kktgen.seed_for(2, 9))
-    vals2 = kktgen.redraw_barrier(inst, rng)
     d = pk.device_inputs(inst)
     vsets = [d["vals"], torch.as_tensor(vals2).cuda()]
-    prec = pk.KKT_MIXED if args.precision == "mixed" else pk.KKT_FP64
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = pk.Solver(inst, precision=prec,
@@ -107,7 +129,7 @@ def main():
         _, rc, info = s.solve(d["b"], x)
         log(f"warmup {i}: rc {rc} info {info} phases {pk.kkt_phase_times(s.ctx)}")
     torch.cuda.synchronize()
-    lat, phases, infos = [], [], []
+    lat, phases, infos, kstats = [], [], [], []
     t_start = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
@@ -116,34 +138,64 @@ def main():
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
         phases.append(pk.kkt_phase_times(s.ctx))
+        kstats.append(pk.kkt_dominant_kernel(s.ctx))
         infos.append(info)
         log(f"step {i}: {lat[-1]*1e3:.2f} ms rc {rc} info {info}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    value = args.steps / elapsed
-    ph = np.array(phases)
-    ph_mean = ph.mean(0).tolist()
-    ng = inst.n_g
-    # dominant kernel sequence: the Schur LDL^T (FP64 MFMA) or the block factor
-    schur_flops = ng ** 3 / 3.0
-    block_flops = inst.N * st["flops_factor"]
-    if ph_mean[2] >= ph_mean[0]:
-        dom = dict(kernel="schur_ldlt (k_diag/k_trsm/k_update, FP64 MFMA)", flops=schur_flops, ms=ph_mean[2],
-                   peak=MI355X_FP64_TFLOPS)
-    else:
-        pk_peak = MI355X_FP32_TFLOPS if prec == pk.KKT_MIXED else MI355X_FP64_TFLOPS
-        dom = dict(kernel="block_factor (multifrontal, all periods)", flops=block_flops, ms=ph_mean[0],
-                   peak=pk_peak)
-    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
+    s.close()
     lat_ms = np.array(lat) * 1e3
+    return dict(value=args.steps / elapsed, elapsed=elapsed, lat_ms=lat_ms, phases=np.array(phases).mean(0).tolist(),
+                infos=infos, kstats=kstats, analyze_ms=t_analyze * 1e3, stats=st)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--refine", default="fgmres", choices=["fgmres", "classic"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline()))
+        return 0
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        return 2
+    if args.copy_probe:
+        copy_probe()
+        return 0
+    import numpy as np
+    import kktgen
+    import paper_1907_05420_amd as pk
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    inst = kktgen.make_workload(2)
+    rng = np.random.default_rng(kktgen.seed_for(2, 9))
+    vals2 = kktgen.redraw_barrier(inst, rng)
+    prec = pk.KKT_MIXED if args.precision == "mixed" else pk.KKT_FP64
+    m = measure(args, inst, vals2, prec, log)
+    ph = m["phases"]
+    ng = inst.n_g
+    # dominant kernel: the dense Schur trailing update (FP64 MFMA)
+    launches = sum(k["launches"] for k in m["kstats"])
+    k_ms = sum(k["total_ms"] for k in m["kstats"])
+    k_flops = sum(k["flops"] for k in m["kstats"])
+    k_bytes = sum(k["bytes"] for k in m["kstats"])
+    achieved = k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+    traffic = measured_traffic()
     res = {
         "metric": METRIC,
-        "value": value,
+        "value": m["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": m["elapsed"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -152,18 +204,24 @@ def main():
         "config": {"workload": "mesh2000_N96", "buses": 2000, "lines": 3000, "generators": 400,
                    "storage": 200, "periods": 96, "block_rows": inst.n_A, "schur_dim": ng, "nrhs": 4,
                    "barrier_range": [1e-8, 1e8], "precision": args.precision, "refine": args.refine},
-        "p50_ms": float(np.percentile(lat_ms, 50)),
-        "p99_ms": float(np.percentile(lat_ms, 99)),
-        "rel_res": max(i["rel_res"] for i in infos),
-        "omega": max(i["omega"] for i in infos),
-        "refine_iters": [i["refine_iters"] for i in infos],
-        "phase_ms": {"block_factor": ph_mean[0], "schur_assembly": ph_mean[1], "schur_ldlt": ph_mean[2],
-                     "solve_refined": ph_mean[3]},
-        "analyze_ms": t_analyze * 1e3,
-        "roofline": {"bound": "mfma", "kernel": dom["kernel"], "achieved": achieved, "peak": dom["peak"],
-                     "unit": "TFLOP/s", "frac": achieved / dom["peak"], "traffic": None},
+        "p50_ms": float(np.percentile(m["lat_ms"], 50)),
+        "p99_ms": float(np.percentile(m["lat_ms"], 99)),
+        "rel_res": max(i["rel_res"] for i in m["infos"]),
+        "omega": max(i["omega"] for i in m["infos"]),
+        "refine_iters": [i["refine_iters"] for i in m["infos"]],
+        "phase_ms": {"block_factor": ph[0], "schur_assembly": ph[1], "schur_ldlt": ph[2], "solve_refined": ph[3],
+                     "schur_update_kernel": ph[4]},
+        "schur_ldlt_tflops": ng ** 3 / 3.0 / (ph[2] * 1e-3) / 1e12 if ph[2] > 0 else 0.0,
+        "analyze_ms": m["analyze_ms"],
+        "roofline": {"bound": "mfma", "kernel": "k_update_big (dense Schur trailing update, FP64 MFMA)",
+                     "achieved": achieved, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / MI355X_FP64_TFLOPS,
+                     "traffic": traffic,
+                     "launches_per_step": launches / max(args.steps, 1),
+                     "avg_launch_ms": k_ms / launches if launches else 0.0,
+                     "flops_per_launch": k_flops / launches if launches else 0.0,
+                     "algorithmic_bytes_per_launch": k_bytes / launches if launches else 0.0},
     }
-    s.close()
     if not args.no_cpu_baseline:
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only"], env=env,

@@ -196,11 +196,26 @@ int kkt_stats(const kkt_ctx *ctx, kkt_symbolic_stats *st);
 /* kkt_phase_times: milliseconds of the phases of the last factor/solve,
  * measured with HIP events on the context's stream (syncs the stream):
  * [0] block factor, [1] Schur assembly, [2] Schur factor, [3] last solve
- * (all refinement steps), [4] the most expensive single kernel of the last
- * factor; t must hold 5 doubles. Timing is off unless enabled with
- * kkt_enable_timing(ctx, 1). */
+ * (all refinement steps), [4] summed launch durations of the Schur
+ * trailing-update kernel (see kkt_dominant_kernel) in the last factor; t must
+ * hold 5 doubles. Timing is off unless enabled with kkt_enable_timing(ctx, 1). */
 int kkt_enable_timing(kkt_ctx *ctx, int on);
 int kkt_phase_times(kkt_ctx *ctx, double *t);
+
+/* Work and time of the dominant kernel of kkt_factor: the trailing update
+ * F -= L D L^T of the dense Schur LDL^T (Algorithm 1 step 12) on 128x128
+ * tiles, over its launches in the last kkt_factor with timing enabled.
+ * Durations come from HIP events recorded around every launch on the stream it
+ * is launched on. flops counts 2 K per updated lower-triangle entry; bytes
+ * counts one read and one write of every updated entry plus one read of the
+ * panel operands (the kernel's algorithmic HBM traffic). */
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double flops;
+    double bytes;
+} kkt_kernel_stat;
+int kkt_dominant_kernel(kkt_ctx *ctx, kkt_kernel_stat *out);
 
 void kkt_destroy(kkt_ctx *ctx);
 const char *kkt_strerror(int code);

@@ -160,6 +160,12 @@ def kkt_phase_times(ctx):
     return list(t)
 
 
+def kkt_dominant_kernel(ctx):
+    st = _abi.KernelStat()
+    _check(load_library().kkt_dominant_kernel(ctx, C.byref(st)), "kkt_dominant_kernel")
+    return {f: getattr(st, f) for f, _ in st._fields_}
+
+
 def kkt_destroy(ctx):
     if ctx:
         load_library().kkt_destroy(ctx)

@@ -45,6 +45,10 @@ class SymbolicStats(C.Structure):
                 ("flops_factor", C.c_double), ("device_bytes", C.c_int64)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
 # name -> (restype, argtypes); every symbol include/kkt.h declares
 SIGNATURES = {
     "kkt_default_options": (None, [C.POINTER(Options)]),
@@ -61,6 +65,7 @@ SIGNATURES = {
     "kkt_stats": (C.c_int, [C.c_void_p, C.POINTER(SymbolicStats)]),
     "kkt_enable_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "kkt_phase_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "kkt_dominant_kernel": (C.c_int, [C.c_void_p, C.POINTER(KernelStat)]),
     "kkt_destroy": (None, [C.c_void_p]),
     "kkt_strerror": (C.c_char_p, [C.c_int]),
 }

@@ -105,6 +105,10 @@ struct kkt_ctx {
     bool timing = false;
     hipEvent_t ev[8] = {};
     double times[5] = {0, 0, 0, 0, 0};
+    // per-launch events of the Schur trailing-update kernel (timing only)
+    std::vector<hipEvent_t> kev;
+    int64_t kcount = 0;
+    kkt_kernel_stat kstat{};
 };
 
 namespace {
@@ -536,6 +540,8 @@ int factor_schur(kkt_ctx *ctx) {
                           ctx->has_corner ? ctx->d_corner : nullptr, ctx->d_S, ctx->d_tauS, ctx->eps,
                           ctx->d_amaxS, 0, st);
     mark(ctx, 2);
+    ctx->kcount = 0;
+    ctx->kstat = kkt_kernel_stat{};
     FactorArgs<double> fa = schur_args(ctx);
     for (const StepHost &s : ctx->ssteps) {
         if (s.kind == SYNC_TO_SIDE) {
@@ -545,7 +551,27 @@ int factor_schur(kkt_ctx *ctx) {
             HIPCHK(hipEventRecord(ctx->ev_side, ctx->side));
             HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
         } else {
-            launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, s.side ? ctx->side : st);
+            hipStream_t ss = s.side ? ctx->side : st;
+            const bool timed = ctx->timing && s.kind == 4;
+            if (timed) {
+                if ((size_t)(2 * ctx->kcount + 2) > ctx->kev.size()) {
+                    hipEvent_t e0, e1;
+                    HIPCHK(hipEventCreate(&e0));
+                    HIPCHK(hipEventCreate(&e1));
+                    ctx->kev.push_back(e0);
+                    ctx->kev.push_back(e1);
+                }
+                HIPCHK(hipEventRecord(ctx->kev[2 * ctx->kcount], ss));
+            }
+            launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, ss);
+            if (timed) {
+                HIPCHK(hipEventRecord(ctx->kev[2 * ctx->kcount + 1], ss));
+                double f = 0.0, b = 0.0;
+                update_work(s.t0, s.pe, (int)ctx->ng, (int)ctx->ng, s.win, &f, &b);
+                ctx->kstat.flops += f;
+                ctx->kstat.bytes += b;
+                ++ctx->kcount;
+            }
         }
     }
     launch_mirror_lower(ctx->d_S, ctx->ng, st);
@@ -753,6 +779,14 @@ extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_v
         ctx->times[0] = elapsed(ctx, 0, 1);
         ctx->times[1] = ctx->ng ? elapsed(ctx, 1, 2) : 0.0;
         ctx->times[2] = ctx->ng ? elapsed(ctx, 2, 3) : 0.0;
+        double kms = 0.0;
+        for (int64_t j = 0; j < ctx->kcount; ++j) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ctx->kev[2 * j], ctx->kev[2 * j + 1]) == hipSuccess) kms += ms;
+        }
+        ctx->kstat.launches = ctx->kcount;
+        ctx->kstat.total_ms = kms;
+        ctx->times[4] = kms;
     }
     if (!out) return KKT_OK;
     std::vector<int64_t> cnt(4 * (ctx->N + 1), 0), cs(4, 0);
@@ -998,6 +1032,12 @@ extern "C" int kkt_phase_times(kkt_ctx *ctx, double *t) {
     return KKT_OK;
 }
 
+extern "C" int kkt_dominant_kernel(kkt_ctx *ctx, kkt_kernel_stat *out) {
+    if (!ctx || !out) return KKT_ERR_ARG;
+    *out = ctx->kstat;
+    return KKT_OK;
+}
+
 extern "C" void kkt_destroy(kkt_ctx *ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
@@ -1006,6 +1046,7 @@ extern "C" void kkt_destroy(kkt_ctx *ctx) {
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->kev) (void)hipEventDestroy(e);
     if (ctx->ev_main) (void)hipEventDestroy(ctx->ev_main);
     if (ctx->ev_side) (void)hipEventDestroy(ctx->ev_side);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);

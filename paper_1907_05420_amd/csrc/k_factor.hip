@@ -535,6 +535,16 @@ __host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int
     return g;
 }
 
+// algorithmic work of one trailing-update launch on a front (see kkt.h)
+void update_work(int t0, int pe, int c, int m, int win, double *flops, double *bytes) {
+    const UpdGeom g = upd_geom(3, t0, pe, c, m, win);
+    const double lo = g.lo, qhi = g.qhi, K = g.K;
+    if (qhi <= lo || K <= 0) { *flops = 0.0; *bytes = 0.0; return; }
+    const double entries = (qhi - lo) * m - (lo + qhi - 1.0) * (qhi - lo) * 0.5;
+    *flops = 2.0 * K * entries;
+    *bytes = 16.0 * entries + 8.0 * K * ((m - lo) + (qhi - lo));
+}
+
 // tile (ti, tj) of a trapezoid: column tiles tj < Tc, row tiles ti in [tj, Tr)
 __device__ inline void trap_decode(int t, int Tr, int &ti, int &tj) {
     int j = (int)floor(((2.0 * Tr + 1.0) - sqrt((2.0 * Tr + 1.0) * (2.0 * Tr + 1.0) - 8.0 * t)) * 0.5);

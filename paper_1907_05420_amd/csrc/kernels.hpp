@@ -45,6 +45,8 @@ struct StepDev {
     int ntasks;
 };
 int step_tasks(int kind, int t0, int pe, int c, int m, int win = 0);
+// algorithmic flops and HBM bytes of one trailing-update launch on a front
+void update_work(int t0, int pe, int c, int m, int win, double *flops, double *bytes);
 
 template <typename T> void launch_zero(T *p, int64_t n, hipStream_t st);
 void launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st);
