@@ -31,7 +31,7 @@ MI355X_FP64_TFLOPS = 78.6
 MI355X_FP32_TFLOPS = 157.3
 
 
-def cpu_baseline(sample_periods=5):
+def cpu_baseline(sample_periods=14):
     """Time the FP64 oracle (Algorithm 1 as it stands) on a bounded sample of
     the same workload: the first `sample_periods` periods, i.e. Algorithm 1 on
     the truncated horizon, whose Schur complement is the leading principal
