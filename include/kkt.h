@@ -61,7 +61,10 @@ extern "C" {
 /* ---- options ------------------------------------------------------------ */
 #define KKT_FP64 0   /* every factor and solve in FP64                         */
 #define KKT_MIXED 1  /* block factors and Schur contributions in FP32, FP64    */
-                     /* refinement residual, FP64 dense Schur factorisation    */
+                     /* refinement residual, FP64 dense Schur factorisation;   */
+                     /* the elimination order then postpones every dual until  */
+                     /* all its primal neighbours are eliminated (no growth     */
+                     /* from early duals, more fill than the FP64 order)        */
 
 typedef struct kkt_options {
     int precision;      /* KKT_FP64 or KKT_MIXED                              */

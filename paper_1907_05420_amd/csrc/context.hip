@@ -17,7 +17,7 @@
 #include "symbolic.hpp"
 
 namespace kkt {
-SymbolicInput make_input(const kkt_structure *s);
+SymbolicInput make_input(const kkt_structure *s, const kkt_options &o);
 void fill_stats(const Symbolic &S, int64_t N, const kkt_options &o, int64_t nrhs_max, kkt_symbolic_stats *st);
 }
 
@@ -699,7 +699,7 @@ extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
     Symbolic S;
     std::string err;
     try {
-        err = analyze(make_input(s), S);
+        err = analyze(make_input(s, ctx->opt), S);
     } catch (...) {
         return KKT_ERR_NOMEM;
     }

@@ -35,8 +35,10 @@ extern "C" const char *kkt_strerror(int code) {
 }
 
 namespace kkt {
-SymbolicInput make_input(const kkt_structure *s) {
+SymbolicInput make_input(const kkt_structure *s, const kkt_options &o) {
     SymbolicInput in;
+    // FP32 factors cannot absorb the growth that early duals cause
+    in.dual_wait = o.precision == KKT_MIXED ? (1 << 30) : 4;
     in.nA = s->nA;
     in.n_primal = s->n_primal;
     in.Ns = s->Ns;
@@ -70,7 +72,7 @@ extern "C" int kkt_plan(const kkt_structure *s, const kkt_options *opt, int64_t 
     kkt::Symbolic S;
     std::string err;
     try {
-        err = kkt::analyze(kkt::make_input(s), S);
+        err = kkt::analyze(kkt::make_input(s, o), S);
     } catch (...) {
         return KKT_ERR_NOMEM;
     }

@@ -18,7 +18,7 @@ namespace kkt {
 // few of their primal neighbours are eliminated (see `need` below).
 // ---------------------------------------------------------------------------
 std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
-                               const std::vector<int32_t> &adj, int64_t n_primal) {
+                               const std::vector<int32_t> &adj, int64_t n_primal, int dual_wait) {
     std::vector<std::vector<int32_t>> Av(n), Ev(n), Le(n), members(n);
     std::vector<int32_t> nv(n, 1), deg(n), status(n, 0);  // 0 var, 1 element, 2 dead
     // dual eligibility: number of primal neighbours not yet eliminated
@@ -28,11 +28,12 @@ std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
     auto is_dual = [&](int32_t i) { return constrained && i >= n_primal; };
     // A dual (negative pivot -delta_c - ...) eliminated before any of its
     // primal neighbours has the bare regularisation -delta_c as its pivot and
-    // feeds updates of size |J|^2/delta_c into the primal pivots; waiting for
-    // a few primal neighbours keeps that growth bounded. Four keeps the fill
-    // of the unconstrained order on the MPOPF blocks; waiting for all of them
-    // multiplies it.
-    const int need = 4;
+    // feeds updates of size |J|^2/delta_c into the primal pivots. Waiting for
+    // four primal neighbours keeps the fill of the unconstrained order on the
+    // MPOPF blocks and leaves growth that FP64 refinement absorbs; waiting for
+    // all of them (the FP32 factors need it) removes the growth but multiplies
+    // the fill.
+    const int need = dual_wait;
     if (constrained)
         for (int32_t i = 0; i < n; ++i)
             if (is_dual(i)) {
@@ -273,7 +274,7 @@ std::string analyze(const SymbolicInput &in, Symbolic &S) {
             adj[pos[j]++] = i;
             adj[pos[i]++] = (int32_t)j;
         }
-    std::vector<int32_t> perm = amd_order((int32_t)nA, xadj, adj, in.n_primal);
+    std::vector<int32_t> perm = amd_order((int32_t)nA, xadj, adj, in.n_primal, in.dual_wait);
     if ((int64_t)perm.size() != nA) return "ordering failed";
 
     // --- lower pattern of M by rows in a given order --------------------------

@@ -18,6 +18,9 @@ namespace kkt {
 
 struct SymbolicInput {
     int64_t nA = 0, n_primal = 0, Ns = 0;
+    // primal neighbours a dual waits for before it may be eliminated
+    // (capped at its count; see amd_order)
+    int dual_wait = 4;
     const int64_t *colptr = nullptr;
     const int32_t *rowind = nullptr;
     const int64_t *C0p = nullptr, *C1p = nullptr;
@@ -59,11 +62,12 @@ struct Symbolic {
 };
 
 // Approximate-minimum-degree order of the symmetric graph (xadj/adj without
-// self loops). Returns perm[new] = old. With n_primal >= 0, variables
-// i >= n_primal (duals) become eligible only once every primal neighbour
-// (i' < n_primal) of the original graph is eliminated.
+// self loops). Returns perm[new] = old. With n_primal >= 0, a variable
+// i >= n_primal (a dual) becomes eligible only once min(dual_wait, its number
+// of primal neighbours) of its primal neighbours (i' < n_primal) of the
+// original graph are eliminated.
 std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
-                               const std::vector<int32_t> &adj, int64_t n_primal = -1);
+                               const std::vector<int32_t> &adj, int64_t n_primal = -1, int dual_wait = 4);
 
 // Full analysis. Returns an empty string on success, else an error message
 // (structural problem in the input).
