@@ -149,6 +149,71 @@ def measure(args, inst, vals2, prec, log):
                 infos=infos, kstats=kstats, analyze_ms=t_analyze * 1e3, stats=st)
 
 
+def bench_batch(args, log):
+    """64 independent instances of the uneven mixture (bus counts log-uniform
+    in [118, 3000], horizons 12/24/48/96), each factored and solved with a
+    fixed number of FP64 refinement steps; the batch runs on several streams,
+    tile shapes and stream count autotuned first. A step is one run of the
+    whole batch (64 KKT solves)."""
+    import numpy as np
+    import torch
+    import kktgen
+    import paper_1907_05420_amd as pk
+    from paper_1907_05420_amd import autotune
+    prec = pk.KKT_MIXED if args.precision == "mixed" else pk.KKT_FP64
+    insts = kktgen.uneven_batch()
+    t0 = time.perf_counter()
+    rows, choice = autotune.tune_tiles(insts, prec, reps=1, log=log)
+    t_tune_tiles = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = pk.Batch(insts, nstreams=4, precision=prec, big_tile_rows=rows)
+    t_analyze = time.perf_counter() - t0
+    ns = autotune.tune_streams(b, args.refine_steps, log=log)
+    for _ in range(max(args.warmup, 1)):
+        b.run(args.refine_steps)
+    b.wait()
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        b.run(args.refine_steps)
+        b.wait()
+        lat.append(time.perf_counter() - ts)
+    elapsed = time.perf_counter() - t_start
+    st = b.status()
+    # the same instances one after another on one stream, eagerly
+    stream = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter()
+    for s, d, x in zip(b.solvers, b.inputs, b.x):
+        pk.kkt_set_stream(s.ctx, stream)
+        pk.kkt_factor_async(s.ctx, d["vals"], d["C0"], d["C1"], d["corner"])
+        pk.kkt_solve_async(s.ctx, d["b"], x, d["b"].shape[0], args.refine_steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t_seq
+    n = len(insts)
+    rel = [r["info"]["rel_res"] for r in st]
+    lat_ms = np.array(lat) * 1e3
+    res = {
+        "metric": METRIC, "value": n * args.steps / elapsed, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == pk.KKT_FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": "uneven64", "instances": n, "buses": [118, 3000], "horizons": [12, 24, 48, 96],
+                   "nrhs": 1, "barrier_range": [1e-6, 1e6], "precision": args.precision,
+                   "refine_steps": args.refine_steps, "streams": ns, "hip_graph": False},
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "rel_res_max": float(max(rel)), "rel_res_median": float(np.median(rel)),
+        "inertia_ok": int(sum(r["inertia"]["inertia_ok"] for r in st)),
+        "sequential_solves_per_s": n / t_seq, "speedup_vs_sequential": (n * args.steps / elapsed) / (n / t_seq),
+        "tiles": choice, "tune_tiles_s": t_tune_tiles, "analyze_s": t_analyze,
+        "device_gb": sum(s.footprint() for s in b.solvers) / 1e9,
+    }
+    b.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--workload", default="mesh2000_N96", choices=["mesh2000_N96", "uneven64"])
+    ap.add_argument("--refine-steps", type=int, default=3, help="fixed refinement steps of a batch")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline()))
@@ -174,6 +241,12 @@ def main():
     import paper_1907_05420_amd as pk
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if args.workload == "uneven64":
+        # switched off: its first run of the 64-instance batch on two streams
+        # ended in a GPU memory fault whose cause has not been found yet
+        print("bench.py --workload uneven64 is switched off (GPU memory fault under investigation)",
+              file=sys.stderr)
+        return 3
     inst = kktgen.make_workload(2)
     rng = np.random.default_rng(kktgen.seed_for(2, 9))
     vals2 = kktgen.redraw_barrier(inst, rng)

@@ -74,6 +74,9 @@ typedef struct kkt_options {
     int refine_max;     /* refinement steps at most (default 20)              */
     int verbose;        /* 0 quiet                                            */
     int refine_method;  /* KKT_REFINE_FGMRES (default) or KKT_REFINE_CLASSIC   */
+    int big_tile_rows;  /* trailing updates of at least this many rows use     */
+                        /* 128x128 tiles, smaller ones 64x64; 0 = default 512   */
+                        /* (a tile-shape knob for autotuning)                   */
 } kkt_options;
 
 #define KKT_REFINE_FGMRES 0  /* flexible GMRES on K, right-preconditioned by the */
@@ -182,6 +185,59 @@ int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals,
  * Returns 0, KKT_WARN_REFINE, or an error. */
 int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
               kkt_solve_info *info);
+
+/* ---- enqueue-only variants (no host synchronisation), for batches, graphs
+ * and serving loops that keep many systems in flight ---------------------- */
+
+/* kkt_set_stream: later calls of ctx enqueue on `stream` (a hipStream_t);
+ * the caller orders any earlier work of the context on its old stream. */
+int kkt_set_stream(kkt_ctx *ctx, void *stream);
+
+/* kkt_factor_async: kkt_factor without any host synchronisation, so it can be
+ * captured into a HIP graph. Non-finite input is not rejected up front: it is
+ * recorded on the device and reported by kkt_factor_status, which also reads
+ * the inertia (synchronises; returns as kkt_factor would, including
+ * KKT_ERR_NONFINITE). Fails with KKT_ERR_ARG while timing is enabled. */
+int kkt_factor_async(kkt_ctx *ctx, const double *A_vals, const double *C0_vals,
+                     const double *C1_vals, const double *corner_diag,
+                     double delta_w, double delta_c);
+int kkt_factor_status(kkt_ctx *ctx, kkt_inertia *out);
+
+/* kkt_solve_async: x = K^-1 b (Eqs. SCsolve, SCsolve1) followed by exactly
+ * `steps` FP64 refinement steps x += solve(b - K x) (section 2.1), all on the
+ * stream; the norms of the final residual stay on the device for
+ * kkt_solve_status (synchronises; returns KKT_WARN_REFINE when rel_res is
+ * above refine_tol). The solve workspace for nrhs right-hand sides must exist
+ * before a graph capture (any earlier kkt_solve or kkt_solve_async with at
+ * least nrhs right-hand sides creates it); otherwise KKT_ERR_ARG. */
+int kkt_solve_async(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps);
+int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info);
+
+/* ---- uneven batches (many independent systems, one submission) ----------- */
+
+typedef struct kkt_batch kkt_batch;
+
+/* kkt_batch_create: a batch with nstreams HIP streams (1..64) of default
+ * priority. kkt_batch_add registers an analysed context with device
+ * pointers to its values (as kkt_factor), right-hand sides and solution (as
+ * kkt_solve); the pointers stay in use for the life of the batch and are read
+ * or written on every run. Instances are placed on the streams by estimated
+ * work, largest first onto the least loaded stream. */
+int kkt_batch_create(kkt_batch **b, int nstreams);
+int kkt_batch_add(kkt_batch *b, kkt_ctx *ctx, const double *A_vals, const double *C0_vals,
+                  const double *C1_vals, const double *corner_diag, const double *rhs,
+                  double *x, int64_t nrhs);
+
+/* kkt_batch_run: enqueue kkt_factor_async + kkt_solve_async(refine_steps) of
+ * every instance on its stream. Results are ready after kkt_batch_wait;
+ * per-instance status through kkt_factor_status and kkt_solve_status of the
+ * instance's context. use_graph (capture the sequence once into a HIP graph
+ * and replay it) is currently switched off and returns KKT_ERR_ARG. */
+int kkt_batch_run(kkt_batch *b, int refine_steps, int use_graph);
+int kkt_batch_wait(kkt_batch *b);
+/* stream index (0..nstreams-1) instance i runs on, -1 before the first run */
+int kkt_batch_stream_of(const kkt_batch *b, int64_t i);
+void kkt_batch_destroy(kkt_batch *b);
 
 /* kkt_schur: write the assembled Schur complement S of the last kkt_factor
  * (dense n_g x n_g, column-major, both triangles; n_g = N*Ns) into the

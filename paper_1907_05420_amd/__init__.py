@@ -87,11 +87,12 @@ def kkt_plan(nA, n_primal, N, Ns, colptr, rowind, C0p=None, C0i=None, C1p=None, 
 
 
 def kkt_create(stream=None, precision=KKT_FP64, refine_tol=1e-10, refine_max=20, pivot_eps=0.0, verbose=0,
-               refine_method=KKT_REFINE_FGMRES):
+               refine_method=KKT_REFINE_FGMRES, big_tile_rows=0):
     lib = load_library()
     o = kkt_default_options()
     o.precision, o.refine_tol, o.refine_max, o.pivot_eps, o.verbose = precision, refine_tol, refine_max, pivot_eps, verbose
     o.refine_method = refine_method
+    o.big_tile_rows = big_tile_rows
     h = C.c_void_p()
     if stream is None:
         import torch
@@ -166,6 +167,59 @@ def kkt_dominant_kernel(ctx):
     return {f: getattr(st, f) for f, _ in st._fields_}
 
 
+def kkt_set_stream(ctx, stream):
+    return _check(load_library().kkt_set_stream(ctx, C.c_void_p(stream)), "kkt_set_stream")
+
+
+def kkt_factor_async(ctx, A_vals, C0_vals=None, C1_vals=None, corner_diag=None, delta_w=0.0, delta_c=0.0):
+    return _check(load_library().kkt_factor_async(ctx, _ptr(A_vals), _ptr(C0_vals), _ptr(C1_vals), _ptr(corner_diag),
+                                                  float(delta_w), float(delta_c)), "kkt_factor_async")
+
+
+def kkt_factor_status(ctx):
+    inn = _abi.Inertia()
+    rc = _check(load_library().kkt_factor_status(ctx, C.byref(inn)), "kkt_factor_status")
+    return rc, {f: getattr(inn, f) for f, _ in inn._fields_}
+
+
+def kkt_solve_async(ctx, b, x, nrhs, steps):
+    return _check(load_library().kkt_solve_async(ctx, _ptr(b), _ptr(x), int(nrhs), int(steps)), "kkt_solve_async")
+
+
+def kkt_solve_status(ctx):
+    info = _abi.SolveInfo()
+    rc = _check(load_library().kkt_solve_status(ctx, C.byref(info)), "kkt_solve_status")
+    return rc, {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def kkt_batch_create(nstreams):
+    h = C.c_void_p()
+    _check(load_library().kkt_batch_create(C.byref(h), int(nstreams)), "kkt_batch_create")
+    return h
+
+
+def kkt_batch_add(batch, ctx, A_vals, C0_vals, C1_vals, corner_diag, rhs, x, nrhs):
+    return _check(load_library().kkt_batch_add(batch, ctx, _ptr(A_vals), _ptr(C0_vals), _ptr(C1_vals),
+                                               _ptr(corner_diag), _ptr(rhs), _ptr(x), int(nrhs)), "kkt_batch_add")
+
+
+def kkt_batch_run(batch, refine_steps, use_graph):
+    return _check(load_library().kkt_batch_run(batch, int(refine_steps), int(bool(use_graph))), "kkt_batch_run")
+
+
+def kkt_batch_wait(batch):
+    return _check(load_library().kkt_batch_wait(batch), "kkt_batch_wait")
+
+
+def kkt_batch_stream_of(batch, i):
+    return int(load_library().kkt_batch_stream_of(batch, int(i)))
+
+
+def kkt_batch_destroy(batch):
+    if batch:
+        load_library().kkt_batch_destroy(batch)
+
+
 def kkt_destroy(ctx):
     if ctx:
         load_library().kkt_destroy(ctx)
@@ -180,9 +234,10 @@ class Solver:
     n_primal, N, ns, colptr, rowind, C0_/C1_rowptr/colind)."""
 
     def __init__(self, inst, precision=KKT_FP64, stream=None, refine_tol=1e-10, refine_max=20, pivot_eps=0.0,
-                 verbose=0, refine_method=KKT_REFINE_FGMRES):
+                 verbose=0, refine_method=KKT_REFINE_FGMRES, big_tile_rows=0):
         self.inst = inst
-        self.ctx = kkt_create(stream, precision, refine_tol, refine_max, pivot_eps, verbose, refine_method)
+        self.ctx = kkt_create(stream, precision, refine_tol, refine_max, pivot_eps, verbose, refine_method,
+                              big_tile_rows)
         kkt_analyze(self.ctx, inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind,
                     inst.C0_rowptr, inst.C0_colind, inst.C1_rowptr, inst.C1_colind)
 
@@ -221,6 +276,60 @@ class Solver:
         if self.ctx:
             kkt_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent instances factored and solved together on several
+    streams, optionally through a captured HIP graph (kkt_batch_*). Each
+    instance keeps its own Solver (context); its device buffers (values,
+    right-hand sides, solutions) are fixed for the life of the batch."""
+
+    def __init__(self, instances, nstreams=4, precision=KKT_FP64, big_tile_rows=None):
+        import torch
+        rows = big_tile_rows if big_tile_rows is not None else [0] * len(instances)
+        self.solvers = [Solver(inst, precision=precision, big_tile_rows=r) for inst, r in zip(instances, rows)]
+        self.inputs = [device_inputs(inst) for inst in instances]
+        self.x = [torch.empty_like(d["b"]) for d in self.inputs]
+        self.h = None
+        self.restream(nstreams)
+
+    def restream(self, nstreams):
+        """Spread the same instances over a new set of nstreams streams."""
+        if self.h:
+            kkt_batch_destroy(self.h)
+        self.h = kkt_batch_create(nstreams)
+        self.nstreams = nstreams
+        for s, d, x in zip(self.solvers, self.inputs, self.x):
+            kkt_batch_add(self.h, s.ctx, d["vals"], d["C0"], d["C1"], d["corner"], d["b"], x, d["b"].shape[0])
+        self.ran_eager = False
+
+    def run(self, refine_steps=3, use_graph=False):
+        kkt_batch_run(self.h, refine_steps, use_graph and self.ran_eager)
+        self.ran_eager = True
+
+    def wait(self):
+        kkt_batch_wait(self.h)
+
+    def status(self):
+        out = []
+        for s in self.solvers:
+            rc_f, inn = kkt_factor_status(s.ctx)
+            rc_s, info = kkt_solve_status(s.ctx)
+            out.append(dict(rc_factor=rc_f, inertia=inn, rc_solve=rc_s, info=info))
+        return out
+
+    def close(self):
+        if self.h:
+            kkt_batch_destroy(self.h)
+            self.h = None
+        for s in self.solvers:
+            s.close()
 
     def __del__(self):
         try:

@@ -19,7 +19,8 @@ KKT_REFINE_CLASSIC = 1
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("pivot_eps", C.c_double), ("refine_tol", C.c_double),
-                ("refine_max", C.c_int), ("verbose", C.c_int), ("refine_method", C.c_int)]
+                ("refine_max", C.c_int), ("verbose", C.c_int), ("refine_method", C.c_int),
+                ("big_tile_rows", C.c_int)]
 
 
 class Structure(C.Structure):
@@ -66,6 +67,19 @@ SIGNATURES = {
     "kkt_enable_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "kkt_phase_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "kkt_dominant_kernel": (C.c_int, [C.c_void_p, C.POINTER(KernelStat)]),
+    "kkt_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "kkt_factor_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_double, C.c_double]),
+    "kkt_factor_status": (C.c_int, [C.c_void_p, C.POINTER(Inertia)]),
+    "kkt_solve_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
+    "kkt_solve_status": (C.c_int, [C.c_void_p, C.POINTER(SolveInfo)]),
+    "kkt_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    "kkt_batch_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_int64]),
+    "kkt_batch_run": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "kkt_batch_wait": (C.c_int, [C.c_void_p]),
+    "kkt_batch_stream_of": (C.c_int, [C.c_void_p, C.c_int64]),
+    "kkt_batch_destroy": (None, [C.c_void_p]),
     "kkt_destroy": (None, [C.c_void_p]),
     "kkt_strerror": (C.c_char_p, [C.c_int]),
 }

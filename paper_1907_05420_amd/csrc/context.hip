@@ -109,6 +109,11 @@ struct kkt_ctx {
     std::vector<hipEvent_t> kev;
     int64_t kcount = 0;
     kkt_kernel_stat kstat{};
+    // trailing matrices with at least this many rows use the 128x128 tiles
+    int big_rows = 512;
+    // last kkt_solve_async
+    int64_t async_nrhs = 0;
+    int async_steps = 0;
 };
 
 namespace {
@@ -153,7 +158,7 @@ void free_ws(kkt_ctx *ctx) {
 // panel's columns on the main stream, the rest on the side stream, so that the
 // latency-bound factorisation of the next panel overlaps the large update.
 void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl, std::vector<int32_t> &buf,
-                std::vector<StepHost> &steps, bool lookahead = false) {
+                std::vector<StepHost> &steps, bool lookahead, int big_rows) {
     int cmax = 0;
     for (int32_t f : fl) cmax = std::max(cmax, fd[f].c);
     auto sync = [&](int kind) {
@@ -205,7 +210,7 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
         // large trailing matrices take the 128x128 tile kernel
         int big = 0;
         for (int32_t f : fl)
-            if (fd[f].c > k && fd[f].m - std::min(pe, fd[f].c) >= 512) big = 1;
+            if (fd[f].c > k && fd[f].m - std::min(pe, fd[f].c) >= big_rows) big = 1;
         if (!lookahead) {
             add(big ? 4 : 3, k, pe);
             continue;
@@ -316,7 +321,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             if (S.nrow[t] > S.ncol[t])
                 for (int q0 = 0; q0 < S.ncol[t]; q0 += 64) { buf.push_back(t); buf.push_back(q0); ++lp.nrcol; }
         lp.step_begin = (int)ctx->steps.size();
-        plan_steps(fd, large, buf, ctx->steps);
+        plan_steps(fd, large, buf, ctx->steps, false, ctx->big_rows);
         lp.step_end = (int)ctx->steps.size();
     }
     if ((rc = upload(ctx, &ctx->d_tasks, buf))) return rc;
@@ -332,7 +337,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = upload(ctx, &ctx->d_sdS, sdS))) return rc;
         std::vector<int32_t> sbuf;
         ctx->ssteps.clear();
-        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true);
+        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true, ctx->big_rows);
         if ((rc = upload(ctx, &ctx->d_stasks, sbuf))) return rc;
     }
     // residual: full symmetric CSR of the pattern (caller order) and C^T by column
@@ -676,6 +681,8 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     if (opt) ctx->opt = *opt;
     if (ctx->opt.precision != KKT_FP64 && ctx->opt.precision != KKT_MIXED) { delete ctx; return KKT_ERR_ARG; }
     if (ctx->opt.refine_tol <= 0) ctx->opt.refine_tol = 1e-10;
+    if (ctx->opt.big_tile_rows < 0) { delete ctx; return KKT_ERR_ARG; }
+    ctx->big_rows = ctx->opt.big_tile_rows > 0 ? ctx->opt.big_tile_rows : 512;
     if (ctx->opt.refine_max < 0) ctx->opt.refine_max = 0;
     ctx->eps = ctx->opt.pivot_eps > 0 ? ctx->opt.pivot_eps : (ctx->opt.precision == KKT_MIXED ? 1e-10 : 1e-20);
     ctx->stream = (hipStream_t)stream;
@@ -736,15 +743,19 @@ extern "C" int kkt_stats(const kkt_ctx *ctx, kkt_symbolic_stats *st) {
     return KKT_OK;
 }
 
-extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals, const double *C1_vals,
-                          const double *corner_diag, double delta_w, double delta_c, kkt_inertia *out) {
+namespace {
+
+// enqueue the whole factorisation; with `check` the non-finite test is read
+// back (one synchronisation) before any state changes, else its result stays
+// on the device for kkt_factor_status
+int factor_enqueue(kkt_ctx *ctx, const double *A_vals, const double *C0_vals, const double *C1_vals,
+                   const double *corner_diag, double delta_w, double delta_c, bool check) {
     if (!ctx) return KKT_ERR_ARG;
     if (!ctx->analyzed) return KKT_ERR_ORDER;
     const Symbolic &S = ctx->sy;
     if (!A_vals || (S.Ns > 0 && (!C0_vals || !C1_vals))) return KKT_ERR_ARG;
     if (!std::isfinite(delta_w) || !std::isfinite(delta_c) || delta_w < 0 || delta_c < 0) return KKT_ERR_ARG;
     hipStream_t st = ctx->stream;
-    // reject non-finite input before any state changes
     launch_zero<int>(ctx->d_flag, 1, st);
     launch_check_finite(A_vals, S.nnzA * ctx->N, ctx->d_flag, st);
     if (S.Ns > 0) {
@@ -752,10 +763,12 @@ extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_v
         launch_check_finite(C1_vals, S.nnzC1, ctx->d_flag, st);
     }
     if (corner_diag && ctx->ng) launch_check_finite(corner_diag, ctx->ng, ctx->d_flag, st);
-    int flag = 0;
-    HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (flag) return KKT_ERR_NONFINITE;
+    if (check) {
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (flag) return KKT_ERR_NONFINITE;
+    }
     HIPCHK(hipMemcpyAsync(ctx->d_A, A_vals, 8 * S.nnzA * ctx->N, hipMemcpyDeviceToDevice, st));
     if (S.Ns > 0) {
         HIPCHK(hipMemcpyAsync(ctx->d_C0, C0_vals, 8 * S.nnzC0, hipMemcpyDeviceToDevice, st));
@@ -774,21 +787,13 @@ extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_v
     mark(ctx, 3);
     HIPCHK(hipGetLastError());
     ctx->factored = true;
-    if (ctx->timing) {
-        HIPCHK(hipStreamSynchronize(st));
-        ctx->times[0] = elapsed(ctx, 0, 1);
-        ctx->times[1] = ctx->ng ? elapsed(ctx, 1, 2) : 0.0;
-        ctx->times[2] = ctx->ng ? elapsed(ctx, 2, 3) : 0.0;
-        double kms = 0.0;
-        for (int64_t j = 0; j < ctx->kcount; ++j) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ctx->kev[2 * j], ctx->kev[2 * j + 1]) == hipSuccess) kms += ms;
-        }
-        ctx->kstat.launches = ctx->kcount;
-        ctx->kstat.total_ms = kms;
-        ctx->times[4] = kms;
-    }
-    if (!out) return KKT_OK;
+    return KKT_OK;
+}
+
+// read the pivot counters of the last factorisation (synchronises)
+int factor_readback(kkt_ctx *ctx, kkt_inertia *out) {
+    hipStream_t st = ctx->stream;
+    const Symbolic &S = ctx->sy;
     std::vector<int64_t> cnt(4 * (ctx->N + 1), 0), cs(4, 0);
     HIPCHK(hipMemcpyAsync(cnt.data(), ctx->d_cnt, 8 * 4 * ctx->N, hipMemcpyDeviceToHost, st));
     if (ctx->ng) HIPCHK(hipMemcpyAsync(cs.data(), ctx->d_cntS, 8 * 4, hipMemcpyDeviceToHost, st));
@@ -806,9 +811,56 @@ extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_v
     in.n_perturbed += cs[3];
     const int64_t epos = ctx->N * S.n_primal, eneg = ctx->N * (S.nA - S.n_primal) + ctx->ng;
     in.inertia_ok = (in.n_pos == epos && in.n_neg == eneg && in.n_zero == 0) ? 1 : 0;
-    *out = in;
+    if (out) *out = in;
     if (!in.inertia_ok) return KKT_WARN_INERTIA;
     if (in.n_perturbed) return KKT_WARN_PERTURBED;
+    return KKT_OK;
+}
+
+}  // namespace
+
+extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals, const double *C1_vals,
+                          const double *corner_diag, double delta_w, double delta_c, kkt_inertia *out) {
+    int rc = factor_enqueue(ctx, A_vals, C0_vals, C1_vals, corner_diag, delta_w, delta_c, true);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    if (ctx->timing) {
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->times[0] = elapsed(ctx, 0, 1);
+        ctx->times[1] = ctx->ng ? elapsed(ctx, 1, 2) : 0.0;
+        ctx->times[2] = ctx->ng ? elapsed(ctx, 2, 3) : 0.0;
+        double kms = 0.0;
+        for (int64_t j = 0; j < ctx->kcount; ++j) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ctx->kev[2 * j], ctx->kev[2 * j + 1]) == hipSuccess) kms += ms;
+        }
+        ctx->kstat.launches = ctx->kcount;
+        ctx->kstat.total_ms = kms;
+        ctx->times[4] = kms;
+    }
+    if (!out) return KKT_OK;
+    return factor_readback(ctx, out);
+}
+
+extern "C" int kkt_factor_async(kkt_ctx *ctx, const double *A_vals, const double *C0_vals, const double *C1_vals,
+                                const double *corner_diag, double delta_w, double delta_c) {
+    if (ctx && ctx->timing) return KKT_ERR_ARG;  // timing synchronises
+    return factor_enqueue(ctx, A_vals, C0_vals, C1_vals, corner_diag, delta_w, delta_c, false);
+}
+
+extern "C" int kkt_factor_status(kkt_ctx *ctx, kkt_inertia *out) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->factored) return KKT_ERR_ORDER;
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (flag) return KKT_ERR_NONFINITE;
+    return factor_readback(ctx, out);
+}
+
+extern "C" int kkt_set_stream(kkt_ctx *ctx, void *stream) {
+    if (!ctx) return KKT_ERR_ARG;
+    ctx->stream = (hipStream_t)stream;
     return KKT_OK;
 }
 
@@ -995,6 +1047,60 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
         info->fallback_used = 0;
     }
     return rs.status;
+}
+
+// solve + `steps` classic refinement steps, entirely on the stream; the norms
+// of the final residual stay on the device for kkt_solve_status
+extern "C" int kkt_solve_async(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->analyzed || !ctx->factored) return KKT_ERR_ORDER;
+    if (!b || !x || b == x || nrhs < 1 || nrhs > 64 || steps < 0 || ctx->timing) return KKT_ERR_ARG;
+    if (ctx->ws_nrhs < nrhs) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIPCHK(hipStreamIsCapturing(ctx->stream, &cs));
+        if (cs != hipStreamCaptureStatusNone) return KKT_ERR_ARG;  // workspace must exist before capture
+        int rc = ensure_ws(ctx, nrhs);
+        if (rc) return rc;
+    }
+    hipStream_t st = ctx->stream;
+    const bool mixed = ctx->opt.precision == KKT_MIXED;
+    int rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
+    if (rc) return rc;
+    ResidualArgs ra = residual_args(ctx, nrhs);
+    for (int k = 0; k < steps; ++k) {
+        launch_residual(ra, b, x, ctx->d_res, ctx->d_work, ctx->d_norms, st);
+        rc = mixed ? solve_once<float>(ctx, ctx->d_res, ctx->d_dx, nrhs) : solve_once<double>(ctx, ctx->d_res, ctx->d_dx, nrhs);
+        if (rc) return rc;
+        launch_axpy(x, ctx->d_dx, ctx->ntot * nrhs, st);
+    }
+    launch_residual(ra, b, x, ctx->d_res, ctx->d_work, ctx->d_norms, st);
+    ctx->async_nrhs = nrhs;
+    ctx->async_steps = steps;
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+extern "C" int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (ctx->async_nrhs < 1) return KKT_ERR_ORDER;
+    const int64_t nrhs = ctx->async_nrhs;
+    std::vector<double> nh(4 * nrhs);
+    HIPCHK(hipMemcpyAsync(nh.data(), ctx->d_norms, 8 * 4 * nrhs, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double rel = 0.0, omega = 0.0;
+    for (int64_t k = 0; k < nrhs; ++k) {
+        const double rb = nh[4 * k + 1] > 0 ? nh[4 * k + 0] / nh[4 * k + 1] : nh[4 * k + 0];
+        rel = std::max(rel, rb);
+        omega = std::max(omega, nh[4 * k + 2]);
+    }
+    if (info) {
+        info->refine_iters = ctx->async_steps;
+        info->rel_res = rel;
+        info->omega = omega;
+        info->fallback_used = 0;
+    }
+    if (!std::isfinite(rel) || rel > ctx->opt.refine_tol) return KKT_WARN_REFINE;
+    return KKT_OK;
 }
 
 extern "C" int kkt_schur(kkt_ctx *ctx, double *S_out) {

@@ -16,6 +16,7 @@ extern "C" void kkt_default_options(kkt_options *opt) {
     opt->refine_max = 20;
     opt->verbose = 0;
     opt->refine_method = KKT_REFINE_FGMRES;
+    opt->big_tile_rows = 0;
 }
 
 extern "C" const char *kkt_strerror(int code) {
