@@ -574,7 +574,9 @@ __global__ __launch_bounds__(256) void k_dense_gemv(const double *S, int64_t ng,
     const int64_t i = (int64_t)blockIdx.x * 64 + a;
     const int qa = 64 * g;
     const int ncq = max(1, min(64, ncol - qa));
-    const double *rowp = S + row0 + min(i, nrow - 1) + (col0 + qa) * ng;
+    // groups past the last column (a ragged last block) read, and then
+    // ignore, that column: every address stays inside the factor
+    const double *rowp = S + row0 + min(i, nrow - 1) + (col0 + min(qa, ncol - 1)) * ng;
     double l[64];
 #pragma unroll
     for (int u = 0; u < 64; ++u) l[u] = rowp[(int64_t)min(u, ncq - 1) * ng];
