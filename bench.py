@@ -242,11 +242,9 @@ def main():
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     if args.workload == "uneven64":
-        # switched off: its first run of the 64-instance batch on two streams
-        # ended in a GPU memory fault whose cause has not been found yet
-        print("bench.py --workload uneven64 is switched off (GPU memory fault under investigation)",
-              file=sys.stderr)
-        return 3
+        res = bench_batch(args, log)
+        print(json.dumps(res), flush=True)
+        return 0
     inst = kktgen.make_workload(2)
     rng = np.random.default_rng(kktgen.seed_for(2, 9))
     vals2 = kktgen.redraw_barrier(inst, rng)

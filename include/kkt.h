@@ -140,7 +140,9 @@ int kkt_create(kkt_ctx **ctx, void *stream, const kkt_options *opt);
  * [C_1; C_0] appended last, the supernodal elimination tree, front row sets
  * and extend-add maps; then allocates device factors and workspace. Host
  * time only plus one host->device copy of the maps. May be called again
- * (re-analysis frees the previous state). */
+ * (re-analysis frees the previous state). Returns KKT_ERR_ARG when a front
+ * has more than 16 320 rows or 11 712 pivots (the triangular solves keep a
+ * front's vector in the 160 KiB of LDS of one workgroup) or N*Ns > 46 000. */
 int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s);
 
 /* Exact device bytes the context holds after kkt_analyze (for admission). */

@@ -714,7 +714,13 @@ extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
         if (ctx->opt.verbose) std::fprintf(stderr, "kkt_analyze: %s\n", err.c_str());
         return KKT_ERR_STRUCT;
     }
-    if (S.max_front > 20000 || (s->N * s->Ns) > 46000) return KKT_ERR_ARG;  // 32-bit launch/index limits
+    // fronts whose solve vectors fit in LDS; 32-bit launch and index limits of S
+    if (S.max_front > MAX_FRONT_ROWS || S.max_pivots > MAX_FRONT_PIVOTS || (s->N * s->Ns) > 46000) {
+        if (ctx->opt.verbose)
+            std::fprintf(stderr, "kkt_analyze: front of %lld rows / %lld pivots or Schur size %lld over the limits\n",
+                         (long long)S.max_front, (long long)S.max_pivots, (long long)(s->N * s->Ns));
+        return KKT_ERR_ARG;
+    }
     (void)hipStreamSynchronize(ctx->stream);
     free_ws(ctx);
     free_static(ctx);

@@ -681,7 +681,7 @@ void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t 
 static int rhs_block(int64_t nrhs, int rows, size_t fixed) {
     int rb = (int)std::min<int64_t>(nrhs, RB);
     if (rb == 3) rb = 4;
-    while (rb > 1 && (size_t)rows * rb * 8 + fixed > 150 * 1024) rb /= 2;
+    while (rb > 1 && (size_t)rows * rb * 8 + fixed > (size_t)LDS_BYTES) rb /= 2;
     return rb;
 }
 

@@ -19,6 +19,14 @@ struct ScatterArgs {
     const int64_t *c0map, *c1map;
 };
 
+// LDS of one workgroup (gfx950). The triangular solves of a large front keep
+// the front's vector in LDS: the forward pass its m rows beside a 64x65
+// staging tile, the backward pass its c pivot rows beside a 128x64 tile and
+// the partial sums, at one right-hand side per pass at the limit.
+constexpr int64_t LDS_BYTES = 160 * 1024;
+constexpr int64_t MAX_FRONT_ROWS = (LDS_BYTES - 8 * 64 * 65) / 8;
+constexpr int64_t MAX_FRONT_PIVOTS = (LDS_BYTES - 8 * (129 * 64 + 8 * 64)) / 8;
+
 struct TreeArgs {
     const int32_t *cptr, *clist;
     const int64_t *relptr;

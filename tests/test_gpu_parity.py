@@ -71,6 +71,11 @@ SMALL = [
     dict(nb=15, nextra=8, ng=4, ns=2, N=5, nrhs=1, seed=4, corner="zero"),
     dict(nb=70, nextra=40, ng=12, ns=9, N=9, nrhs=3, seed=6),        # n_g = 81: two Schur steps, ragged
     dict(nb=160, nextra=90, ng=30, ns=12, N=7, nrhs=2, seed=8),      # several large fronts
+    # Schur dimensions around the 256-wide blocks of the dense solves
+    dict(nb=60, nextra=30, ng=8, ns=26, N=12, nrhs=2, seed=10),      # n_g = 312: last block 56 wide
+    dict(nb=70, nextra=30, ng=8, ns=43, N=12, nrhs=1, seed=12),      # n_g = 516: last block 4 wide
+    dict(nb=40, nextra=20, ng=6, ns=16, N=32, nrhs=1, seed=11),      # n_g = 512: two whole blocks
+    dict(nb=50, nextra=25, ng=8, ns=24, N=20, nrhs=3, seed=13),      # n_g = 480: last block 224 wide
 ]
 
 
