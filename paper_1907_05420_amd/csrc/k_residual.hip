@@ -5,95 +5,202 @@
 
 namespace kkt {
 
-// border rows: r_g[m] = b_C[m] - C x_g[m] - C_1 x_m - sum_{n<m} C_0 x_n ; also
-// the suffix sums sg[n] = sum_{m>n} x_g[m] used by the period rows.
-__global__ void k_res_border(ResidualArgs ra, const double *b, const double *x, double *r, double *sg,
-                             double *norms) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    if (s >= ra.Ns) return;
+// inclusive scan of buf[0..255] over the workgroup (Hillis-Steele)
+__device__ inline void block_scan256(double *buf, int tid) {
+    for (int off = 1; off < 256; off <<= 1) {
+        double v = buf[tid];
+        if (tid >= off) v += buf[tid - off];
+        __syncthreads();
+        buf[tid] = v;
+        __syncthreads();
+    }
+}
+
+__device__ inline double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Border rows, one workgroup per (storage unit s, right-hand side k), one
+// thread per period m (chunks of 256 periods with carries):
+//   r_g[m] = b_C[m] - C x_g[m] - C_1 x_m - sum_{n<m} C_0 x_n   (Eq. B12N)
+// and the suffix sums sg[n] = sum_{m>n} x_g[m] used by the period rows. The
+// sums over periods are workgroup scans.
+__global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const double *b, const double *x, double *r,
+                                                    double *sg, double *norms) {
+    __shared__ double sc[256], sa[256];
+    __shared__ double wred[4];
+    const int64_t s = blockIdx.x;
+    const int k = blockIdx.y, tid = threadIdx.x;
     const int64_t ng = ra.N * ra.Ns;
     const double *xk = x + (int64_t)k * ra.ntot;
     const double *xg = xk + ra.N * ra.nA;
-    double acc0 = 0.0, abs0 = 0.0, wmax = 0.0;
-    for (int64_t m = 0; m < ra.N; ++m) {
-        const int64_t g = m * ra.Ns + s;
-        const double *xm = xk + m * ra.nA;
-        double bc = b ? b[(int64_t)k * ra.ntot + ra.N * ra.nA + g] : 0.0;
+    const int64_t c1a = ra.c1p[s], c1b = ra.c1p[s + 1], c0a = ra.c0p[s], c0b = ra.c0p[s + 1];
+    double carry = 0.0, carry_abs = 0.0, wmax = 0.0;
+    for (int64_t m0 = 0; m0 < ra.N; m0 += 256) {
+        const int64_t m = m0 + tid;
+        const bool on = m < ra.N;
+        const int64_t mc = on ? m : ra.N - 1;
+        const int64_t g = mc * ra.Ns + s;
+        const double *xm = xk + mc * ra.nA;
+        const double bc = b ? b[(int64_t)k * ra.ntot + ra.N * ra.nA + g] : 0.0;
         double acc = bc, ab = fabs(bc);
-        if (ra.corner) { double t = ra.corner[g] * xg[g]; acc -= t; ab += fabs(t); }
-        for (int64_t e = ra.c1p[s]; e < ra.c1p[s + 1]; ++e) {
-            double t = ra.C1v[e] * xm[ra.c1i[e]];
+        if (ra.corner) {
+            const double t = ra.corner[g] * xg[g];
             acc -= t;
             ab += fabs(t);
         }
-        acc -= acc0;
-        ab += abs0;
-        r[(int64_t)k * ra.ntot + ra.N * ra.nA + g] = b ? acc : -acc;
-        if (ab > 0.0) wmax = fmax(wmax, fabs(acc) / ab);
-        else if (acc != 0.0) wmax = INFINITY;
-        for (int64_t e = ra.c0p[s]; e < ra.c0p[s + 1]; ++e) {
-            double t = ra.C0v[e] * xm[ra.c0i[e]];
-            acc0 += t;
-            abs0 += fabs(t);
+        for (int64_t e = c1a; e < c1b; ++e) {
+            const double t = ra.C1v[e] * xm[ra.c1i[e]];
+            acc -= t;
+            ab += fabs(t);
         }
+        double c0 = 0.0, a0 = 0.0;
+        for (int64_t e = c0a; e < c0b; ++e) {
+            const double t = ra.C0v[e] * xm[ra.c0i[e]];
+            c0 += t;
+            a0 += fabs(t);
+        }
+        sc[tid] = on ? c0 : 0.0;
+        sa[tid] = on ? a0 : 0.0;
+        __syncthreads();
+        block_scan256(sc, tid);
+        block_scan256(sa, tid);
+        // exclusive sums over the earlier periods
+        acc -= carry + (tid > 0 ? sc[tid - 1] : 0.0);
+        ab += carry_abs + (tid > 0 ? sa[tid - 1] : 0.0);
+        if (on) {
+            r[(int64_t)k * ra.ntot + ra.N * ra.nA + g] = b ? acc : -acc;
+            if (ab > 0.0) wmax = fmax(wmax, fabs(acc) / ab);
+            else if (acc != 0.0) wmax = INFINITY;
+        }
+        carry += sc[255];
+        carry_abs += sa[255];
+        __syncthreads();
     }
-    double acc = 0.0;
-    for (int64_t n = ra.N - 1; n >= 0; --n) {
-        sg[(int64_t)k * ng + n * ra.Ns + s] = acc;
-        acc += xg[n * ra.Ns + s];
+    // suffix sums of x_g over the periods, from the last chunk back
+    double scarry = 0.0;
+    const int64_t nch = (ra.N + 255) / 256;
+    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+        const int64_t m = ch * 256 + (255 - tid);  // reversed: thread 0 holds the last period
+        const bool on = m < ra.N;
+        const double v = on ? xg[m * ra.Ns + s] : 0.0;
+        sc[tid] = v;
+        __syncthreads();
+        block_scan256(sc, tid);
+        if (on) sg[(int64_t)k * ng + m * ra.Ns + s] = scarry + (tid > 0 ? sc[tid - 1] : 0.0);
+        scarry += sc[255];
+        __syncthreads();
     }
-    if (norms) atomic_max_nonneg(norms + 4 * k + 2, wmax);
+    if (norms) {
+        wmax = wave_max(wmax);
+        if ((tid & 63) == 0) wred[tid >> 6] = wmax;
+        __syncthreads();
+        if (tid == 0) atomic_max_nonneg(norms + 4 * k + 2, fmax(fmax(wred[0], wred[1]), fmax(wred[2], wred[3])));
+    }
 }
 
+// Period rows, one thread per row i of A_n (all right-hand sides of a pass
+// together, so that the row's indices and values are read once per pass):
+//   r_n = b_n - (A_n + shifts) x_n - C_1^T x_g[n] - C_0^T sg[n]
+// The row's entries are loaded in batches of RES_B from clamped addresses and
+// masked afterwards.
+constexpr int RES_B = 8;
+template <int RBT>
 __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const double *b, const double *x, double *r,
                                                      const double *sg, double *wpart) {
-    __shared__ double red[256];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ double wred[4 * RBT];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
     const int n = blockIdx.y;
+    const bool on = i < ra.nA;
+    const int64_t ic = on ? i : ra.nA - 1;
     const int64_t ng = ra.N * ra.Ns;
-    const int64_t e0 = i < ra.nA ? ra.rp[i] : 0, e1 = i < ra.nA ? ra.rp[i + 1] : 0;
+    const int64_t e0 = ra.rp[ic], e1 = on ? ra.rp[ic + 1] : e0;
     const double *An = ra.A + (int64_t)n * ra.nnz;
-    for (int k = 0; k < ra.nrhs; ++k) {
-        double w = 0.0;
-        if (i < ra.nA) {
-            const double *xk = x + (int64_t)k * ra.ntot;
-            const double *xn = xk + (int64_t)n * ra.nA;
-            const double *xg = xk + ra.N * ra.nA;
-            const int64_t row = (int64_t)k * ra.ntot + (int64_t)n * ra.nA + i;
-            double acc = b ? b[row] : 0.0, ab = fabs(acc);
-#pragma unroll 4
-            for (int64_t e = e0; e < e1; ++e) {
-                const int32_t j = ra.ci[e];
-                double a = An[ra.vi[e]];
-                if (j == i) a += i < ra.n_primal ? ra.dw : -ra.dc;
-                const double t = a * xn[j];
-                acc -= t;
-                ab += fabs(t);
-            }
-            for (int64_t e = ra.c1tp[i]; e < ra.c1tp[i + 1]; ++e) {
-                const double t = ra.C1v[ra.c1tk[e]] * xg[(int64_t)n * ra.Ns + ra.c1ts[e]];
-                acc -= t;
-                ab += fabs(t);
-            }
-            for (int64_t e = ra.c0tp[i]; e < ra.c0tp[i + 1]; ++e) {
-                const double t = ra.C0v[ra.c0tk[e]] * sg[(int64_t)k * ng + (int64_t)n * ra.Ns + ra.c0ts[e]];
-                acc -= t;
-                ab += fabs(t);
-            }
-            r[row] = b ? acc : -acc;
-            if (ab > 0.0) w = fabs(acc) / ab;
-            else if (acc != 0.0) w = INFINITY;
+    const double shift = ic < ra.n_primal ? ra.dw : -ra.dc;
+    for (int k0 = 0; k0 < ra.nrhs; k0 += RBT) {
+        const int nr = (int)min((int64_t)RBT, ra.nrhs - k0);
+        const double *xn[RBT];
+        double acc[RBT], ab[RBT];
+#pragma unroll
+        for (int q = 0; q < RBT; ++q) {
+            const int kk = k0 + min(q, nr - 1);
+            xn[q] = x + (int64_t)kk * ra.ntot + (int64_t)n * ra.nA;
+            acc[q] = b ? b[(int64_t)kk * ra.ntot + (int64_t)n * ra.nA + ic] : 0.0;
+            ab[q] = fabs(acc[q]);
         }
-        red[threadIdx.x] = w;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        for (int64_t eb = e0; eb < e1; eb += RES_B) {
+            int32_t j[RES_B];
+            int64_t v[RES_B];
+#pragma unroll
+            for (int u = 0; u < RES_B; ++u) {
+                const int64_t e = min(eb + u, e1 - 1);
+                j[u] = ra.ci[e];
+                v[u] = ra.vi[e];
+            }
+            double a[RES_B], xv[RES_B][RBT];
+#pragma unroll
+            for (int u = 0; u < RES_B; ++u) {
+                a[u] = An[v[u]];
+#pragma unroll
+                for (int q = 0; q < RBT; ++q) xv[u][q] = xn[q][j[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < RES_B; ++u) {
+                const double au = eb + u < e1 ? a[u] + (j[u] == ic ? shift : 0.0) : 0.0;
+#pragma unroll
+                for (int q = 0; q < RBT; ++q) {
+                    const double t = au * xv[u][q];
+                    acc[q] -= t;
+                    ab[q] += fabs(t);
+                }
+            }
+        }
+        const int64_t t1a = on ? ra.c1tp[ic] : 0, t1b = on ? ra.c1tp[ic + 1] : 0;
+        for (int64_t e = t1a; e < t1b; ++e) {
+            const double cv = ra.C1v[ra.c1tk[e]];
+            const int64_t gi = (int64_t)n * ra.Ns + ra.c1ts[e];
+#pragma unroll
+            for (int q = 0; q < RBT; ++q) {
+                const double t = cv * x[(int64_t)(k0 + min(q, nr - 1)) * ra.ntot + ra.N * ra.nA + gi];
+                acc[q] -= t;
+                ab[q] += fabs(t);
+            }
+        }
+        const int64_t t0a = on ? ra.c0tp[ic] : 0, t0b = on ? ra.c0tp[ic + 1] : 0;
+        for (int64_t e = t0a; e < t0b; ++e) {
+            const double cv = ra.C0v[ra.c0tk[e]];
+            const int64_t gi = (int64_t)n * ra.Ns + ra.c0ts[e];
+#pragma unroll
+            for (int q = 0; q < RBT; ++q) {
+                const double t = cv * sg[(int64_t)(k0 + min(q, nr - 1)) * ng + gi];
+                acc[q] -= t;
+                ab[q] += fabs(t);
+            }
+        }
+        double w[RBT];
+#pragma unroll
+        for (int q = 0; q < RBT; ++q) {
+            w[q] = 0.0;
+            if (on && q < nr) {
+                r[(int64_t)(k0 + q) * ra.ntot + (int64_t)n * ra.nA + i] = b ? acc[q] : -acc[q];
+                if (ab[q] > 0.0) w[q] = fabs(acc[q]) / ab[q];
+                else if (acc[q] != 0.0) w[q] = INFINITY;
+            }
+        }
+        if (wpart) {
+#pragma unroll
+            for (int q = 0; q < RBT; ++q) {
+                const double wm = wave_max(w[q]);
+                if ((tid & 63) == 0) wred[q * 4 + (tid >> 6)] = wm;
+            }
+            __syncthreads();
+            if (tid < nr)
+                wpart[(int64_t)(k0 + tid) * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] =
+                    fmax(fmax(wred[tid * 4 + 0], wred[tid * 4 + 1]), fmax(wred[tid * 4 + 2], wred[tid * 4 + 3]));
             __syncthreads();
         }
-        if (threadIdx.x == 0 && wpart)
-            wpart[(int64_t)k * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
-        __syncthreads();
     }
 }
 
@@ -162,6 +269,14 @@ int64_t residual_work(int64_t N, int64_t nA, int64_t Ns, int64_t nrhs) {
     return N * Ns * nrhs + 2 * NPART * nrhs + ((nA + 255) / 256) * N * nrhs + 8;
 }
 
+static void launch_res_periods(const ResidualArgs &ra, const double *b, const double *x, double *r, const double *sg,
+                               double *wpart, hipStream_t st) {
+    const dim3 grid((unsigned)((ra.nA + 255) / 256), (unsigned)ra.N);
+    if (ra.nrhs >= 3) hipLaunchKernelGGL(k_res_periods<4>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
+    else if (ra.nrhs == 2) hipLaunchKernelGGL(k_res_periods<2>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
+    else hipLaunchKernelGGL(k_res_periods<1>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
+}
+
 // work must hold residual_work() doubles
 void launch_residual(const ResidualArgs &ra, const double *b, const double *x, double *r, double *work,
                      double *norms, hipStream_t st) {
@@ -171,10 +286,9 @@ void launch_residual(const ResidualArgs &ra, const double *b, const double *x, d
     double *wpart = part + 2 * NPART * ra.nrhs;
     const int64_t nw = ((ra.nA + 255) / 256) * ra.N;
     if (ra.Ns > 0)
-        hipLaunchKernelGGL(k_res_border, dim3((unsigned)((ra.Ns + 127) / 128), (unsigned)ra.nrhs), dim3(128), 0, st,
-                           ra, b, x, r, sg, norms);
-    hipLaunchKernelGGL(k_res_periods, dim3((unsigned)((ra.nA + 255) / 256), (unsigned)ra.N), dim3(256), 0, st, ra, b,
-                       x, r, sg, wpart);
+        hipLaunchKernelGGL(k_res_border, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra, b, x, r, sg,
+                           norms);
+    launch_res_periods(ra, b, x, r, sg, wpart, st);
     hipLaunchKernelGGL(k_norm_partial, dim3(NPART, (unsigned)ra.nrhs), dim3(256), 0, st, r, b, ra.ntot, part);
     hipLaunchKernelGGL(k_norm_final, dim3((unsigned)ra.nrhs), dim3(256), 0, st, part, wpart, nw, norms);
 }
@@ -183,10 +297,9 @@ void launch_residual(const ResidualArgs &ra, const double *b, const double *x, d
 void launch_matvec(const ResidualArgs &ra, const double *x, double *y, double *work, hipStream_t st) {
     double *sg = work;
     if (ra.Ns > 0)
-        hipLaunchKernelGGL(k_res_border, dim3((unsigned)((ra.Ns + 127) / 128), (unsigned)ra.nrhs), dim3(128), 0, st,
-                           ra, (const double *)nullptr, x, y, sg, (double *)nullptr);
-    hipLaunchKernelGGL(k_res_periods, dim3((unsigned)((ra.nA + 255) / 256), (unsigned)ra.N), dim3(256), 0, st, ra,
-                       (const double *)nullptr, x, y, sg, (double *)nullptr);
+        hipLaunchKernelGGL(k_res_border, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra,
+                           (const double *)nullptr, x, y, sg, (double *)nullptr);
+    launch_res_periods(ra, nullptr, x, y, sg, nullptr, st);
 }
 
 __global__ void k_axpy(double *x, const double *dx, int64_t n) {
