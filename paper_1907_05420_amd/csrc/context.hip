@@ -158,7 +158,7 @@ void free_ws(kkt_ctx *ctx) {
 // panel's columns on the main stream, the rest on the side stream, so that the
 // latency-bound factorisation of the next panel overlaps the large update.
 void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl, std::vector<int32_t> &buf,
-                std::vector<StepHost> &steps, bool lookahead, int big_rows) {
+                std::vector<StepHost> &steps, bool lookahead, int big_rows, int outer_w, int inner_w) {
     int cmax = 0;
     for (int32_t f : fl) cmax = std::max(cmax, fd[f].c);
     auto sync = [&](int kind) {
@@ -193,31 +193,42 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
         s.ntasks = acc;
         steps.push_back(s);
     };
-    for (int k = 0; k < cmax; k += OUTER_W) {
-        const int pe = k + OUTER_W;
+    // large trailing matrices (rows below column `col`) take the 128x128 tile kernel
+    auto big_from = [&](int t0, int col) {
+        for (int32_t f : fl)
+            if (fd[f].c > t0 && fd[f].m - std::min(col, fd[f].c) >= big_rows) return 1;
+        return 0;
+    };
+    for (int k = 0; k < cmax; k += outer_w) {
+        const int pe = k + outer_w;
         // the panel's columns were brought up to date by the main stream's
         // update from the previous panel, after the side stream had finished
         // the updates of the panels before it; the side stream's update from
-        // the previous panel (columns beyond this panel) runs meanwhile
-        for (int j0 = k; j0 < std::min(pe, cmax); j0 += 64) {
-            add(0, j0, pe);
-            add(1, j0, pe);
-            add(2, j0, pe);
+        // the previous panel (columns beyond this panel) runs meanwhile.
+        // Inside the panel, sub-panels of inner_w columns: 64-column steps
+        // update only their own sub-panel, and each finished sub-panel updates
+        // the next sub-panel's columns in one rank-inner_w product.
+        for (int s0 = k; s0 < std::min(pe, cmax); s0 += inner_w) {
+            const int se = std::min(s0 + inner_w, pe);
+            for (int j0 = s0; j0 < std::min(se, cmax); j0 += 64) {
+                add(0, j0, se);
+                add(1, j0, se);
+                add(2, j0, se);
+            }
+            if (se < std::min(pe, cmax)) add(big_from(s0, se) ? 4 : 3, s0, se, 1, 0);
         }
         // the next panel's columns: the side stream's update from the
         // previous panel must be done before this panel's update of them
         if (lookahead && k > 0) sync(SYNC_TO_MAIN);
-        // large trailing matrices take the 128x128 tile kernel
-        int big = 0;
-        for (int32_t f : fl)
-            if (fd[f].c > k && fd[f].m - std::min(pe, fd[f].c) >= big_rows) big = 1;
+        const int big = big_from(k, pe);
         if (!lookahead) {
             add(big ? 4 : 3, k, pe);
             continue;
         }
         add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
         sync(SYNC_TO_SIDE);
-        add(5, k, pe, 0, 1);            // inverse of the panel's diagonal block (dense solves)
+        for (int j0 = k; j0 < std::min(pe, cmax); j0 += INV_W)
+            add(5, j0, pe, 0, 1);       // inverses of the panel's diagonal blocks (dense solves)
         add(big ? 4 : 3, k, pe, 2, 1);  // the rest, side stream
     }
     if (lookahead) sync(SYNC_TO_MAIN);
@@ -321,7 +332,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             if (S.nrow[t] > S.ncol[t])
                 for (int q0 = 0; q0 < S.ncol[t]; q0 += 64) { buf.push_back(t); buf.push_back(q0); ++lp.nrcol; }
         lp.step_begin = (int)ctx->steps.size();
-        plan_steps(fd, large, buf, ctx->steps, false, ctx->big_rows);
+        plan_steps(fd, large, buf, ctx->steps, false, ctx->big_rows, OUTER_W, OUTER_W);
         lp.step_end = (int)ctx->steps.size();
     }
     if ((rc = upload(ctx, &ctx->d_tasks, buf))) return rc;
@@ -337,7 +348,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = upload(ctx, &ctx->d_sdS, sdS))) return rc;
         std::vector<int32_t> sbuf;
         ctx->ssteps.clear();
-        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true, ctx->big_rows);
+        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true, ctx->big_rows, SCHUR_OUTER_W, INV_W);
         if ((rc = upload(ctx, &ctx->d_stasks, sbuf))) return rc;
     }
     // residual: full symmetric CSR of the pattern (caller order) and C^T by column

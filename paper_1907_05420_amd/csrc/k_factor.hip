@@ -528,7 +528,8 @@ __host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int
         g.K = cend - t0;
         g.lo = cend;
         g.qhi = m;
-        const int nxt = pe + OUTER_W < m ? pe + OUTER_W : m;
+        // the next outer panel has the width of this one (pe - t0)
+        const int nxt = pe + (pe - t0) < m ? pe + (pe - t0) : m;
         if (win == 1) g.qhi = nxt;
         else if (win == 2) g.lo = nxt;
     }
@@ -644,8 +645,8 @@ __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const F
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
-    // pivots D of the K range, staged once (K <= OUTER_W)
-    __shared__ T sD[OUTER_W];
+    // pivots D of the K range, staged once (K <= MAX_OUTER_W)
+    __shared__ T sD[MAX_OUTER_W];
     for (int k = tid; k < g.K; k += 256) sD[k] = P[(t0 + k) + (int64_t)(t0 + k) * m];
     // loader: row = tid % 128, k = tid / 128 + 2 j (j < 8); clamped addresses,
     // no arithmetic on the loaded values until they are stored to LDS, so the
@@ -730,7 +731,7 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
     const FrontDesc d = sd[fl[blockIdx.x]];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m = d.m;
-    const int nbw = min(OUTER_W, d.c - j0);
+    const int nbw = min(INV_W, d.c - j0);
     const int nsb = (nbw + 63) / 64;
     double *P = fa.L + d.Loff;
     const int row = tid & 63, kk = tid >> 6;

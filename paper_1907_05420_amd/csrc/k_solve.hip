@@ -560,7 +560,7 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
 // one, so that both L (forward) and L^T (backward) are read down columns.
 // Steps go over 256-wide blocks: forward y_J = X_J v_J then v_below -=
 // L[below, J] y_J; backward x_J = X_J^T z_J then z_above -= L[J, above]^T x_J.
-constexpr int DBW = 256;
+constexpr int DBW = INV_W;  // the dense factor stores the inverses of its INV_W-wide diagonal blocks
 
 // out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow:
 // 64 rows per workgroup, four groups of 64 columns, reduced at the end. All

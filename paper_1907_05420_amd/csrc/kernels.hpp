@@ -36,20 +36,24 @@ struct TreeArgs {
 };
 
 // One launch of the blocked right-looking factorisation over a group of large
-// fronts. Pivot columns go in 64-wide blocks inside outer panels of OUTER_W
-// columns: per block the pivot block (kind 0), the rows below it (kind 1) and
-// the rest of the outer panel (kind 2); after each outer panel one trailing
-// update of rank <= OUTER_W (kind 3 on 64x64 tiles, kind 4 on 128x128 tiles
-// for large trailing matrices); for the dense Schur factor also the inverse of
-// each OUTER_W diagonal block (kind 5).
+// fronts. Pivot columns go in 64-wide blocks inside outer panels (OUTER_W
+// columns for the period fronts, SCHUR_OUTER_W for the dense Schur factor):
+// per block the pivot block (kind 0), the rows below it (kind 1) and the rest
+// of the outer panel (kind 2); after each outer panel one trailing update of
+// rank <= the panel width (kind 3 on 64x64 tiles, kind 4 on 128x128 tiles for
+// large trailing matrices); for the dense Schur factor also the inverse of
+// each INV_W-wide diagonal block (kind 5), which the dense solves use.
 constexpr int OUTER_W = 256;
+constexpr int SCHUR_OUTER_W = 512;
+constexpr int MAX_OUTER_W = 512;
+constexpr int INV_W = 256;
 struct StepDev {
     int kind;
     int win;                // trailing updates: 0 all, 1 next panel's columns, 2 the rest
     int t0, pe;             // first column of the block (kinds 0-2) or panel (3); panel end
     int nf;                 // fronts in this launch
     const int32_t *fl;      // their FrontDesc indices
-    const int32_t *pre;     // prefix sums of the per-front task counts (kinds 1-3)
+    const int32_t *pre;     // prefix sums of the per-front task counts (kinds 1-4)
     int ntasks;
 };
 int step_tasks(int kind, int t0, int pe, int c, int m, int win = 0);
