@@ -214,6 +214,98 @@ def bench_batch(args, log):
     return res
 
 
+class DeviceRedraw:
+    """Per-iteration barrier re-draw on the device (input synthesis for the
+    serving workload, the device form of kktgen.redraw_barrier): Hessian
+    diagonals = row sums of |off-diagonal| + a log-uniform barrier, pure
+    barrier entries = the barrier; the off-diagonals and Jacobian stay."""
+
+    def __init__(self, inst, seed):
+        import numpy as np
+        kind = np.asarray(inst.meta["kind"])
+        self.inst, self.seed = inst, seed
+        cols = np.repeat(np.arange(inst.n_A), np.diff(inst.colptr))
+        self.h = np.nonzero(kind == 1)[0]
+        self.b = np.nonzero(kind == 2)[0]
+        self.off = np.nonzero(kind == 0)[0]
+        self.cols, self.rows = cols, np.asarray(inst.rowind, dtype=np.int64)
+        self.lo, self.hi = inst.barrier_range
+        self.dev = None
+
+    def _setup(self, vals):
+        import torch
+        t = lambda a: torch.as_tensor(a, dtype=torch.int64, device=vals.device)
+        off, h, b = t(self.off), t(self.h), t(self.b)
+        rows, cols = t(self.rows), t(self.cols)
+        av = vals[:, off].abs()
+        rs = torch.zeros(vals.shape[0], self.inst.n_A, dtype=vals.dtype, device=vals.device)
+        rs.index_add_(1, rows[off], av)
+        rs.index_add_(1, cols[off], av)
+        self.dev = dict(h=h, b=b, hcols=cols[h], bcols=cols[b], base=rs[:, cols[h]].contiguous())
+
+    def __call__(self, it, vals):
+        import math
+        import torch
+        if self.dev is None:
+            self._setup(vals)
+        d = self.dev
+        g = torch.Generator(device=vals.device)
+        g.manual_seed(self.seed * 1000 + it)
+        u = torch.rand(vals.shape[0], self.inst.n_A, generator=g, dtype=vals.dtype, device=vals.device)
+        bar = torch.exp(math.log(self.lo) + u * (math.log(self.hi) - math.log(self.lo)))
+        vals[:, d["h"]] = d["base"] + bar[:, d["hcols"]]
+        vals[:, d["b"]] = bar[:, d["bcols"]]
+
+
+def bench_serve(args, log):
+    """Serving: a Poisson stream of requests drawn from the uneven mixture
+    (bus counts log-uniform in [118, 3000], horizons 12/24/48/96), each 30
+    IPM-like iterations (barrier re-drawn on the device, then factor + solve
+    with fixed refinement steps), admitted by device footprint into a few
+    slots and run side by side on their own streams. A step is one solve."""
+    import numpy as np
+    import torch
+    import kktgen
+    import paper_1907_05420_amd as pk
+    from paper_1907_05420_amd import serve
+    prec = pk.KKT_MIXED if args.precision == "mixed" else pk.KKT_FP64
+    iters = args.iterations
+
+    def make(count, seed, rate):
+        insts = kktgen.uneven_batch(count=count, seed=seed)
+        arr = serve.poisson_arrivals(count, rate=rate, rng=np.random.default_rng(seed + 1))
+        return [serve.Request(i, inst, float(t), iters, redraw=DeviceRedraw(inst, seed + i))
+                for i, (inst, t) in enumerate(zip(insts, arr))]
+
+    # warmup: two small requests (module loading, first launches)
+    warm = kktgen.uneven_batch(count=2, seed=kktgen.seed_for(5, 9), nb_range=(118, 300), horizons=(12,))
+    serve.serve([serve.Request(i, w, 0.0, 2, redraw=DeviceRedraw(w, 7 + i)) for i, w in enumerate(warm)],
+                slots=2, precision=prec, refine_steps=args.refine_steps, refine=args.serve_refine)
+    torch.cuda.synchronize()
+    reqs = make(args.requests, kktgen.seed_for(5, 0), args.rate)
+    done, st = serve.serve(reqs, slots=args.slots, hbm_budget=int(args.hbm_budget_gb * 2**30), precision=prec,
+                           refine_steps=args.refine_steps, log=log, refine=args.serve_refine)
+    n = sum(len(r.rel_res) for r in done)
+    lat_req = np.array([r.finished - r.arrival for r in done]) * 1e3
+    lat_it = np.concatenate([np.array(r.solve_s) for r in done]) * 1e3
+    rel = np.concatenate([np.array(r.rel_res) for r in done])
+    return {
+        "metric": METRIC, "value": n / st["wall_s"], "unit": "solves/s", "n_gpus": 1, "steps": int(n),
+        "warmup": 2, "ms_per_step": st["wall_s"] / n * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == pk.KKT_FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": "serve", "requests": len(done), "iterations": iters, "arrival_rate_per_s": args.rate,
+                   "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "buses": [118, 3000],
+                   "horizons": [12, 24, 48, 96], "barrier_range": [1e-6, 1e6], "precision": args.precision,
+                   "refine": args.serve_refine,
+                   "refine_steps": args.refine_steps if args.serve_refine == "fixed" else None},
+        "p50_ms": float(np.percentile(lat_it, 50)), "p99_ms": float(np.percentile(lat_it, 99)),
+        "request_p50_ms": float(np.percentile(lat_req, 50)), "request_p99_ms": float(np.percentile(lat_req, 99)),
+        "rel_res_max": float(rel.max()), "above_1e-10": int((rel > 1e-10).sum()),
+        "inertia_ok": int(sum(sum(r.inertia_ok) for r in done)), "max_in_flight": st["max_active"],
+        "max_device_gb": st["max_used"] / 1e9, "wall_s": st["wall_s"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,7 +316,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--workload", default="mesh2000_N96", choices=["mesh2000_N96", "uneven64"])
+    ap.add_argument("--workload", default="mesh2000_N96", choices=["mesh2000_N96", "uneven64", "serve"])
+    ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
+    ap.add_argument("--iterations", type=int, default=30, help="serve: IPM-like iterations per request")
+    ap.add_argument("--rate", type=float, default=50.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--slots", type=int, default=4, help="serve: requests in flight at most")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serve: device memory for admission")
+    ap.add_argument("--serve-refine", default="tolerance", choices=["tolerance", "fixed"],
+                    help="serve: refine every solve to 1e-10, or a fixed number of steps (--refine-steps)")
     ap.add_argument("--refine-steps", type=int, default=3, help="fixed refinement steps of a batch")
     args = ap.parse_args()
     if args.cpu_baseline_only:
@@ -241,8 +340,8 @@ def main():
     import paper_1907_05420_amd as pk
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    if args.workload == "uneven64":
-        res = bench_batch(args, log)
+    if args.workload in ("uneven64", "serve"):
+        res = bench_batch(args, log) if args.workload == "uneven64" else bench_serve(args, log)
         print(json.dumps(res), flush=True)
         return 0
     inst = kktgen.make_workload(2)

@@ -45,6 +45,25 @@ def test_serving_mix_equals_alone():
         assert alone[0].rel_res == mixed.rel_res
 
 
+def test_serving_to_tolerance_mix_equals_alone():
+    """Requests refined to the residual tolerance (kkt_factor/kkt_solve in a
+    host thread per admitted request) give, in the mix, bitwise what they give
+    alone, and every iteration meets 1e-10."""
+    from paper_1907_05420_amd import serve
+    reqs = make_requests(seed=24)
+    done, stats = serve.serve(reqs, slots=3, keep_x=True, refine="tolerance")
+    assert stats["max_active"] >= 2
+    assert stats["iterations"] == sum(r.iterations for r in reqs)
+    for r in done:
+        assert len(r.rel_res) == r.iterations and max(r.rel_res) <= 1e-10, r.rel_res
+        assert all(r.inertia_ok)
+    for r in make_requests(seed=24):
+        alone, _ = serve.serve([r], slots=1, keep_x=True, refine="tolerance")
+        mixed = [m for m in done if m.rid == r.rid][0]
+        assert np.array_equal(alone[0].x, mixed.x)
+        assert alone[0].rel_res == mixed.rel_res
+
+
 def test_serving_admission_respects_budget():
     from paper_1907_05420_amd import serve
     reqs = make_requests(count=5, iterations=2, seed=22)
