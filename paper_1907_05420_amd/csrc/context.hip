@@ -34,7 +34,7 @@ using namespace kkt;
 
 namespace {
 
-// kind 0-5: launches (see StepDev); SYNC_TO_SIDE: the side stream waits for
+// kind 0-6: launches (see StepDev); SYNC_TO_SIDE: the side stream waits for
 // the main stream's work so far; SYNC_TO_MAIN: the main stream waits for the
 // side stream's work so far.
 constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101;
@@ -88,6 +88,7 @@ struct kkt_ctx {
     bool has_corner = false;
     double dw = 0.0, dc = 0.0;
     double *d_S = nullptr, *d_prefix = nullptr, *d_tauS = nullptr, *d_amaxS = nullptr;
+    double *d_invtmp = nullptr;  // INV_W x INV_W staging of the block-inverse combination
     int64_t *d_cntS = nullptr;
     // solve workspace
     int64_t ws_nrhs = 0;
@@ -229,6 +230,7 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
         sync(SYNC_TO_SIDE);
         for (int j0 = k; j0 < std::min(pe, cmax); j0 += INV_W)
             add(5, j0, pe, 0, 1);       // inverses of the panel's diagonal blocks (dense solves)
+        if (outer_w == 2 * INV_W) add(6, k, pe, 0, 1);  // and of the whole panel's diagonal block
         add(big ? 4 : 3, k, pe, 2, 1);  // the rest, side stream
     }
     if (lookahead) sync(SYNC_TO_MAIN);
@@ -432,6 +434,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = dalloc(ctx, (void **)&ctx->d_tauS, 8 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_amaxS, 256))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_cntS, 256))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_invtmp, 8 * INV_W * INV_W))) return rc;
     }
     return KKT_OK;
 }
@@ -579,7 +582,10 @@ int factor_schur(kkt_ctx *ctx) {
                 }
                 HIPCHK(hipEventRecord(ctx->kev[2 * ctx->kcount], ss));
             }
-            launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, ss);
+            if (s.kind == 6)
+                launch_inv_combine(fa, ctx->d_sdS, ctx->d_stasks + s.fl_off, s.t0, (int)ctx->ng, ctx->d_invtmp, ss);
+            else
+                launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, ss);
             if (timed) {
                 HIPCHK(hipEventRecord(ctx->kev[2 * ctx->kcount + 1], ss));
                 double f = 0.0, b = 0.0;

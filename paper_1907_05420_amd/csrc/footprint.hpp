@@ -54,7 +54,7 @@ inline DevPlan make_plan(const Symbolic &Sy, int64_t N, int precision, int64_t n
     p.counters = align_up(8 * 4 * (N + 1));
     p.amax = align_up(8 * (N + 1));
     p.S = ng ? align_up(8 * ng * ng) : 0;
-    p.prefix = ng ? align_up(8 * (N + 1) * Sy.Ns * Sy.Ns) : 0;
+    p.prefix = ng ? align_up(8 * (N + 1) * Sy.Ns * Sy.Ns) + align_up(8 * 256 * 256) : 0;  // + inverse staging
     // solve workspace
     p.xperm = align_up(8 * (Sy.nA + nb) * N * nrhs);
     p.uvec = align_up(8 * Sy.Usize_vec() * N * nrhs);

@@ -806,6 +806,93 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
     }
 }
 
+// Inverse of the unit lower 2*INV_W block [j0, j0 + 2*INV_W) of the dense
+// factor from the inverses Xa, Xb of its two INV_W diagonal blocks (stored by
+// k_inv256): X = [Xa 0; Xba Xb] with Xba = -Xb Lba Xa, in two launches of
+// 64x64 tiles: mode 0 forms T = Lba Xa into `tmp` (ld INV_W), mode 1 writes
+// -Xb T in place of Lba. Lba is no longer needed by the factorisation once
+// the panel's own updates are done.
+__device__ inline void load_tile64(double *sX, const double *base, int64_t ld, int r0, int c0, int rlim, int clim,
+                                   bool asA, bool diag, int row, int kk) {
+    // sX[k][r] = M[r0 + r][c0 + k] ("A" operand, transposed) or
+    // sX[k][q] = M[r0 + k][c0 + q] ("B" operand); rows >= rlim and columns
+    // >= clim read as zero; unit lower (upper part zero) when diag
+    double val[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int k = kk + 4 * j;
+        const int a = asA ? row : k, b = asA ? k : row;
+        val[j] = base[(int64_t)min(r0 + a, rlim - 1) + (int64_t)min(c0 + b, clim - 1) * ld];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int k = kk + 4 * j;
+        const int a = asA ? row : k, b = asA ? k : row;
+        const bool in = r0 + a < rlim && c0 + b < clim;
+        double v = in ? val[j] : 0.0;
+        if (diag) v = a > b ? v : (a == b ? 1.0 : 0.0);
+        sX[k * LDS_LD + row] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl,
+                                                     int j0, int mode, double *tmp) {
+    typedef Acc<double>::type acc_t;
+    __shared__ double sA[NB * LDS_LD];
+    __shared__ double sB[NB * LDS_LD];
+    const FrontDesc d = sd[fl[0]];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int row = tid & 63, kk = tid >> 6;
+    const int m = d.m;
+    const int ja = j0, jb = j0 + INV_W;
+    const int nbw_b = min(INV_W, d.c - jb);  // > 0: the launch exists only then
+    const int ti = blockIdx.x / (INV_W / 64), tj = blockIdx.x % (INV_W / 64);
+    double *P = fa.L + d.Loff;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+    if (mode == 0) {
+        // T_ij = sum_{k >= j} Lba_ik Xa_kj
+        for (int k = tj; k < INV_W / 64; ++k) {
+            __syncthreads();
+            load_tile64(sA, P, m, jb + 64 * ti, ja + 64 * k, jb + nbw_b, jb, true, false, row, kk);
+            load_tile64(sB, P, m, ja + 64 * k, ja + 64 * tj, jb, jb, false, k == tj, row, kk);
+            __syncthreads();
+            tile_mma<double>(sA, sB, acc, lane, w);
+        }
+    } else {
+        // Xba_ij = -sum_{k <= i} Xb_ik T_kj
+        for (int k = 0; k <= ti; ++k) {
+            __syncthreads();
+            load_tile64(sA, P, m, jb + 64 * ti, jb + 64 * k, jb + nbw_b, jb + nbw_b, true, k == ti, row, kk);
+            load_tile64(sB, tmp, INV_W, 64 * k, 64 * tj, nbw_b, INV_W, false, false, row, kk);
+            __syncthreads();
+            tile_mma<double>(sA, sB, acc, lane, w);
+        }
+    }
+    __syncthreads();
+    tile_stage<double>(sA, acc, lane, w);
+    __syncthreads();
+    const int r = 64 * ti + row;
+    if (r < nbw_b)
+        for (int q = kk; q < 64; q += 4) {
+            const double v = sA[row + q * LDT];
+            if (mode == 0) tmp[r + (int64_t)(64 * tj + q) * INV_W] = v;
+            else P[(int64_t)(jb + r) + (int64_t)(ja + 64 * tj + q) * m] = -v;
+        }
+}
+
+void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, int c, double *tmp,
+                        hipStream_t st) {
+    const int nbw_b = std::min(INV_W, c - (j0 + INV_W));
+    if (nbw_b <= 0) return;
+    const int tiles = ((nbw_b + 63) / 64) * (INV_W / 64);
+    for (int mode = 0; mode < 2; ++mode)
+        hipLaunchKernelGGL(k_inv_combine, dim3(tiles), dim3(256), 0, st, fa, sd, fl, j0, mode, tmp);
+}
+
 int step_tasks_big(int t0, int pe, int c, int m, int win) {
     const UpdGeom g = upd_geom(3, t0, pe, c, m, win);
     if (g.K <= 0 || g.qhi <= g.lo) return 0;
@@ -886,6 +973,7 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
 int step_tasks(int kind, int t0, int pe, int c, int m, int win) {
     if (kind == 4) return step_tasks_big(t0, pe, c, m, win);
     if (kind == 5) return c > t0 ? 1 : 0;
+    if (kind == 6) return c > t0 + INV_W ? 1 : 0;
     if (kind == 0) return c > t0 ? 1 : 0;
     if (kind == 1) {
         const int nb = std::min(NB, c - t0);

@@ -554,21 +554,23 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
 
 // ---- dense Schur factor solves ----------------------------------------------
 // The factor of S (column-major, ld ng) keeps D on its diagonal, the inverse
-// X_J of every unit lower 256x256 diagonal block J strictly below that
+// X_J of every unit lower DBW x DBW diagonal block J strictly below that
 // block's diagonal, and L elsewhere strictly below the diagonal; after the
 // factorisation the strict lower triangle is mirrored into the strict upper
 // one, so that both L (forward) and L^T (backward) are read down columns.
-// Steps go over 256-wide blocks: forward y_J = X_J v_J then v_below -=
+// Steps go over DBW-wide blocks: forward y_J = X_J v_J then v_below -=
 // L[below, J] y_J; backward x_J = X_J^T z_J then z_above -= L[J, above]^T x_J.
-constexpr int DBW = INV_W;  // the dense factor stores the inverses of its INV_W-wide diagonal blocks
+constexpr int DBW = 2 * INV_W;  // the factor holds the inverses of its 2*INV_W-wide diagonal blocks
 
-// out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow:
-// 64 rows per workgroup, four groups of 64 columns, reduced at the end. All
-// global loads of a workgroup are issued before the first use.
-__global__ __launch_bounds__(256) void k_dense_gemv(const double *S, int64_t ng, int64_t row0, int64_t nrow,
-                                                    int64_t col0, int ncol, const double *w, double *out, int nrhs) {
+// out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow
+// (ncol <= DBW): 64 rows per workgroup, DBW/64 groups of 64 columns, reduced
+// at the end. All global loads of a workgroup are issued before the first use.
+constexpr int GV_G = DBW / 64;
+__global__ __launch_bounds__(64 * GV_G) void k_dense_gemv(const double *S, int64_t ng, int64_t row0, int64_t nrow,
+                                                          int64_t col0, int ncol, const double *w, double *out,
+                                                          int nrhs) {
     __shared__ double wb[DBW * RB];
-    __shared__ double red[4 * 64 * RB];
+    __shared__ double red[GV_G * 64 * RB];
     const int tid = threadIdx.x;
     const int a = tid & 63, g = tid >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + a;
@@ -587,7 +589,7 @@ __global__ __launch_bounds__(256) void k_dense_gemv(const double *S, int64_t ng,
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr)
                 if (rr < nr) o[rr] = out[(int64_t)(k0r + rr) * ng + row0 + i];
-        for (int idx = tid; idx < DBW * RB; idx += 256) {
+        for (int idx = tid; idx < DBW * RB; idx += 64 * GV_G) {
             const int q = idx / RB, r = idx % RB;
             wb[idx] = (q < ncol && r < nr) ? w[(int64_t)(k0r + r) * ng + q] : 0.0;
         }
@@ -606,8 +608,9 @@ __global__ __launch_bounds__(256) void k_dense_gemv(const double *S, int64_t ng,
         __syncthreads();
         if (g == 0 && i < nrow)
             for (int rr = 0; rr < nr; ++rr) {
-                const double t = red[(0 * 64 + a) * RB + rr] + red[(1 * 64 + a) * RB + rr] +
-                                 red[(2 * 64 + a) * RB + rr] + red[(3 * 64 + a) * RB + rr];
+                double t = 0.0;
+#pragma unroll
+                for (int gg = 0; gg < GV_G; ++gg) t += red[(gg * 64 + a) * RB + rr];
                 out[(int64_t)(k0r + rr) * ng + row0 + i] = o[rr] - t;
             }
         __syncthreads();
@@ -617,7 +620,8 @@ __global__ __launch_bounds__(256) void k_dense_gemv(const double *S, int64_t ng,
 // In-block product with the stored inverse of diagonal block [j0, j0 + nbw):
 // out[j0 + i] = in[j0 + i] + sum_q M[i][q] in[j0 + q] with M = X_J (lower,
 // q < i) or X_J^T read from the mirrored upper triangle (upper, q > i).
-// 16 rows per workgroup, 16 groups of 16 columns.
+// 16 rows per workgroup, 16 groups of DBW/16 columns.
+constexpr int BK_C = DBW / 16;
 __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, int64_t j0, const double *in,
                                                    double *out, int nrhs, int upper) {
     __shared__ double vb[DBW * RB];
@@ -626,11 +630,11 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
     const int nbw = (int)min((int64_t)DBW, ng - j0);
     const int rl = tid & 15, g = tid >> 4;
     const int i = blockIdx.x * 16 + rl;
-    const int q0 = min(16 * g, nbw - 1);
+    const int q0 = min(BK_C * g, nbw - 1);
     const double *rowp = S + j0 + min(i, nbw - 1) + (j0 + q0) * ng;
-    double l[16];
+    double l[BK_C];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) l[u] = rowp[(int64_t)min(u, nbw - 1 - q0) * ng];
+    for (int u = 0; u < BK_C; ++u) l[u] = rowp[(int64_t)min(u, nbw - 1 - q0) * ng];
     for (int k0r = 0; k0r < nrhs; k0r += RB) {
         const int nr = min(RB, nrhs - k0r);
         for (int idx = tid; idx < DBW * RB; idx += 256) {
@@ -640,8 +644,8 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
         __syncthreads();
         double acc[RB] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int q = 16 * g + u;
+        for (int u = 0; u < BK_C; ++u) {
+            const int q = BK_C * g + u;
             const bool ok = q < nbw && (upper ? q > i : q < i);
             const double x = ok ? l[u] : 0.0;
 #pragma unroll
@@ -774,7 +778,7 @@ void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t
                            (const double *)v, y, (int)nrhs, 0);
         const int64_t below = ng - j0 - nbw;
         if (below > 0)
-            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((below + 63) / 64)), dim3(256), 0, st, S, ng, j0 + nbw,
+            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((below + 63) / 64)), dim3(64 * GV_G), 0, st, S, ng, j0 + nbw,
                                below, j0, (int)nbw, (const double *)(y + j0), v, (int)nrhs);
     }
 }
@@ -786,7 +790,7 @@ void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t
         hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, j0,
                            (const double *)z, x, (int)nrhs, 1);
         if (j0 > 0)
-            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((j0 + 63) / 64)), dim3(256), 0, st, S, ng, (int64_t)0,
+            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((j0 + 63) / 64)), dim3(64 * GV_G), 0, st, S, ng, (int64_t)0,
                                j0, j0, (int)nbw, (const double *)(x + j0), z, (int)nrhs);
     }
 }

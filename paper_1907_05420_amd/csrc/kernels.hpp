@@ -42,7 +42,8 @@ struct TreeArgs {
 // of the outer panel (kind 2); after each outer panel one trailing update of
 // rank <= the panel width (kind 3 on 64x64 tiles, kind 4 on 128x128 tiles for
 // large trailing matrices); for the dense Schur factor also the inverse of
-// each INV_W-wide diagonal block (kind 5), which the dense solves use.
+// each INV_W-wide diagonal block (kind 5) and, from two of them, of each
+// 2*INV_W-wide one (kind 6), which the dense solves use.
 constexpr int OUTER_W = 256;
 constexpr int SCHUR_OUTER_W = 512;
 constexpr int MAX_OUTER_W = 512;
@@ -115,6 +116,10 @@ void launch_schur_assemble(const void *U, int64_t Ustride, int64_t uoff, int64_t
 void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t nb, int precision,
                       double *out, hipStream_t st);
 void launch_mirror_lower(double *S, int64_t ng, hipStream_t st);
+// inverse of the 2*INV_W diagonal block at j0 from its two INV_W inverses
+// (tmp: INV_W x INV_W doubles)
+void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, int c, double *tmp,
+                        hipStream_t st);
 void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st);
 void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st);
 
