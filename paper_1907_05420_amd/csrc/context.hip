@@ -18,7 +18,7 @@
 
 namespace kkt {
 SymbolicInput make_input(const kkt_structure *s, const kkt_options &o);
-void fill_stats(const Symbolic &S, int64_t N, const kkt_options &o, int64_t nrhs_max, kkt_symbolic_stats *st);
+void fill_stats(const Symbolic &S, kkt_symbolic_stats *st);
 }
 
 using namespace kkt;
@@ -56,6 +56,7 @@ struct LevelPlan {
 
 struct kkt_ctx {
     hipStream_t stream = nullptr;
+    bool dry = false;  // planning only: allocations and uploads are counted, not made
     kkt_options opt{};
     int device = 0;
     bool analyzed = false, factored = false;
@@ -123,6 +124,10 @@ int dalloc(kkt_ctx *ctx, void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return KKT_OK;
     bytes = align_up(bytes);
+    if (ctx->dry) {
+        ctx->bytes_static += bytes;
+        return KKT_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) { *p = nullptr; return e == hipErrorOutOfMemory ? KKT_ERR_NOMEM : KKT_ERR_HIP; }
     ctx->allocs.emplace_back(*p, bytes);
@@ -134,7 +139,8 @@ template <typename V>
 int upload(kkt_ctx *ctx, V **dst, const std::vector<V> &src) {
     int rc = dalloc(ctx, (void **)dst, sizeof(V) * std::max<size_t>(src.size(), 1));
     if (rc) return rc;
-    if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice));
+    if (!src.empty() && !ctx->dry)
+        HIPCHK(hipMemcpy(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice));
     return KKT_OK;
 }
 
@@ -445,6 +451,11 @@ int ensure_ws(kkt_ctx *ctx, int64_t nrhs) {
     const Symbolic &S = ctx->sy;
     auto get = [&](double **p, int64_t count) -> int {
         size_t bytes = align_up(8 * std::max<int64_t>(count, 1));
+        if (ctx->dry) {
+            *p = nullptr;
+            ctx->bytes_ws += bytes;
+            return KKT_OK;
+        }
         hipError_t e = hipMalloc((void **)p, bytes);
         if (e != hipSuccess) return e == hipErrorOutOfMemory ? KKT_ERR_NOMEM : KKT_ERR_HIP;
         ctx->ws.push_back(*p);
@@ -467,7 +478,8 @@ int ensure_ws(kkt_ctx *ctx, int64_t nrhs) {
         if ((rc = get(&ctx->d_Z, KRYLOV_M * ctx->ntot * nrhs))) return rc;
         if ((rc = get(&ctx->d_h, 3 * ldh * nrhs + nrhs))) return rc;
         if ((rc = get(&ctx->d_kpart, (int64_t)KRYLOV_PART * ldh * nrhs))) return rc;
-        if (hipHostMalloc((void **)&ctx->h_pin, 8 * (3 * ldh * nrhs + nrhs), hipHostMallocDefault) != hipSuccess) {
+        if (!ctx->dry &&
+            hipHostMalloc((void **)&ctx->h_pin, 8 * (3 * ldh * nrhs + nrhs), hipHostMallocDefault) != hipSuccess) {
             ctx->h_pin = nullptr;
             return KKT_ERR_NOMEM;
         }
@@ -716,28 +728,36 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     return KKT_OK;
 }
 
-extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
-    if (!ctx || !s || s->N < 1 || s->Ns < 0 || s->nA < 1) return KKT_ERR_ARG;
+// symbolic analysis with the structure checks and the kernels' size limits
+int analyze_checked(const kkt_structure *s, const kkt_options &o, Symbolic &S) {
+    if (!s || s->N < 1 || s->Ns < 0 || s->nA < 1) return KKT_ERR_ARG;
     if (!s->A_colptr || !s->A_rowind) return KKT_ERR_ARG;
     if (s->Ns > 0 && (!s->C0_rowptr || !s->C0_colind || !s->C1_rowptr || !s->C1_colind)) return KKT_ERR_ARG;
-    Symbolic S;
     std::string err;
     try {
-        err = analyze(make_input(s, ctx->opt), S);
+        err = analyze(make_input(s, o), S);
     } catch (...) {
         return KKT_ERR_NOMEM;
     }
     if (!err.empty()) {
-        if (ctx->opt.verbose) std::fprintf(stderr, "kkt_analyze: %s\n", err.c_str());
+        if (o.verbose) std::fprintf(stderr, "kkt_analyze: %s\n", err.c_str());
         return KKT_ERR_STRUCT;
     }
     // fronts whose solve vectors fit in LDS; 32-bit launch and index limits of S
     if (S.max_front > MAX_FRONT_ROWS || S.max_pivots > MAX_FRONT_PIVOTS || (s->N * s->Ns) > 46000) {
-        if (ctx->opt.verbose)
+        if (o.verbose)
             std::fprintf(stderr, "kkt_analyze: front of %lld rows / %lld pivots or Schur size %lld over the limits\n",
                          (long long)S.max_front, (long long)S.max_pivots, (long long)(s->N * s->Ns));
         return KKT_ERR_ARG;
     }
+    return KKT_OK;
+}
+
+extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
+    if (!ctx) return KKT_ERR_ARG;
+    Symbolic S;
+    const int arc = analyze_checked(s, ctx->opt, S);
+    if (arc) return arc;
     (void)hipStreamSynchronize(ctx->stream);
     free_ws(ctx);
     free_static(ctx);
@@ -752,6 +772,27 @@ extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
     return KKT_OK;
 }
 
+namespace kkt {
+int plan_device_bytes(const kkt_structure *s, const kkt_options &o, int64_t nrhs, size_t *bytes) {
+    if (!bytes || nrhs < 1) return KKT_ERR_ARG;
+    kkt_ctx ctx;
+    ctx.dry = true;
+    ctx.opt = o;
+    ctx.big_rows = o.big_tile_rows > 0 ? o.big_tile_rows : 512;
+    Symbolic S;
+    int rc = analyze_checked(s, o, S);
+    if (rc) return rc;
+    ctx.sy = std::move(S);
+    ctx.N = s->N;
+    ctx.ng = s->N * s->Ns;
+    ctx.ntot = s->N * s->nA + ctx.ng;
+    if ((rc = build_device_symbolic(&ctx, s))) return rc;
+    if ((rc = ensure_ws(&ctx, nrhs))) return rc;
+    *bytes = ctx.bytes_static + ctx.bytes_ws;
+    return KKT_OK;
+}
+}  // namespace kkt
+
 extern "C" int kkt_footprint(const kkt_ctx *ctx, size_t *bytes) {
     if (!ctx || !bytes) return KKT_ERR_ARG;
     *bytes = ctx->bytes_static + ctx->bytes_ws;
@@ -761,7 +802,7 @@ extern "C" int kkt_footprint(const kkt_ctx *ctx, size_t *bytes) {
 extern "C" int kkt_stats(const kkt_ctx *ctx, kkt_symbolic_stats *st) {
     if (!ctx || !st) return KKT_ERR_ARG;
     if (!ctx->analyzed) return KKT_ERR_ORDER;
-    fill_stats(ctx->sy, ctx->N, ctx->opt, std::max<int64_t>(ctx->ws_nrhs, 1), st);
+    fill_stats(ctx->sy, st);
     st->device_bytes = (int64_t)(ctx->bytes_static + ctx->bytes_ws);
     return KKT_OK;
 }

@@ -52,7 +52,7 @@ SymbolicInput make_input(const kkt_structure *s, const kkt_options &o) {
     return in;
 }
 
-void fill_stats(const Symbolic &S, int64_t N, const kkt_options &o, int64_t nrhs_max, kkt_symbolic_stats *st) {
+void fill_stats(const Symbolic &S, kkt_symbolic_stats *st) {
     st->n_supernodes = S.nsup;
     st->n_levels = S.nlevels;
     st->nnz_L = S.nnzL;
@@ -60,7 +60,7 @@ void fill_stats(const Symbolic &S, int64_t N, const kkt_options &o, int64_t nrhs
     st->max_front = S.max_front;
     st->max_pivots = S.max_pivots;
     st->flops_factor = S.flops;
-    st->device_bytes = (int64_t)device_bytes(S, N, o.precision, nrhs_max, uses_krylov(o));
+    st->device_bytes = 0;
 }
 }  // namespace kkt
 
@@ -78,23 +78,11 @@ extern "C" int kkt_plan(const kkt_structure *s, const kkt_options *opt, int64_t 
         return KKT_ERR_NOMEM;
     }
     if (!err.empty()) return KKT_ERR_STRUCT;
-    kkt::fill_stats(S, s->N, o, nrhs_max, st);
-    if (std::getenv("KKT_DEBUG_FRONTS")) {
-        for (int32_t l = 0; l < S.nlevels; ++l) {
-            int64_t cnt = 0, big = 0, mx = 0, sm = 0;
-            double fl = 0;
-            for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
-                int32_t t = S.level_list[q];
-                int64_t m = S.nrow[t], c = S.ncol[t];
-                cnt++;
-                if (m > 64) big++; else sm++;
-                mx = std::max(mx, m);
-                for (int64_t k = 0; k < c; ++k) fl += double(m - k - 1) * double(m - k - 1);
-            }
-            std::fprintf(stderr, "level %d: %lld fronts (%lld small, %lld >64), max m %lld, flops %.3g\n", l,
-                         (long long)cnt, (long long)sm, (long long)big, (long long)mx, fl);
-        }
-    }
+    kkt::fill_stats(S, st);
+    size_t bytes = 0;
+    const int rc = kkt::plan_device_bytes(s, o, nrhs_max, &bytes);
+    if (rc) return rc;
+    st->device_bytes = (int64_t)bytes;
     if (perm) std::memcpy(perm, S.perm.data(), sizeof(int32_t) * S.nA);
     return KKT_OK;
 }

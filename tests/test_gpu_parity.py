@@ -218,3 +218,21 @@ def test_inertia_correction_shifts():
     i2.vals = v
     x, K = sc.solve_mono(i2)
     assert _rel(g["x"], x) <= 1e-9
+
+
+@pytest.mark.parametrize("case", [SMALL[1], SMALL[3], SMALL[5], SMALL[8]])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plan_equals_footprint(case, precision):
+    """The host-only planning query (used for admission) names exactly the
+    device bytes the context holds after analysis and a solve."""
+    import paper_1907_05420_amd as pk
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    nrhs = inst.b.shape[0]
+    st, _ = pk.kkt_plan(inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind, inst.C0_rowptr,
+                        inst.C0_colind, inst.C1_rowptr, inst.C1_colind, precision=precision, nrhs_max=nrhs)
+    s = pk.Solver(inst, precision=precision)
+    d = pk.device_inputs(inst)
+    s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
+    s.solve(d["b"])
+    assert s.footprint() == st["device_bytes"]
+    s.close()
