@@ -76,10 +76,15 @@ struct kkt_ctx {
     std::vector<StepHost> steps, ssteps;   // sparse levels, Schur
     int32_t *d_stasks = nullptr;           // Schur step tasks
     FrontDesc *d_sdS = nullptr;
-    // residual structures
-    int64_t *d_rp = nullptr, *d_vi = nullptr, *d_c1tp = nullptr, *d_c0tp = nullptr, *d_c1tk = nullptr,
+    // residual: K's pattern as sliced ELLPACK (64-row slices) with the values
+    // of every period in that order (shifts included), rebuilt per factorisation
+    int64_t nnz_sell = 0;
+    int64_t *d_sl_off = nullptr;
+    int32_t *d_sl_ci = nullptr, *d_sl_vi = nullptr;
+    double *d_Asell = nullptr;
+    int64_t *d_c1tp = nullptr, *d_c0tp = nullptr, *d_c1tk = nullptr,
             *d_c0tk = nullptr, *d_c0p = nullptr, *d_c1p = nullptr;
-    int32_t *d_ci = nullptr, *d_c1ts = nullptr, *d_c0ts = nullptr, *d_c0i = nullptr, *d_c1i = nullptr;
+    int32_t *d_c1ts = nullptr, *d_c0ts = nullptr, *d_c0i = nullptr, *d_c1i = nullptr;
     // numeric
     void *d_L = nullptr, *d_U = nullptr;
     double *d_tau = nullptr, *d_amax = nullptr;
@@ -380,9 +385,33 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
                 vi[q[i]++] = k;
                 if (i != j) { ci[q[j]] = i; vi[q[j]++] = k; }
             }
-        if ((rc = upload(ctx, &ctx->d_rp, rp))) return rc;
-        if ((rc = upload(ctx, &ctx->d_ci, ci))) return rc;
-        if ((rc = upload(ctx, &ctx->d_vi, vi))) return rc;
+        // sliced ELLPACK of that CSR: 64-row slices, entry u of row 64 s + l at
+        // sl_off[s] + 64 u + l, padded with the row itself and no value
+        const int64_t nsl = (nA + 63) / 64;
+        std::vector<int64_t> sl_off(nsl + 1, 0);
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            int64_t w = 0;
+            for (int64_t i = 64 * sl; i < std::min(nA, 64 * sl + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+            sl_off[sl + 1] = sl_off[sl] + 64 * w;
+        }
+        std::vector<int32_t> sl_ci(sl_off[nsl]), sl_vi(sl_off[nsl], -1);
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            const int64_t w = (sl_off[sl + 1] - sl_off[sl]) / 64;
+            for (int64_t l = 0; l < 64; ++l) {
+                const int64_t i = std::min(nA - 1, 64 * sl + l);
+                for (int64_t u = 0; u < w; ++u) {
+                    const int64_t p = sl_off[sl] + 64 * u + l;
+                    const bool has = 64 * sl + l < nA && rp[i] + u < rp[i + 1];
+                    sl_ci[p] = has ? ci[rp[i] + u] : (int32_t)i;
+                    sl_vi[p] = has ? (int32_t)vi[rp[i] + u] : -1;
+                }
+            }
+        }
+        ctx->nnz_sell = sl_off[nsl];
+        if ((rc = upload(ctx, &ctx->d_sl_off, sl_off))) return rc;
+        if ((rc = upload(ctx, &ctx->d_sl_ci, sl_ci))) return rc;
+        if ((rc = upload(ctx, &ctx->d_sl_vi, sl_vi))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_Asell, 8 * ctx->nnz_sell * ctx->N))) return rc;
         const int64_t Ns = S.Ns;
         auto transpose = [&](const int64_t *p, const int32_t *c, std::vector<int64_t> &tp, std::vector<int32_t> &ts,
                              std::vector<int64_t> &tk) {
@@ -667,9 +696,10 @@ ResidualArgs residual_args(kkt_ctx *ctx, int64_t nrhs) {
     ra.nrhs = nrhs;
     ra.A = ctx->d_A;
     ra.nnz = S.nnzA;
-    ra.rp = ctx->d_rp;
-    ra.ci = ctx->d_ci;
-    ra.vi = ctx->d_vi;
+    ra.sl_off = ctx->d_sl_off;
+    ra.sl_ci = ctx->d_sl_ci;
+    ra.Asell = ctx->d_Asell;
+    ra.nnz_sell = ctx->nnz_sell;
     ra.c1tp = ctx->d_c1tp;
     ra.c0tp = ctx->d_c0tp;
     ra.c1ts = ctx->d_c1ts;
@@ -842,6 +872,8 @@ int factor_enqueue(kkt_ctx *ctx, const double *A_vals, const double *C0_vals, co
     if (ctx->has_corner) HIPCHK(hipMemcpyAsync(ctx->d_corner, corner_diag, 8 * ctx->ng, hipMemcpyDeviceToDevice, st));
     ctx->dw = delta_w;
     ctx->dc = delta_c;
+    launch_sell_values(ctx->d_A, S.nnzA, ctx->N, S.nA, S.n_primal, ctx->d_sl_off, ctx->d_sl_ci, ctx->d_sl_vi,
+                       ctx->nnz_sell, delta_w, delta_c, ctx->d_Asell, st);
     mark(ctx, 0);
     int rc = ctx->opt.precision == KKT_MIXED ? factor_blocks<float>(ctx) : factor_blocks<double>(ctx);
     if (rc) return rc;

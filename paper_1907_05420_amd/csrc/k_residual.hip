@@ -100,25 +100,30 @@ __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const doubl
     }
 }
 
-// Period rows, one thread per row i of A_n (all right-hand sides of a pass
-// together, so that the row's indices and values are read once per pass):
+// Period rows, one wavefront per 64-row slice of K's sliced ELLPACK, lane l
+// holding row i = 64 s + l (all right-hand sides of a pass together):
 //   r_n = b_n - (A_n + shifts) x_n - C_1^T x_g[n] - C_0^T sg[n]
-// The row's entries are loaded in batches of RES_B from clamped addresses and
-// masked afterwards.
+// The slice's column indices and values are read coalesced, RES_B entries
+// per row at a time (padding entries carry a zero value and the row's own
+// column).
 constexpr int RES_B = 8;
 template <int RBT>
 __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const double *b, const double *x, double *r,
                                                      const double *sg, double *wpart) {
     __shared__ double wred[4 * RBT];
-    const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
-    const int n = blockIdx.y;
-    const bool on = i < ra.nA;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t nsl = (ra.nA + 63) / 64;
+    const int64_t sl = min((int64_t)blockIdx.x * 4 + (tid >> 6), nsl - 1);
+    const bool slice_on = (int64_t)blockIdx.x * 4 + (tid >> 6) < nsl;
+    const int64_t i = 64 * sl + lane;
+    const bool on = slice_on && i < ra.nA;
     const int64_t ic = on ? i : ra.nA - 1;
+    const int n = blockIdx.y;
     const int64_t ng = ra.N * ra.Ns;
-    const int64_t e0 = ra.rp[ic], e1 = on ? ra.rp[ic + 1] : e0;
-    const double *An = ra.A + (int64_t)n * ra.nnz;
-    const double shift = ic < ra.n_primal ? ra.dw : -ra.dc;
+    const int64_t p0 = ra.sl_off[sl];
+    const int w = (int)((ra.sl_off[sl + 1] - p0) / 64);
+    const int32_t *cis = ra.sl_ci + p0 + lane;
+    const double *avs = ra.Asell + (int64_t)n * ra.nnz_sell + p0 + lane;
     for (int k0 = 0; k0 < ra.nrhs; k0 += RBT) {
         const int nr = (int)min((int64_t)RBT, ra.nrhs - k0);
         const double *xn[RBT];
@@ -130,25 +135,22 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
             acc[q] = b ? b[(int64_t)kk * ra.ntot + (int64_t)n * ra.nA + ic] : 0.0;
             ab[q] = fabs(acc[q]);
         }
-        for (int64_t eb = e0; eb < e1; eb += RES_B) {
+        for (int u0 = 0; u0 < w; u0 += RES_B) {
             int32_t j[RES_B];
-            int64_t v[RES_B];
-#pragma unroll
-            for (int u = 0; u < RES_B; ++u) {
-                const int64_t e = min(eb + u, e1 - 1);
-                j[u] = ra.ci[e];
-                v[u] = ra.vi[e];
-            }
             double a[RES_B], xv[RES_B][RBT];
 #pragma unroll
             for (int u = 0; u < RES_B; ++u) {
-                a[u] = An[v[u]];
-#pragma unroll
-                for (int q = 0; q < RBT; ++q) xv[u][q] = xn[q][j[u]];
+                const int uu = min(u0 + u, w - 1);
+                j[u] = cis[64 * uu];
+                a[u] = avs[64 * uu];
             }
 #pragma unroll
+            for (int u = 0; u < RES_B; ++u)
+#pragma unroll
+                for (int q = 0; q < RBT; ++q) xv[u][q] = xn[q][j[u]];
+#pragma unroll
             for (int u = 0; u < RES_B; ++u) {
-                const double au = eb + u < e1 ? a[u] + (j[u] == ic ? shift : 0.0) : 0.0;
+                const double au = u0 + u < w ? a[u] : 0.0;
 #pragma unroll
                 for (int q = 0; q < RBT; ++q) {
                     const double t = au * xv[u][q];
@@ -179,21 +181,21 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
                 ab[q] += fabs(t);
             }
         }
-        double w[RBT];
+        double wq[RBT];
 #pragma unroll
         for (int q = 0; q < RBT; ++q) {
-            w[q] = 0.0;
+            wq[q] = 0.0;
             if (on && q < nr) {
                 r[(int64_t)(k0 + q) * ra.ntot + (int64_t)n * ra.nA + i] = b ? acc[q] : -acc[q];
-                if (ab[q] > 0.0) w[q] = fabs(acc[q]) / ab[q];
-                else if (acc[q] != 0.0) w[q] = INFINITY;
+                if (ab[q] > 0.0) wq[q] = fabs(acc[q]) / ab[q];
+                else if (acc[q] != 0.0) wq[q] = INFINITY;
             }
         }
         if (wpart) {
 #pragma unroll
             for (int q = 0; q < RBT; ++q) {
-                const double wm = wave_max(w[q]);
-                if ((tid & 63) == 0) wred[q * 4 + (tid >> 6)] = wm;
+                const double wm = wave_max(wq[q]);
+                if (lane == 0) wred[q * 4 + (tid >> 6)] = wm;
             }
             __syncthreads();
             if (tid < nr)
@@ -202,6 +204,33 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
             __syncthreads();
         }
     }
+}
+
+// values of every period in the sliced layout, shifts on the diagonal
+__global__ __launch_bounds__(64) void k_sell_values(const double *A, int64_t nnzA, int64_t nA, int64_t n_primal,
+                                                    const int64_t *sl_off, const int32_t *sl_ci,
+                                                    const int32_t *sl_vi, int64_t nnz_sell, double dw, double dc,
+                                                    double *Asell) {
+    const int64_t sl = blockIdx.x;
+    const int n = blockIdx.y, lane = threadIdx.x;
+    const int64_t i = 64 * sl + lane;
+    const int64_t p0 = sl_off[sl];
+    const int w = (int)((sl_off[sl + 1] - p0) / 64);
+    const double shift = i < n_primal ? dw : -dc;
+    const double *An = A + (int64_t)n * nnzA;
+    double *out = Asell + (int64_t)n * nnz_sell + p0 + lane;
+    for (int u = 0; u < w; ++u) {
+        const int32_t v = sl_vi[p0 + 64 * u + lane];
+        const int32_t c = sl_ci[p0 + 64 * u + lane];
+        out[64 * u] = v >= 0 ? An[v] + (c == i ? shift : 0.0) : 0.0;
+    }
+}
+
+void launch_sell_values(const double *A, int64_t nnzA, int64_t N, int64_t nA, int64_t n_primal,
+                        const int64_t *sl_off, const int32_t *sl_ci, const int32_t *sl_vi, int64_t nnz_sell,
+                        double dw, double dc, double *Asell, hipStream_t st) {
+    hipLaunchKernelGGL(k_sell_values, dim3((unsigned)((nA + 63) / 64), (unsigned)N), dim3(64), 0, st, A, nnzA, nA,
+                       n_primal, sl_off, sl_ci, sl_vi, nnz_sell, dw, dc, Asell);
 }
 
 // deterministic two-stage sums of r^2 and b^2 per right-hand side
@@ -271,7 +300,7 @@ int64_t residual_work(int64_t N, int64_t nA, int64_t Ns, int64_t nrhs) {
 
 static void launch_res_periods(const ResidualArgs &ra, const double *b, const double *x, double *r, const double *sg,
                                double *wpart, hipStream_t st) {
-    const dim3 grid((unsigned)((ra.nA + 255) / 256), (unsigned)ra.N);
+    const dim3 grid((unsigned)(((ra.nA + 63) / 64 + 3) / 4), (unsigned)ra.N);  // four 64-row slices per workgroup
     if (ra.nrhs >= 3) hipLaunchKernelGGL(k_res_periods<4>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
     else if (ra.nrhs == 2) hipLaunchKernelGGL(k_res_periods<2>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
     else hipLaunchKernelGGL(k_res_periods<1>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);

@@ -128,9 +128,13 @@ struct ResidualArgs {
     int64_t N, nA, Ns, ntot, nrhs;
     const double *A;           // [N][nnz]
     int64_t nnz;
-    const int64_t *rp;         // full symmetric CSR of the pattern (old order)
-    const int32_t *ci;
-    const int64_t *vi;         // value index into the lower CSC of each CSR entry
+    // K's blocks as sliced ELLPACK (old order): 64-row slices, entry u of row
+    // 64 s + l at sl_off[s] + 64 u + l; Asell [N][nnz_sell] the values with
+    // the shifts on the diagonal, zero in the padding (column = the row)
+    const int64_t *sl_off;
+    const int32_t *sl_ci;
+    const double *Asell;
+    int64_t nnz_sell;
     const int64_t *c1tp, *c0tp;   // C_1^T, C_0^T by A column: (s, k)
     const int32_t *c1ts, *c0ts;
     const int64_t *c1tk, *c0tk;
@@ -147,6 +151,10 @@ int64_t residual_work(int64_t N, int64_t nA, int64_t Ns, int64_t nrhs);
 void launch_residual(const ResidualArgs &ra, const double *b, const double *x, double *r, double *work,
                      double *norms, hipStream_t st);
 void launch_axpy(double *x, const double *dx, int64_t n, hipStream_t st);
+// Asell[n][p] = A[n][sl_vi[p]] (+ delta_w / -delta_c on the diagonal), 0 in the padding
+void launch_sell_values(const double *A, int64_t nnzA, int64_t N, int64_t nA, int64_t n_primal,
+                        const int64_t *sl_off, const int32_t *sl_ci, const int32_t *sl_vi, int64_t nnz_sell,
+                        double dw, double dc, double *Asell, hipStream_t st);
 void launch_matvec(const ResidualArgs &ra, const double *x, double *y, double *work, hipStream_t st);
 
 // ---- Krylov helpers (vectors are [nrhs][n] blocks; coefficient arrays on device)
