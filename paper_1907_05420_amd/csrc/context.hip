@@ -48,6 +48,7 @@ struct LevelPlan {
     int64_t small_off = 0, all_off = 0, ea_off = 0, large_off = 0;  // int32 offsets into the task buffer
     int64_t rrow_off = 0, rcol_off = 0;                             // RowTask lists of the solve
     int nsmall = 0, nall = 0, nea = 0, nlarge = 0, nrrow = 0, nrcol = 0;
+    int nsmall_cls[3] = {0, 0, 0};  // small fronts of <= 16, <= 32, <= 64 rows (listed in that order)
     int maxm = 0, maxm_large = 0, maxc_large = 0;
     int step_begin = 0, step_end = 0;
 };
@@ -321,7 +322,14 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         }
         lp.small_off = (int64_t)buf.size();
         lp.nsmall = (int)small.size();
-        buf.insert(buf.end(), small.begin(), small.end());
+        for (int cls = 0; cls < 3; ++cls) {
+            const int lo = cls == 0 ? 0 : (16 << (cls - 1)), hi = 16 << cls;
+            for (int32_t t : small)
+                if (S.nrow[t] > lo && S.nrow[t] <= hi) {
+                    buf.push_back(t);
+                    ++lp.nsmall_cls[cls];
+                }
+        }
         lp.all_off = (int64_t)buf.size();
         lp.nall = (int)all.size();
         buf.insert(buf.end(), all.begin(), all.end());
@@ -580,7 +588,7 @@ int factor_blocks(kkt_ctx *ctx) {
     launch_scatter<T>(sa, fa, N, st);
     TreeArgs tr = tree_args(ctx);
     for (const LevelPlan &lp : ctx->levels) {
-        launch_small_fronts<T>(fa, ctx->d_sd, ctx->d_tasks + lp.small_off, lp.nsmall, N, tr, st);
+        launch_small_fronts<T>(fa, ctx->d_sd, ctx->d_tasks + lp.small_off, lp.nsmall_cls, N, tr, st);
         launch_extend_add<T>(fa, ctx->d_sd, (const RowTask *)(ctx->d_tasks + lp.ea_off), lp.nea, N, tr, st);
         for (int q = lp.step_begin; q < lp.step_end; ++q)
             launch_step<T>(fa, ctx->d_sd, step_dev(ctx->steps[q], ctx->d_tasks), N, st);

@@ -124,21 +124,28 @@ __global__ void k_scatter_C(const double *C0, int64_t n0, const int64_t *c0map, 
 }
 
 // --------------------------------------------------------------------------
-// small fronts (m <= 64): extend-add + full partial factorisation in LDS
+// small fronts (m <= MAXM <= 64): extend-add + full partial factorisation in
+// LDS, one wavefront per front, lane r owning row r. The LDS tile is sized by
+// the front's size class (16, 32 or 64 rows) so that many fronts of the lower
+// tree levels share a compute unit.
 // --------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MAXM>
 __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *tasks,
                                                     const int32_t *cptr, const int32_t *clist,
                                                     const int64_t *relptr, const int32_t *rel) {
-    __shared__ T F[SMALL_M * LDT];
+    constexpr int LD = MAXM + 1;
+    __shared__ T F[MAXM * LD];
     __shared__ T piv;
+    __shared__ double taus[MAXM];
+    __shared__ int sgns[MAXM];
     const int s = tasks[blockIdx.x];
     const int n = blockIdx.y;
     const int tid = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c, u = m - c;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
-    // lane r owns row r; loads in batches of 8 from clamped addresses
+    // row tid of the pivot columns (loads in batches of 8 from clamped
+    // addresses), zero in the update columns
     const int rc = min(tid, m - 1);
     for (int q0 = 0; q0 < m; q0 += 8) {
         T v[8];
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
 #pragma unroll
         for (int u2 = 0; u2 < 8; ++u2) {
             const int q = q0 + u2;
-            if (tid < m && q <= tid) F[tid + q * LDT] = q < c ? v[u2] : T(0);
+            if (tid < m && q <= tid) F[tid + q * LD] = q < c ? v[u2] : T(0);
         }
     }
     __syncthreads();
@@ -166,14 +173,12 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
             for (int u2 = 0; u2 < 8; ++u2) {
                 const int j = j0 + u2;
                 const int rj = __shfl(ri, min(j, 63), 64);
-                if (tid < uc && j <= tid) F[ri + rj * LDT] += v[u2];
+                if (tid < uc && j <= tid) F[ri + rj * LD] += v[u2];
             }
         }
         __syncthreads();
     }
     PivTally tl;
-    __shared__ double taus[SMALL_M];
-    __shared__ int sgns[SMALL_M];
     if (tid < c) {
         taus[tid] = fa.tau[(int64_t)n * fa.tstride + d.piv0 + tid];
         sgns[tid] = pivot_sign(fa, d.piv0 + tid);
@@ -182,22 +187,22 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
     __syncthreads();
     for (int j = 0; j < c; ++j) {
         if (tid == 0) {
-            T v = do_pivot(F[j + j * LDT], taus[j], sgns[j], tfb, tl);
-            F[j + j * LDT] = v;
+            T v = do_pivot(F[j + j * LD], taus[j], sgns[j], tfb, tl);
+            F[j + j * LD] = v;
             piv = v;
         }
         __syncthreads();
         const T dj = piv;
-        for (int i = j + 1 + tid; i < m; i += 64) F[i + j * LDT] /= dj;
-        __syncthreads();
-        const int nt = m - j - 1;
-        for (int idx = tid; idx < nt * nt; idx += 64) {
-            int ii = idx % nt, qq = idx / nt;
-            if (ii >= qq) {
-                int i = j + 1 + ii, q = j + 1 + qq;
-                F[i + q * LDT] -= F[i + j * LDT] * dj * F[q + j * LDT];
-            }
+        // multiplier of row tid, then its rank-1 update of columns j < q <= tid
+        T li = T(0);
+        if (tid > j && tid < m) {
+            li = F[tid + j * LD] / dj;
+            F[tid + j * LD] = li;
         }
+        __syncthreads();
+        const T ld = li * dj;
+        if (tid > j && tid < m)
+            for (int q = j + 1; q <= tid; ++q) F[tid + q * LD] -= ld * F[q + j * LD];
         __syncthreads();
     }
     flush_tally(tl, fa.cnt + 4 * n);
@@ -207,23 +212,20 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
         T x = T(0);
         const int i = tid;
         if (i > q && i < c) {
-            x = F[i + q * LDT];
-            for (int t = q + 1; t < i; ++t) x += F[i + t * LDT] * F[t + q * LDT];
+            x = F[i + q * LD];
+            for (int t = q + 1; t < i; ++t) x += F[i + t * LD] * F[t + q * LD];
             x = -x;
         }
         __syncthreads();
-        if (i > q && i < c) F[i + q * LDT] = x;
+        if (i > q && i < c) F[i + q * LD] = x;
         __syncthreads();
     }
-    for (int idx = tid; idx < m * c; idx += 64) {
-        int r = idx % m, q = idx / m;
-        if (r >= q) P[r + (int64_t)q * m] = F[r + q * LDT];
-    }
+    // stores down the columns, lane = row
+    if (tid < m)
+        for (int q = 0; q < c && q <= tid; ++q) P[tid + (int64_t)q * m] = F[tid + q * LD];
     T *Us = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
-    for (int idx = tid; idx < u * u; idx += 64) {
-        int i = idx % u, j = idx / u;
-        if (i >= j) Us[i + (int64_t)j * u] = F[(c + i) + (c + j) * LDT];
-    }
+    if (tid < u)
+        for (int j = 0; j <= tid; ++j) Us[tid + (int64_t)j * u] = F[(c + tid) + (c + j) * LD];
 }
 
 // --------------------------------------------------------------------------
@@ -929,11 +931,18 @@ void launch_scatter(const ScatterArgs &a, FactorArgs<T> fa, int64_t N, hipStream
 }
 
 template <typename T>
-void launch_small_fronts(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *tasks, int ntasks, int64_t N,
+void launch_small_fronts(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *tasks, const int *ncls, int64_t N,
                          const TreeArgs &tr, hipStream_t st) {
-    if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_small_front<T>, dim3(ntasks, (unsigned)N), dim3(64), 0, st, fa, sd, tasks, tr.cptr,
-                       tr.clist, tr.relptr, tr.rel);
+    // tasks: the fronts of at most 16, then 32, then 64 rows (ncls[0..2] of each)
+    if (ncls[0] > 0)
+        hipLaunchKernelGGL((k_small_front<T, 16>), dim3(ncls[0], (unsigned)N), dim3(64), 0, st, fa, sd, tasks,
+                           tr.cptr, tr.clist, tr.relptr, tr.rel);
+    if (ncls[1] > 0)
+        hipLaunchKernelGGL((k_small_front<T, 32>), dim3(ncls[1], (unsigned)N), dim3(64), 0, st, fa, sd,
+                           tasks + ncls[0], tr.cptr, tr.clist, tr.relptr, tr.rel);
+    if (ncls[2] > 0)
+        hipLaunchKernelGGL((k_small_front<T, 64>), dim3(ncls[2], (unsigned)N), dim3(64), 0, st, fa, sd,
+                           tasks + ncls[0] + ncls[1], tr.cptr, tr.clist, tr.relptr, tr.rel);
 }
 
 template <typename T>
@@ -989,7 +998,7 @@ int step_tasks(int kind, int t0, int pe, int c, int m, int win) {
 #define KKT_INST(T)                                                                                        \
     template void launch_zero<T>(T *, int64_t, hipStream_t);                                              \
     template void launch_scatter<T>(const ScatterArgs &, FactorArgs<T>, int64_t, hipStream_t);            \
-    template void launch_small_fronts<T>(FactorArgs<T>, const FrontDesc *, const int32_t *, int, int64_t, \
+    template void launch_small_fronts<T>(FactorArgs<T>, const FrontDesc *, const int32_t *, const int *, int64_t, \
                                          const TreeArgs &, hipStream_t);                                  \
     template void launch_extend_add<T>(FactorArgs<T>, const FrontDesc *, const RowTask *, int, int64_t,   \
                                        const TreeArgs &, hipStream_t);                                    \

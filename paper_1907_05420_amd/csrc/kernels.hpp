@@ -65,7 +65,7 @@ template <typename T> void launch_zero(T *p, int64_t n, hipStream_t st);
 void launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st);
 template <typename T> void launch_scatter(const ScatterArgs &a, FactorArgs<T> fa, int64_t N, hipStream_t st);
 template <typename T>
-void launch_small_fronts(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *tasks, int ntasks, int64_t N,
+void launch_small_fronts(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *tasks, const int *ncls, int64_t N,
                          const TreeArgs &tr, hipStream_t st);
 template <typename T>
 void launch_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const RowTask *tasks, int ntasks, int64_t N,
