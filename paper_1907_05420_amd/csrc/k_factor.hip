@@ -343,8 +343,11 @@ __device__ inline int lane_value(int v, int lane) { return __builtin_amdgcn_read
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int t0) {
-    __shared__ T col[NB];
-    __shared__ T piv;
+    // multipliers and pivot of step j in buffer j % 2: the wave that owns
+    // column j + 1 may write the next step's while the others still read
+    // this one's, so one barrier per step suffices
+    __shared__ T col[2][NB];
+    __shared__ T piv[2];
     const FrontDesc d = sd[fl[blockIdx.x]];
     const int n = blockIdx.y, i = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nb = min(NB, d.c - t0), m = d.m;
@@ -366,35 +369,38 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
             X[k] = (q == i) ? T(1) : T(0);
         }
     }
-    // step j: the pivot in lane j of wave j/16, the multipliers of column j
-    // through LDS, then the rank-1 update of F and the row operation on X
-    // (branch-free so that the LDS reads of a step are issued together)
+    // step j: wave j/16 (which holds column j) takes the pivot from its lane
+    // j, forms the multipliers of column j and publishes both through LDS;
+    // then every wave applies the rank-1 update of F and the row operation
+    // on X (branch-free so that the LDS reads of a step are issued together)
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
 #pragma unroll
         for (int kj = 0; kj < 16; ++kj) {
             const int j = 16 * jb + kj;
             if (j >= nb) break;
-            const double tj = lane_value(my_tau, j);
-            const int sj = lane_value(my_sgn, j);
-            if (w == jb && i == j) {
-                const T v = do_pivot(R[kj], tj, sj, tfb, tl);
-                R[kj] = v;
-                piv = v;
-            }
-            __syncthreads();
-            const T dj = piv;
+            const int ph = j & 1;
             if (w == jb) {
+                const double tj = lane_value(my_tau, j);
+                const int sj = lane_value(my_sgn, j);
+                int cls, pert;
+                const T dj = (T)pivot_rule((double)lane_value(R[kj], j), tj > 0.0 ? tj : tfb, sj, cls, pert);
+                if (i == j) {
+                    tl.add(cls, pert);
+                    R[kj] = dj;
+                }
                 const T l = (i > j && i < nb) ? R[kj] / dj : T(0);
                 if (i > j) R[kj] = l;
-                col[i] = l;
+                col[ph][i] = l;
+                if (i == 0) piv[ph] = dj;
             }
             __syncthreads();
-            const T li = col[i];
+            const T dj = piv[ph];
+            const T li = col[ph][i];
             const T ld = li * dj;
             T cq[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) cq[k] = col[16 * w + k];
+            for (int k = 0; k < 16; ++k) cq[k] = col[ph][16 * w + k];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int q = 16 * w + k;
