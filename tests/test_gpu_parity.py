@@ -76,6 +76,7 @@ SMALL = [
     dict(nb=70, nextra=30, ng=8, ns=43, N=12, nrhs=1, seed=12),      # n_g = 516: last block 4 wide
     dict(nb=40, nextra=20, ng=6, ns=16, N=32, nrhs=1, seed=11),      # n_g = 512: two whole blocks
     dict(nb=50, nextra=25, ng=8, ns=24, N=20, nrhs=3, seed=13),      # n_g = 480: last block 224 wide
+    dict(nb=80, nextra=40, ng=10, ns=50, N=16, nrhs=2, seed=14),     # n_g = 800: a second 512-panel with two halves
 ]
 
 
