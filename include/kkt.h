@@ -77,7 +77,21 @@ typedef struct kkt_options {
     int big_tile_rows;  /* trailing updates of at least this many rows use     */
                         /* 128x128 tiles, smaller ones 64x64; 0 = default 512   */
                         /* (a tile-shape knob for autotuning)                   */
+    int schur_mode;     /* KKT_SCHUR_DENSE (default) or KKT_SCHUR_STRUCTURED    */
 } kkt_options;
+
+/* Factorisation of the Schur complement S (Algorithm 1 step 12):
+ * KKT_SCHUR_DENSE: assemble the dense n_g x n_g S and factor it (LDL^T on
+ *   FP64 MFMA, n_g^3/3 flops, n_g^2 doubles of device memory).
+ * KKT_SCHUR_STRUCTURED: section 4.3 (Eq. GlobalSchur): every block below the
+ *   diagonal of a block column of S is the same N_s x N_s matrix, so block
+ *   elimination keeps that structure and only needs, for j = 1..N, the
+ *   N_s x N_s pivot block S_jj - U_j, the common block below it S_j+1,j - U_j,
+ *   and U_j+1 = U_j + (S_j+1,j - U_j)(S_jj - U_j)^-1 (S_j+1,j - U_j)^T:
+ *   O(N N_s^3) flops and O(N N_s^2) memory. Same solution and inertia up to
+ *   rounding; requires N_s <= 512 (kkt_analyze returns KKT_ERR_ARG beyond). */
+#define KKT_SCHUR_DENSE 0
+#define KKT_SCHUR_STRUCTURED 1
 
 #define KKT_REFINE_FGMRES 0  /* flexible GMRES on K, right-preconditioned by the */
                              /* factorisation; CGS2 orthogonalisation            */

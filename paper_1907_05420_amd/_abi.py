@@ -15,12 +15,15 @@ KKT_FP64 = 0
 KKT_MIXED = 1
 KKT_REFINE_FGMRES = 0
 KKT_REFINE_CLASSIC = 1
+KKT_SCHUR_DENSE = 0
+KKT_SCHUR_STRUCTURED = 1
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("pivot_eps", C.c_double), ("refine_tol", C.c_double),
                 ("refine_max", C.c_int), ("verbose", C.c_int), ("refine_method", C.c_int),
-                ("big_tile_rows", C.c_int)]
+                ("big_tile_rows", C.c_int),
+                ("schur_mode", C.c_int)]
 
 
 class Structure(C.Structure):

@@ -96,6 +96,16 @@ struct kkt_ctx {
     double dw = 0.0, dc = 0.0;
     double *d_S = nullptr, *d_prefix = nullptr, *d_tauS = nullptr, *d_amaxS = nullptr;
     double *d_invtmp = nullptr;  // INV_W x INV_W staging of the block-inverse combination
+    // structured Schur (section 4.3): the N fronts [A_j; B_j] (2 Ns x Ns, ld
+    // 2 Ns; Ns x Ns for the last), G_j = W_j Linv_j and its transpose, the
+    // running U_j and the update block of the current front, and the solve's
+    // recurrences; two planned fronts (full, last) and their launch sequences
+    bool structured = false;
+    double *d_sfront = nullptr, *d_sG = nullptr, *d_sGT = nullptr, *d_sU = nullptr, *d_sUb = nullptr;
+    double *d_ssa = nullptr, *d_saa = nullptr;
+    FrontDesc *d_sfd = nullptr;
+    int32_t *d_sftasks = nullptr;
+    std::vector<StepHost> sf_steps[2];
     int64_t *d_cntS = nullptr;
     // solve workspace
     int64_t ws_nrhs = 0;
@@ -358,7 +368,25 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
     }
     if ((rc = upload(ctx, &ctx->d_tasks, buf))) return rc;
     // Schur front and its steps
-    if (ctx->ng > 0) {
+    if (ctx->ng > 0 && ctx->structured) {
+        const int32_t ns = (int32_t)S.Ns;
+        std::vector<FrontDesc> sf(2);
+        for (int k = 0; k < 2; ++k) {
+            sf[k].Loff = 0;
+            sf[k].Uoff = 0;
+            sf[k].m = k == 0 ? 2 * ns : ns;
+            sf[k].c = ns;
+            sf[k].piv0 = 0;
+            sf[k].sn = 0;
+        }
+        if ((rc = upload(ctx, &ctx->d_sfd, sf))) return rc;
+        std::vector<int32_t> sbuf;
+        for (int k = 0; k < 2; ++k) {
+            ctx->sf_steps[k].clear();
+            plan_steps(sf, std::vector<int32_t>{k}, sbuf, ctx->sf_steps[k], false, ctx->big_rows, OUTER_W, OUTER_W);
+        }
+        if ((rc = upload(ctx, &ctx->d_sftasks, sbuf))) return rc;
+    } else if (ctx->ng > 0) {
         std::vector<FrontDesc> sdS(1);
         sdS[0].Loff = 0;
         sdS[0].Uoff = 0;
@@ -470,7 +498,22 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
     if ((rc = dalloc(ctx, (void **)&ctx->d_A, 8 * S.nnzA * ctx->N))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_C0, 8 * std::max<int64_t>(S.nnzC0, 1)))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_C1, 8 * std::max<int64_t>(S.nnzC1, 1)))) return rc;
-    if (ctx->ng > 0) {
+    if (ctx->ng > 0 && ctx->structured) {
+        const int64_t ns = S.Ns;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_corner, 8 * ctx->ng))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_sfront, 8 * ctx->N * 2 * ns * ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_sG, 8 * ctx->N * ns * ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_sGT, 8 * ctx->N * ns * ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_sU, 8 * ns * ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_sUb, 8 * ns * ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_ssa, 8 * 4 * ctx->ng))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_saa, 8 * 4 * ctx->ng))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_prefix, 8 * (ctx->N + 1) * S.Ns * S.Ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_tauS, 8 * ctx->ng))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_amaxS, 256))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_cntS, 256))) return rc;
+        if (ns > INV_W && (rc = dalloc(ctx, (void **)&ctx->d_invtmp, 8 * INV_W * INV_W))) return rc;
+    } else if (ctx->ng > 0) {
         if ((rc = dalloc(ctx, (void **)&ctx->d_corner, 8 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_S, 8 * ctx->ng * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_prefix, 8 * (ctx->N + 1) * S.Ns * S.Ns))) return rc;
@@ -596,6 +639,46 @@ int factor_blocks(kkt_ctx *ctx) {
     return KKT_OK;
 }
 
+// structured Schur elimination (section 4.3): one front per block column,
+// factored on the main stream; the pivot-block inverse and G_j = W_j Linv_j
+// (used only by the solves) on the side stream
+int factor_schur_structured(kkt_ctx *ctx) {
+    hipStream_t st = ctx->stream;
+    const Symbolic &S = ctx->sy;
+    const int64_t uoff = S.Uoff[S.border_sn], ns = S.Ns, N = ctx->N;
+    const double *corner = ctx->has_corner ? ctx->d_corner : nullptr;
+    launch_struct_tau(ctx->d_U, S.Usize, uoff, N, ns, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_tauS, ctx->eps,
+                      ctx->d_amaxS, st);
+    mark(ctx, 2);
+    launch_zero<double>(ctx->d_sU, ns * ns, st);
+    FactorArgs<double> fa = schur_args(ctx);
+    fa.U = ctx->d_sUb;
+    for (int64_t j = 0; j < N; ++j) {
+        const int last = j + 1 == N ? 1 : 0;
+        double *Fj = ctx->d_sfront + j * 2 * ns * ns;
+        launch_struct_front(ctx->d_U, S.Usize, uoff, ns, j, last, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_sU,
+                            Fj, ctx->d_sUb, st);
+        fa.L = Fj;
+        fa.tau = ctx->d_tauS + j * ns;
+        for (const StepHost &s : ctx->sf_steps[last]) launch_step<double>(fa, ctx->d_sfd, step_dev(s, ctx->d_sftasks), 1, st);
+        if (!last) launch_struct_uacc(ctx->d_sUb, ns, ctx->d_sU, st);
+        // the front is final: its inverse and G_j on the side stream
+        HIPCHK(hipEventRecord(ctx->ev_main, st));
+        HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_main, 0));
+        const int32_t *fl = ctx->d_sftasks + ctx->sf_steps[last].front().fl_off;  // this front's index list {last}
+        launch_inv256(fa, ctx->d_sfd, fl, 0, ctx->side);
+        if (ns > INV_W) {
+            launch_inv256(fa, ctx->d_sfd, fl, INV_W, ctx->side);
+            launch_inv_combine(fa, ctx->d_sfd, fl, 0, (int)ns, ctx->d_invtmp, ctx->side);
+        }
+        if (!last)
+            launch_struct_g(Fj, (int)(2 * ns), (int)ns, ctx->d_sG + j * ns * ns, ctx->d_sGT + j * ns * ns, ctx->side);
+    }
+    HIPCHK(hipEventRecord(ctx->ev_side, ctx->side));
+    HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
+    return KKT_OK;
+}
+
 int factor_schur(kkt_ctx *ctx) {
     if (ctx->ng == 0) return KKT_OK;
     hipStream_t st = ctx->stream;
@@ -603,6 +686,10 @@ int factor_schur(kkt_ctx *ctx) {
     const int64_t uoff = S.Uoff[S.border_sn];
     launch_zero<double>(ctx->d_amaxS, 1, st);
     launch_zero<int64_t>(ctx->d_cntS, 4, st);
+    if (ctx->structured) {
+        launch_schur_prefix(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
+        return factor_schur_structured(ctx);
+    }
     launch_schur_prefix(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
     launch_schur_assemble(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
                           ctx->has_corner ? ctx->d_corner : nullptr, ctx->d_S, ctx->d_tauS, ctx->eps,
@@ -682,8 +769,13 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
     for (const LevelPlan &lp : ctx->levels) launch_fwd_level<T>(L, S.Lsize, ctx->d_sd, tasks_of(lp), tr, sa, st);
     if (ctx->ng > 0) {
         launch_schur_rhs(b, ctx->ntot, S.nA, sa, S.Ns, S.relptr[S.border_sn], ctx->d_bh, st);
-        launch_dense_fwd(ctx->d_S, ctx->ng, ctx->d_bh, ctx->d_y, nrhs, st);
-        launch_dense_bwd(ctx->d_S, ctx->ng, ctx->d_y, ctx->d_xg, nrhs, st);
+        if (ctx->structured) {
+            launch_struct_solve(ctx->d_sfront, ctx->d_sG, ctx->d_sGT, ctx->N, S.Ns, ctx->d_bh, ctx->d_xg, ctx->d_ssa,
+                                ctx->d_saa, nrhs, st);
+        } else {
+            launch_dense_fwd(ctx->d_S, ctx->ng, ctx->d_bh, ctx->d_y, nrhs, st);
+            launch_dense_bwd(ctx->d_S, ctx->ng, ctx->d_y, ctx->d_xg, nrhs, st);
+        }
         launch_border_values(ctx->d_xg, sa, S.nA, S.Ns, st);
     }
     for (int l = (int)ctx->levels.size() - 1; l >= 0; --l) {
@@ -749,6 +841,11 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     if (ctx->opt.precision != KKT_FP64 && ctx->opt.precision != KKT_MIXED) { delete ctx; return KKT_ERR_ARG; }
     if (ctx->opt.refine_tol <= 0) ctx->opt.refine_tol = 1e-10;
     if (ctx->opt.big_tile_rows < 0) { delete ctx; return KKT_ERR_ARG; }
+    if (ctx->opt.schur_mode != KKT_SCHUR_DENSE && ctx->opt.schur_mode != KKT_SCHUR_STRUCTURED) {
+        delete ctx;
+        return KKT_ERR_ARG;
+    }
+    ctx->structured = ctx->opt.schur_mode == KKT_SCHUR_STRUCTURED;
     ctx->big_rows = ctx->opt.big_tile_rows > 0 ? ctx->opt.big_tile_rows : 512;
     if (ctx->opt.refine_max < 0) ctx->opt.refine_max = 0;
     ctx->eps = ctx->opt.pivot_eps > 0 ? ctx->opt.pivot_eps : (ctx->opt.precision == KKT_MIXED ? 1e-10 : 1e-20);
@@ -781,8 +878,11 @@ int analyze_checked(const kkt_structure *s, const kkt_options &o, Symbolic &S) {
         if (o.verbose) std::fprintf(stderr, "kkt_analyze: %s\n", err.c_str());
         return KKT_ERR_STRUCT;
     }
-    // fronts whose solve vectors fit in LDS; 32-bit launch and index limits of S
-    if (S.max_front > MAX_FRONT_ROWS || S.max_pivots > MAX_FRONT_PIVOTS || (s->N * s->Ns) > 46000) {
+    // fronts whose solve vectors fit in LDS; 32-bit launch and index limits of
+    // the dense S; the structured Schur's block inverses cover Ns <= 2 INV_W
+    const bool structured = o.schur_mode == KKT_SCHUR_STRUCTURED;
+    if (S.max_front > MAX_FRONT_ROWS || S.max_pivots > MAX_FRONT_PIVOTS || (!structured && s->N * s->Ns > 46000) ||
+        (structured && s->Ns > 2 * INV_W)) {
         if (o.verbose)
             std::fprintf(stderr, "kkt_analyze: front of %lld rows / %lld pivots or Schur size %lld over the limits\n",
                          (long long)S.max_front, (long long)S.max_pivots, (long long)(s->N * s->Ns));
@@ -816,6 +916,7 @@ int plan_device_bytes(const kkt_structure *s, const kkt_options &o, int64_t nrhs
     kkt_ctx ctx;
     ctx.dry = true;
     ctx.opt = o;
+    ctx.structured = o.schur_mode == KKT_SCHUR_STRUCTURED;
     ctx.big_rows = o.big_tile_rows > 0 ? o.big_tile_rows : 512;
     Symbolic S;
     int rc = analyze_checked(s, o, S);

@@ -892,6 +892,10 @@ __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, cons
         }
 }
 
+void launch_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, hipStream_t st) {
+    hipLaunchKernelGGL(k_inv256, dim3(1), dim3(256), 0, st, fa, sd, fl, j0);
+}
+
 void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, int c, double *tmp,
                         hipStream_t st) {
     const int nbw_b = std::min(INV_W, c - (j0 + INV_W));
@@ -899,6 +903,51 @@ void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_
     const int tiles = ((nbw_b + 63) / 64) * (INV_W / 64);
     for (int mode = 0; mode < 2; ++mode)
         hipLaunchKernelGGL(k_inv_combine, dim3(tiles), dim3(256), 0, st, fa, sd, fl, j0, mode, tmp);
+}
+
+// Structured Schur elimination (section 4.3): G = W Linv for one front, W the
+// N_s x N_s block below its pivot block (rows ns.., ld m) and Linv the
+// inverse of the unit lower pivot block stored strictly below its diagonal
+// (ld m); G (ld ns) and its transpose GT (ld ns) are written out. 64x64 tiles:
+//   G[I][Q] = sum_{K >= Q} W[I][K] Linv[K][Q]   (Linv[Q][Q] unit lower)
+__global__ __launch_bounds__(256) void k_struct_g(const double *F, int m, int ns, double *G, double *GT) {
+    typedef Acc<double>::type acc_t;
+    __shared__ double sA[NB * LDS_LD];
+    __shared__ double sB[NB * LDS_LD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int row = tid & 63, kk = tid >> 6;
+    const int nt = (ns + 63) / 64;
+    const int ti = blockIdx.x / nt, tq = blockIdx.x % nt;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+    for (int k = tq; k < nt; ++k) {
+        __syncthreads();
+        load_tile64(sA, F, m, ns + 64 * ti, 64 * k, m, ns, true, false, row, kk);   // W[I][K]
+        load_tile64(sB, F, m, 64 * k, 64 * tq, ns, ns, false, k == tq, row, kk);   // Linv[K][Q]
+        __syncthreads();
+        tile_mma<double>(sA, sB, acc, lane, w);
+    }
+    __syncthreads();
+    tile_stage<double>(sA, acc, lane, w);
+    __syncthreads();
+    const int i = 64 * ti + row;
+    if (i < ns)
+        for (int c = kk; c < 64; c += 4) {
+            const int q = 64 * tq + c;
+            if (q < ns) {
+                const double v = sA[row + c * LDT];
+                G[i + (int64_t)q * ns] = v;
+                GT[q + (int64_t)i * ns] = v;
+            }
+        }
+}
+
+void launch_struct_g(const double *F, int m, int ns, double *G, double *GT, hipStream_t st) {
+    const int nt = (ns + 63) / 64;
+    hipLaunchKernelGGL(k_struct_g, dim3((unsigned)(nt * nt)), dim3(256), 0, st, F, m, ns, G, GT);
 }
 
 int step_tasks_big(int t0, int pe, int c, int m, int win) {

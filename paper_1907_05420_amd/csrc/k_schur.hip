@@ -8,6 +8,8 @@
 // so every block below the diagonal of a block column is the same matrix.
 // The local blocks S_bar_n = [[S_11, S_10^T], [S_10, S_00]] are the update
 // matrix of the border node of period n (lower triangle, ld 2Ns).
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -89,6 +91,259 @@ __global__ __launch_bounds__(256) void k_mirror_lower(double *S, int64_t ng, int
     for (int idx = tid; idx < 64 * 64; idx += 256) {
         const int q = idx & 63, a = idx >> 6;
         if (a < nr && q < nc && (I > J || q < a)) S[(c0 + q) + (r0 + a) * ng] = T[a + q * 65];
+    }
+}
+
+// ---- structured Schur (section 4.3, Eq. GlobalSchur) ------------------------
+// Block column j (0-based) of S has the diagonal block S_d[j] = C_jj + S_11,j +
+// P_j and, in every row block below it, S_o[j] = S_10,j + P_j (P_j = sum of
+// S_00,n over n < j). Block elimination keeps that structure: with U_0 = 0,
+//   A_j = S_d[j] - U_j,  B_j = S_o[j] - U_j,  U_j+1 = U_j + B_j A_j^-1 B_j^T.
+// Each step is one front [A_j; B_j] (ld 2 Ns, Ns for the last block column)
+// with Ns pivots whose update matrix is -B_j A_j^-1 B_j^T.
+
+// pivot thresholds eps |S_ii| and max |S_ii| from the diagonal of S
+template <typename T>
+__global__ void k_struct_tau(const T *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, const double *prefix,
+                             const double *corner, double *tau_s, double eps, double *amax_s) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N * Ns) return;
+    const int64_t m = r / Ns, i = r % Ns;
+    double v = sbar_at(U + m * Ustride + uoff, 2 * Ns, i, i) + prefix[m * Ns * Ns + i + i * Ns];
+    if (corner) v += corner[r];
+    tau_s[r] = eps * fabs(v);
+    atomic_max_nonneg(amax_s, fabs(v));
+}
+
+template <typename T>
+__global__ void k_struct_front(const T *U, int64_t Ustride, int64_t uoff, int64_t Ns, int64_t j, int last,
+                               const double *prefix, const double *corner, const double *Uacc, double *F,
+                               double *Ub) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // row of the front
+    const int64_t q = blockIdx.y;                                        // pivot column
+    const int64_t mj = last ? Ns : 2 * Ns;
+    const T *Sb = U + j * Ustride + uoff;
+    const double *Pj = prefix + j * Ns * Ns;
+    if (r < mj) {
+        double v = 0.0;
+        if (r < Ns) {
+            if (r >= q) {
+                v = sbar_at(Sb, 2 * Ns, r, q) + Pj[r + q * Ns] - Uacc[r + q * Ns];
+                if (r == q && corner) v += corner[j * Ns + r];
+            }
+        } else {
+            const int64_t i = r - Ns;
+            v = sbar_at(Sb, 2 * Ns, Ns + i, q) + Pj[i + q * Ns] - Uacc[i + q * Ns];
+        }
+        F[r + q * mj] = v;
+    }
+    if (!last && r < Ns) Ub[r + q * Ns] = 0.0;
+}
+
+// U += B A^-1 B^T = -(update matrix, lower triangle in Ub): kept full
+__global__ void k_struct_uacc(const double *Ub, int64_t Ns, double *Uacc) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Ns * Ns) return;
+    const int64_t i = idx % Ns, q = idx / Ns;
+    Uacc[idx] -= i >= q ? Ub[i + q * Ns] : Ub[q + i * Ns];
+}
+
+// Solves with the structured factor. With Linv_j the inverse of front j's
+// unit lower pivot block, D_j its pivots, W_j its block below and G_j =
+// W_j Linv_j, the block factor of S is unit lower with L_j on the diagonal
+// and W_j D_j^-1... in every block of column j below it; the forward
+// substitution carries s_j = sum_{k<j} W_k z_k:
+//   s_j+1 = s_j + G_j (bh_j - s_j),  z_j = Linv_j (bh_j - s_j),  w_j = z_j / D_j
+// and the backward one t_j = sum_{m>j} x_m:
+//   a_j = Linv_j^T w_j,  x_j = a_j - G_j^T t_j,  t_j-1 = t_j + x_j.
+// The recurrences on s and t are one N_s x N_s product per block column (one
+// workgroup walks them); everything else is per block column and parallel.
+constexpr int SC_T = 1024;  // threads of the recurrence kernels
+constexpr int SC_R = 4;     // right-hand sides per pass
+
+// y[i] (+)= sum_q M[i + q ld] x[q] for i < Ns, all threads of the workgroup:
+// thread (i, g) sums over its share of q, partial sums reduced through red
+__device__ inline void sc_matvec(const double *M, int64_t ld, int Ns, const double *x, double *red, double *acc_out,
+                                 int nr, int tid) {
+    const int G = max(1, min(16, SC_T / max(Ns, 1)));
+    const int i = tid % Ns, g = tid / Ns;
+    const bool on = tid < G * Ns;
+    double acc[SC_R] = {0.0, 0.0, 0.0, 0.0};
+    if (on) {
+        const int q0 = (int)((int64_t)Ns * g / G), q1 = (int)((int64_t)Ns * (g + 1) / G);
+        for (int qb = q0; qb < q1; qb += 16) {
+            double mv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) mv[u] = M[i + (int64_t)min(qb + u, q1 - 1) * ld];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int q = min(qb + u, q1 - 1);
+                const double a = qb + u < q1 ? mv[u] : 0.0;
+#pragma unroll
+                for (int r = 0; r < SC_R; ++r) acc[r] += a * x[q * SC_R + r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < SC_R; ++r) red[(g * Ns + i) * SC_R + r] = acc[r];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < Ns * nr; idx += SC_T) {
+        const int ii = idx / nr, r = idx % nr;
+        double t = 0.0;
+        for (int gg = 0; gg < G; ++gg) t += red[(gg * Ns + ii) * SC_R + r];
+        acc_out[ii * SC_R + r] = t;
+    }
+    __syncthreads();
+}
+
+// forward recurrence: s_all[j] = s_j for every block column (nrhs <= SC_R)
+__global__ __launch_bounds__(SC_T) void k_struct_fwd_chain(const double *G, int64_t N, int Ns, const double *bh,
+                                                           int64_t ng, double *s_all, int nrhs) {
+    extern __shared__ double sm[];
+    double *s = sm, *v = sm + (int64_t)Ns * SC_R, *p = v + (int64_t)Ns * SC_R, *red = p + (int64_t)Ns * SC_R;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) s[idx] = 0.0;
+    __syncthreads();
+    for (int64_t j = 0; j < N; ++j) {
+        for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+            const int i = idx / nrhs, r = idx % nrhs;
+            s_all[((int64_t)r * N + j) * Ns + i] = s[i * SC_R + r];
+            v[i * SC_R + r] = bh[(int64_t)r * ng + j * Ns + i] - s[i * SC_R + r];
+        }
+        __syncthreads();
+        if (j + 1 == N) break;
+        sc_matvec(G + j * Ns * Ns, Ns, Ns, v, red, p, nrhs, tid);
+        for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+            const int i = idx / nrhs, r = idx % nrhs;
+            s[i * SC_R + r] += p[i * SC_R + r];
+        }
+        __syncthreads();
+    }
+}
+
+// backward recurrence: x_j = a_j - G_j^T t_j (a_all holds a_j), into xg
+__global__ __launch_bounds__(SC_T) void k_struct_bwd_chain(const double *GT, int64_t N, int Ns, const double *a_all,
+                                                           double *xg, int64_t ng, int nrhs) {
+    extern __shared__ double sm[];
+    double *t = sm, *p = sm + (int64_t)Ns * SC_R, *red = p + (int64_t)Ns * SC_R;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) t[idx] = 0.0;
+    __syncthreads();
+    for (int64_t j = N - 1; j >= 0; --j) {
+        if (j + 1 < N) sc_matvec(GT + j * Ns * Ns, Ns, Ns, t, red, p, nrhs, tid);
+        for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+            const int i = idx / nrhs, r = idx % nrhs;
+            const double x = a_all[((int64_t)r * N + j) * Ns + i] - (j + 1 < N ? p[i * SC_R + r] : 0.0);
+            xg[(int64_t)r * ng + j * Ns + i] = x;
+            t[i * SC_R + r] += x;
+        }
+        __syncthreads();
+    }
+}
+
+// per block column j (workgroup j): z = Linv_j (bh_j - s_j), w = z / D_j,
+// a_j = Linv_j^T w, written to a_all. Linv_j lives below the diagonal of front
+// j's pivot block (ld mj), D_j on its diagonal.
+__global__ __launch_bounds__(256) void k_struct_blocks(const double *F, int64_t N, int Ns, const double *bh,
+                                                       int64_t ng, const double *s_all, double *a_all, int nrhs) {
+    extern __shared__ double sm[];
+    double *v = sm, *w = sm + (int64_t)Ns * SC_R;
+    const int64_t j = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t mj = j + 1 < N ? 2 * (int64_t)Ns : Ns;
+    const double *Fj = F + j * 2 * (int64_t)Ns * Ns;
+    for (int idx = tid; idx < Ns * SC_R; idx += 256) {
+        const int i = idx / SC_R, r = idx % SC_R;
+        v[idx] = r < nrhs ? bh[(int64_t)r * ng + j * Ns + i] - s_all[((int64_t)r * N + j) * Ns + i] : 0.0;
+    }
+    __syncthreads();
+    // w_i = (v_i + sum_{q<i} Linv[i][q] v_q) / D_i, thread per row
+    for (int i = tid; i < Ns; i += 256) {
+        double acc[SC_R];
+#pragma unroll
+        for (int r = 0; r < SC_R; ++r) acc[r] = v[i * SC_R + r];
+        for (int q = 0; q < i; ++q) {
+            const double l = Fj[i + q * mj];
+#pragma unroll
+            for (int r = 0; r < SC_R; ++r) acc[r] += l * v[q * SC_R + r];
+        }
+        const double dinv = 1.0 / Fj[i + (int64_t)i * mj];
+#pragma unroll
+        for (int r = 0; r < SC_R; ++r) w[i * SC_R + r] = acc[r] * dinv;
+    }
+    __syncthreads();
+    // a_q = w_q + sum_{i>q} Linv[i][q] w_i: one wavefront per column q, lanes over i
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int q = wv; q < Ns; q += 4) {
+        double acc[SC_R] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = q + 1 + lane; i < Ns; i += 64) {
+            const double l = Fj[i + (int64_t)q * mj];
+#pragma unroll
+            for (int r = 0; r < SC_R; ++r) acc[r] += l * w[i * SC_R + r];
+        }
+#pragma unroll
+        for (int r = 0; r < SC_R; ++r)
+            for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+        if (lane == 0)
+            for (int r = 0; r < nrhs; ++r) a_all[((int64_t)r * N + j) * Ns + q] = w[q * SC_R + r] + acc[r];
+    }
+}
+
+void launch_struct_tau(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
+                       const double *prefix, const double *corner, double *tau_s, double eps, double *amax_s,
+                       hipStream_t st) {
+    const int64_t ng = N * Ns;
+    const unsigned g = (unsigned)((ng + 255) / 256);
+    if (precision == 1)
+        hipLaunchKernelGGL(k_struct_tau<float>, dim3(g), dim3(256), 0, st, (const float *)U, Ustride, uoff, N, Ns,
+                           prefix, corner, tau_s, eps, amax_s);
+    else
+        hipLaunchKernelGGL(k_struct_tau<double>, dim3(g), dim3(256), 0, st, (const double *)U, Ustride, uoff, N, Ns,
+                           prefix, corner, tau_s, eps, amax_s);
+}
+
+void launch_struct_front(const void *U, int64_t Ustride, int64_t uoff, int64_t Ns, int64_t j, int last, int precision,
+                         const double *prefix, const double *corner, const double *Uacc, double *F, double *Ub,
+                         hipStream_t st) {
+    const int64_t mj = last ? Ns : 2 * Ns;
+    const dim3 g((unsigned)((mj + 255) / 256), (unsigned)Ns);
+    if (precision == 1)
+        hipLaunchKernelGGL(k_struct_front<float>, g, dim3(256), 0, st, (const float *)U, Ustride, uoff, Ns, j, last,
+                           prefix, corner, Uacc, F, Ub);
+    else
+        hipLaunchKernelGGL(k_struct_front<double>, g, dim3(256), 0, st, (const double *)U, Ustride, uoff, Ns, j, last,
+                           prefix, corner, Uacc, F, Ub);
+}
+
+void launch_struct_uacc(const double *Ub, int64_t Ns, double *Uacc, hipStream_t st) {
+    hipLaunchKernelGGL(k_struct_uacc, dim3((unsigned)((Ns * Ns + 255) / 256)), dim3(256), 0, st, Ub, Ns, Uacc);
+}
+
+// bh [nrhs][ng] -> xg [nrhs][ng]; sa, aa: [SC_R][N][Ns] workspace
+void launch_struct_solve(const double *F, const double *G, const double *GT, int64_t N, int64_t Ns, const double *bh,
+                         double *xg, double *sa, double *aa, int64_t nrhs, hipStream_t st) {
+    const int64_t ng = N * Ns;
+    const int Gm = std::max(1, std::min(16, SC_T / (int)std::max<int64_t>(Ns, 1)));
+    const size_t lds_f = sizeof(double) * ((size_t)3 * Ns * SC_R + (size_t)Gm * Ns * SC_R);
+    const size_t lds_b = sizeof(double) * ((size_t)2 * Ns * SC_R + (size_t)Gm * Ns * SC_R);
+    const size_t lds_k = sizeof(double) * ((size_t)2 * Ns * SC_R);
+    if (lds_f > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_struct_fwd_chain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_f);
+    if (lds_b > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_struct_bwd_chain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_b);
+    if (lds_k > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_struct_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_k);
+    for (int64_t k0 = 0; k0 < nrhs; k0 += SC_R) {
+        const int nr = (int)std::min<int64_t>(SC_R, nrhs - k0);
+        hipLaunchKernelGGL(k_struct_fwd_chain, dim3(1), dim3(SC_T), lds_f, st, G, N, (int)Ns, bh + k0 * ng, ng, sa,
+                           nr);
+        hipLaunchKernelGGL(k_struct_blocks, dim3((unsigned)N), dim3(256), lds_k, st, F, N, (int)Ns, bh + k0 * ng, ng,
+                           (const double *)sa, aa, nr);
+        hipLaunchKernelGGL(k_struct_bwd_chain, dim3(1), dim3(SC_T), lds_b, st, GT, N, (int)Ns, (const double *)aa,
+                           xg + k0 * ng, ng, nr);
     }
 }
 

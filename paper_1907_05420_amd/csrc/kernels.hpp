@@ -116,6 +116,20 @@ void launch_schur_assemble(const void *U, int64_t Ustride, int64_t uoff, int64_t
 void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t nb, int precision,
                       double *out, hipStream_t st);
 void launch_mirror_lower(double *S, int64_t ng, hipStream_t st);
+// inverse of the INV_W diagonal block at j0 of the (single) front fl[0]
+void launch_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, hipStream_t st);
+// structured Schur (section 4.3): thresholds from S's diagonal, front j
+// [S_d[j] - U; S_o[j] - U], U accumulation, G_j = W_j Linv_j, and the solve
+void launch_struct_tau(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
+                       const double *prefix, const double *corner, double *tau_s, double eps, double *amax_s,
+                       hipStream_t st);
+void launch_struct_front(const void *U, int64_t Ustride, int64_t uoff, int64_t Ns, int64_t j, int last, int precision,
+                         const double *prefix, const double *corner, const double *Uacc, double *F, double *Ub,
+                         hipStream_t st);
+void launch_struct_uacc(const double *Ub, int64_t Ns, double *Uacc, hipStream_t st);
+void launch_struct_g(const double *F, int m, int ns, double *G, double *GT, hipStream_t st);
+void launch_struct_solve(const double *F, const double *G, const double *GT, int64_t N, int64_t Ns, const double *bh,
+                         double *xg, double *sa, double *aa, int64_t nrhs, hipStream_t st);
 // inverse of the 2*INV_W diagonal block at j0 from its two INV_W inverses
 // (tmp: INV_W x INV_W doubles)
 void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, int c, double *tmp,

@@ -17,6 +17,7 @@ extern "C" void kkt_default_options(kkt_options *opt) {
     opt->verbose = 0;
     opt->refine_method = KKT_REFINE_FGMRES;
     opt->big_tile_rows = 0;
+    opt->schur_mode = KKT_SCHUR_DENSE;
 }
 
 extern "C" const char *kkt_strerror(int code) {

@@ -222,18 +222,60 @@ def test_inertia_correction_shifts():
 
 
 @pytest.mark.parametrize("case", [SMALL[1], SMALL[3], SMALL[5], SMALL[8]])
-@pytest.mark.parametrize("precision", [0, 1])
-def test_plan_equals_footprint(case, precision):
+@pytest.mark.parametrize("precision,schur_mode", [(0, 0), (1, 0), (0, 1)])
+def test_plan_equals_footprint(case, precision, schur_mode):
     """The host-only planning query (used for admission) names exactly the
     device bytes the context holds after analysis and a solve."""
     import paper_1907_05420_amd as pk
     inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
     nrhs = inst.b.shape[0]
     st, _ = pk.kkt_plan(inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind, inst.C0_rowptr,
-                        inst.C0_colind, inst.C1_rowptr, inst.C1_colind, precision=precision, nrhs_max=nrhs)
-    s = pk.Solver(inst, precision=precision)
+                        inst.C0_colind, inst.C1_rowptr, inst.C1_colind, precision=precision, nrhs_max=nrhs,
+                        schur_mode=schur_mode)
+    s = pk.Solver(inst, precision=precision, schur_mode=schur_mode)
     d = pk.device_inputs(inst)
     s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
     s.solve(d["b"])
     assert s.footprint() == st["device_bytes"]
     s.close()
+
+
+@pytest.mark.parametrize("case", SMALL)
+def test_parity_structured_schur(case):
+    """The structured Schur elimination (section 4.3) gives the oracle's
+    solution and inertia, like the dense path."""
+    import paper_1907_05420_amd as pk
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    ref, xref, K = reference(inst)
+    d = pk.device_inputs(inst)
+    s = pk.Solver(inst, schur_mode=pk.KKT_SCHUR_STRUCTURED)
+    rc_f, inn = s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
+    x, rc_s, info = s.solve(d["b"])
+    x = x.cpu().numpy()
+    s.close()
+    rel, _ = ah.rel_residual(inst, x, inst.b, K)
+    assert rel <= 1e-10, rel
+    assert _rel(x, xref) <= 1e-9, _rel(x, xref)
+    assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == ref["inertia"]
+    assert inn["inertia_ok"] == 1 and inn["n_perturbed"] == 0
+
+
+def test_parity_structured_ring30_wide_barrier():
+    import paper_1907_05420_amd as pk
+    inst = kktgen.make_workload(1, rep=1, barrier=(1e-8, 1e8), nrhs=4)
+    ref, xref, K = reference(inst)
+    d = pk.device_inputs(inst)
+    out = {}
+    for mode in (pk.KKT_SCHUR_DENSE, pk.KKT_SCHUR_STRUCTURED):
+        s = pk.Solver(inst, schur_mode=mode)
+        _, inn = s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
+        x, _, info = s.solve(d["b"])
+        out[mode] = (x.cpu().numpy(), inn, info)
+        s.close()
+    xs, inn, info = out[pk.KKT_SCHUR_STRUCTURED]
+    rel, _ = ah.rel_residual(inst, xs, inst.b, K)
+    assert rel <= residual_bar(ref), rel
+    assert inn["inertia_ok"] == 1
+    assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == \
+        (out[pk.KKT_SCHUR_DENSE][1]["n_pos"], out[pk.KKT_SCHUR_DENSE][1]["n_neg"], 0)
+    assert _rel(xs, out[pk.KKT_SCHUR_DENSE][0]) <= 1e-6
