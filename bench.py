@@ -108,8 +108,8 @@ def copy_probe(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}))
 
 
-def measure(args, inst, vals2, prec, log):
-    """Warm up, then time exactly args.steps factor+solve steps."""
+def measure(args, inst, vals2, prec, log, schur_mode=0, steps=None, warmup=None):
+    """Warm up, then time exactly `steps` (default args.steps) factor+solve steps."""
     import numpy as np
     import torch
     import paper_1907_05420_amd as pk
@@ -117,21 +117,24 @@ def measure(args, inst, vals2, prec, log):
     vsets = [d["vals"], torch.as_tensor(vals2).cuda()]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s = pk.Solver(inst, precision=prec,
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    s = pk.Solver(inst, precision=prec, schur_mode=schur_mode,
                   refine_method=pk.KKT_REFINE_CLASSIC if args.refine == "classic" else pk.KKT_REFINE_FGMRES)
     t_analyze = time.perf_counter() - t0
     st = s.stats()
+    st["footprint"] = s.footprint()
     log(f"analyze {t_analyze*1e3:.1f} ms; stats {st}")
     pk.kkt_enable_timing(s.ctx, True)
     x = torch.empty_like(d["b"])
-    for i in range(args.warmup):
+    for i in range(warmup):
         s.factor(vsets[i % 2], d["C0"], d["C1"], d["corner"], want_inertia=False)
         _, rc, info = s.solve(d["b"], x)
         log(f"warmup {i}: rc {rc} info {info} phases {pk.kkt_phase_times(s.ctx)}")
     torch.cuda.synchronize()
     lat, phases, infos, kstats = [], [], [], []
     t_start = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ts = time.perf_counter()
         s.factor(vsets[i % 2], d["C0"], d["C1"], d["corner"], want_inertia=False)
         _, rc, info = s.solve(d["b"], x)
@@ -145,7 +148,7 @@ def measure(args, inst, vals2, prec, log):
     elapsed = time.perf_counter() - t_start
     s.close()
     lat_ms = np.array(lat) * 1e3
-    return dict(value=args.steps / elapsed, elapsed=elapsed, lat_ms=lat_ms, phases=np.array(phases).mean(0).tolist(),
+    return dict(value=steps / elapsed, elapsed=elapsed, lat_ms=lat_ms, phases=np.array(phases).mean(0).tolist(),
                 infos=infos, kstats=kstats, analyze_ms=t_analyze * 1e3, stats=st)
 
 
@@ -325,6 +328,9 @@ def main():
     ap.add_argument("--serve-refine", default="tolerance", choices=["tolerance", "fixed"],
                     help="serve: refine every solve to 1e-10, or a fixed number of steps (--refine-steps)")
     ap.add_argument("--refine-steps", type=int, default=3, help="fixed refinement steps of a batch")
+    ap.add_argument("--schur", default="both", choices=["both", "dense", "structured"],
+                    help="mesh2000_N96: factor S densely (the timed value), by structured block elimination, or "
+                         "both (dense timed, structured reported beside it)")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline()))
@@ -348,7 +354,8 @@ def main():
     rng = np.random.default_rng(kktgen.seed_for(2, 9))
     vals2 = kktgen.redraw_barrier(inst, rng)
     prec = pk.KKT_MIXED if args.precision == "mixed" else pk.KKT_FP64
-    m = measure(args, inst, vals2, prec, log)
+    main_mode = pk.KKT_SCHUR_STRUCTURED if args.schur == "structured" else pk.KKT_SCHUR_DENSE
+    m = measure(args, inst, vals2, prec, log, schur_mode=main_mode)
     ph = m["phases"]
     ng = inst.n_g
     # dominant kernel: the dense Schur trailing update (FP64 MFMA)
@@ -373,7 +380,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "mesh2000_N96", "buses": 2000, "lines": 3000, "generators": 400,
                    "storage": 200, "periods": 96, "block_rows": inst.n_A, "schur_dim": ng, "nrhs": 4,
-                   "barrier_range": [1e-8, 1e8], "precision": args.precision, "refine": args.refine},
+                   "barrier_range": [1e-8, 1e8], "precision": args.precision, "refine": args.refine,
+                   "schur": "structured" if main_mode == pk.KKT_SCHUR_STRUCTURED else "dense"},
         "p50_ms": float(np.percentile(m["lat_ms"], 50)),
         "p99_ms": float(np.percentile(m["lat_ms"], 99)),
         "rel_res": max(i["rel_res"] for i in m["infos"]),
@@ -392,6 +400,19 @@ def main():
                      "flops_per_launch": k_flops / launches if launches else 0.0,
                      "algorithmic_bytes_per_launch": k_bytes / launches if launches else 0.0},
     }
+    if args.schur == "both":
+        # the same workload with S factored by structured block elimination
+        ms = measure(args, inst, vals2, prec, log, schur_mode=pk.KKT_SCHUR_STRUCTURED)
+        ps = ms["phases"]
+        res["schur_structured"] = {
+            "value": ms["value"], "unit": "solves/s", "ms_per_step": ms["elapsed"] / args.steps * 1e3,
+            "speedup_vs_dense": ms["value"] / m["value"],
+            "p50_ms": float(np.percentile(ms["lat_ms"], 50)), "p99_ms": float(np.percentile(ms["lat_ms"], 99)),
+            "rel_res": max(i["rel_res"] for i in ms["infos"]), "omega": max(i["omega"] for i in ms["infos"]),
+            "refine_iters": [i["refine_iters"] for i in ms["infos"]],
+            "phase_ms": {"block_factor": ps[0], "schur_prefix": ps[1], "schur_elimination": ps[2],
+                         "solve_refined": ps[3]},
+            "device_bytes": ms["stats"]["footprint"], "device_bytes_dense": m["stats"]["footprint"]}
     if not args.no_cpu_baseline:
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only"], env=env,

@@ -151,8 +151,8 @@ __global__ void k_struct_uacc(const double *Ub, int64_t Ns, double *Uacc) {
 // Solves with the structured factor. With Linv_j the inverse of front j's
 // unit lower pivot block, D_j its pivots, W_j its block below and G_j =
 // W_j Linv_j, the block factor of S is unit lower with L_j on the diagonal
-// and W_j D_j^-1... in every block of column j below it; the forward
-// substitution carries s_j = sum_{k<j} W_k z_k:
+// and W_j (the front's rows below its pivots) in every block of column j
+// below it; the forward substitution carries s_j = sum_{k<j} W_k z_k:
 //   s_j+1 = s_j + G_j (bh_j - s_j),  z_j = Linv_j (bh_j - s_j),  w_j = z_j / D_j
 // and the backward one t_j = sum_{m>j} x_m:
 //   a_j = Linv_j^T w_j,  x_j = a_j - G_j^T t_j,  t_j-1 = t_j + x_j.
