@@ -128,6 +128,12 @@ typedef struct kkt_solve_info {
                          /* FP64, on the unscaled K                             */
     double omega;        /* componentwise backward error max_i |r_i|/(|K||x|+|b|)_i */
     int fallback_used;   /* 1 when the mixed path fell back to FP64 factors     */
+    double rel_floor;    /* max over right-hand sides of                        */
+                         /* eps || |K||x| + |b| ||_2 / ||b||_2: the rounding    */
+                         /* level of rel_res itself. FGMRES refinement does not */
+                         /* restart after a converged cycle once every          */
+                         /* right-hand side is within 4x of its own floor       */
+                         /* (KKT_WARN_REFINE when rel_res is above the target)  */
 } kkt_solve_info;
 
 typedef struct kkt_symbolic_stats {

@@ -40,7 +40,7 @@ class Inertia(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("refine_iters", C.c_int), ("rel_res", C.c_double), ("omega", C.c_double),
-                ("fallback_used", C.c_int)]
+                ("fallback_used", C.c_int), ("rel_floor", C.c_double)]
 
 
 class SymbolicStats(C.Structure):

@@ -1076,7 +1076,15 @@ constexpr double EPS64 = 2.220446049250313e-16;
 struct RefineState {
     int it = 0, status = KKT_OK;
     double rel = 0.0, omega = 0.0;
+    double floor = 0.0;      // max_k eps || |K||x_k| + |b_k| ||_2 / ||b_k||_2
+    bool at_floor = false;   // every right-hand side within FLOOR_C times its floor
 };
+
+// A residual evaluated in FP64 carries a rounding error of order
+// eps || |K||x| + |b| ||. A restart of the Krylov refinement whose previous
+// cycle converged is skipped once the true residual is within FLOOR_C times
+// that level.
+constexpr double FLOOR_C = 4.0;
 
 // true residual r = b - K x with its norms; returns false on a HIP error
 int true_residual(kkt_ctx *ctx, const ResidualArgs &ra, const double *b, const double *x, double *r, int64_t nrhs,
@@ -1087,13 +1095,19 @@ int true_residual(kkt_ctx *ctx, const ResidualArgs &ra, const double *b, const d
     HIPCHK(hipStreamSynchronize(st));
     rs.rel = 0.0;
     rs.omega = 0.0;
+    rs.floor = 0.0;
+    rs.at_floor = true;
     for (int64_t k = 0; k < nrhs; ++k) {
-        double rb = nh[4 * k + 1] > 0 ? nh[4 * k + 0] / nh[4 * k + 1] : nh[4 * k + 0];
+        const double bn = nh[4 * k + 1] > 0 ? nh[4 * k + 1] : 1.0;
+        const double rb = nh[4 * k + 0] / bn, fl = EPS64 * nh[4 * k + 3] / bn;
         rs.rel = std::max(rs.rel, rb);
         rs.omega = std::max(rs.omega, nh[4 * k + 2]);
+        rs.floor = std::max(rs.floor, fl);
+        if (!(rb <= FLOOR_C * fl)) rs.at_floor = false;
     }
     if (ctx->opt.verbose)
-        std::fprintf(stderr, "kkt_solve: step %d rel_res %.3e omega %.3e\n", rs.it, rs.rel, rs.omega);
+        std::fprintf(stderr, "kkt_solve: step %d rel_res %.3e omega %.3e floor %.3e\n", rs.it, rs.rel, rs.omega,
+                     rs.floor);
     return KKT_OK;
 }
 
@@ -1152,10 +1166,15 @@ int refine_fgmres(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, Refine
     std::vector<double> nh(4 * nrhs), bnorm(nrhs), H((size_t)nrhs * M * ldh), g((size_t)nrhs * ldh),
         cs((size_t)nrhs * M), sn((size_t)nrhs * M);
     double prev_cycle = INFINITY;
+    bool converged = false;  // the last cycle's estimate reached the target
     int rc;
     while (true) {
         if ((rc = true_residual(ctx, ra, b, x, V, nrhs, nh, rs))) return rc;
         if (refine_done(ctx, rs)) break;
+        // the Krylov cycle converged in exact arithmetic and the true residual
+        // sits at its own rounding level: a restart cannot improve it
+        if (converged && rs.at_floor) { rs.status = KKT_WARN_REFINE; break; }
+        converged = false;
         // a restart that did not halve the residual ends refinement
         if (rs.rel > 0.5 * prev_cycle) { rs.status = KKT_WARN_REFINE; break; }
         prev_cycle = rs.rel;
@@ -1201,7 +1220,10 @@ int refine_fgmres(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, Refine
             ++j;
             if (ctx->opt.verbose) std::fprintf(stderr, "kkt_solve:   fgmres %d estimate %.3e\n", rs.it, est);
             if (!std::isfinite(est)) break;
-            if (est <= 0.5 * ctx->opt.refine_tol) break;
+            if (est <= 0.5 * ctx->opt.refine_tol) {
+                converged = true;
+                break;
+            }
         }
         // y = R^-1 g (upper triangular R in the rotated H), x += Z y
         for (int64_t k = 0; k < nrhs; ++k) {
@@ -1250,6 +1272,7 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
         info->rel_res = rs.rel;
         info->omega = rs.omega;
         info->fallback_used = 0;
+        info->rel_floor = rs.floor;
     }
     return rs.status;
 }
@@ -1292,17 +1315,19 @@ extern "C" int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info) {
     std::vector<double> nh(4 * nrhs);
     HIPCHK(hipMemcpyAsync(nh.data(), ctx->d_norms, 8 * 4 * nrhs, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    double rel = 0.0, omega = 0.0;
+    double rel = 0.0, omega = 0.0, fl = 0.0;
     for (int64_t k = 0; k < nrhs; ++k) {
-        const double rb = nh[4 * k + 1] > 0 ? nh[4 * k + 0] / nh[4 * k + 1] : nh[4 * k + 0];
-        rel = std::max(rel, rb);
+        const double bn = nh[4 * k + 1] > 0 ? nh[4 * k + 1] : 1.0;
+        rel = std::max(rel, nh[4 * k + 0] / bn);
         omega = std::max(omega, nh[4 * k + 2]);
+        fl = std::max(fl, EPS64 * nh[4 * k + 3] / bn);
     }
     if (info) {
         info->refine_iters = ctx->async_steps;
         info->rel_res = rel;
         info->omega = omega;
         info->fallback_used = 0;
+        info->rel_floor = fl;
     }
     if (!std::isfinite(rel) || rel > ctx->opt.refine_tol) return KKT_WARN_REFINE;
     return KKT_OK;

@@ -21,15 +21,24 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
+// butterfly sum over the wavefront (the same order on every run)
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // Border rows, one workgroup per (storage unit s, right-hand side k), one
 // thread per period m (chunks of 256 periods with carries):
 //   r_g[m] = b_C[m] - C x_g[m] - C_1 x_m - sum_{n<m} C_0 x_n   (Eq. B12N)
 // and the suffix sums sg[n] = sum_{m>n} x_g[m] used by the period rows. The
-// sums over periods are workgroup scans.
+// sums over periods are workgroup scans. With norms: the largest
+// componentwise error |r_i|/(|K||x| + |b|)_i goes to norms[4k + 2] and the
+// workgroup's sum of (|K||x| + |b|)_i^2 to bpart[k Ns + s].
 __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const double *b, const double *x, double *r,
-                                                    double *sg, double *norms) {
+                                                    double *sg, double *norms, double *bpart) {
     __shared__ double sc[256], sa[256];
     __shared__ double wred[4];
+    double ab2 = 0.0;  // this thread's sum of (|K||x| + |b|)_row^2
     const int64_t s = blockIdx.x;
     const int k = blockIdx.y, tid = threadIdx.x;
     const int64_t ng = ra.N * ra.Ns;
@@ -73,6 +82,7 @@ __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const doubl
             r[(int64_t)k * ra.ntot + ra.N * ra.nA + g] = b ? acc : -acc;
             if (ab > 0.0) wmax = fmax(wmax, fabs(acc) / ab);
             else if (acc != 0.0) wmax = INFINITY;
+            ab2 += ab * ab;
         }
         carry += sc[255];
         carry_abs += sa[255];
@@ -97,6 +107,14 @@ __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const doubl
         if ((tid & 63) == 0) wred[tid >> 6] = wmax;
         __syncthreads();
         if (tid == 0) atomic_max_nonneg(norms + 4 * k + 2, fmax(fmax(wred[0], wred[1]), fmax(wred[2], wred[3])));
+        // fixed-order tree sum of the rows' (|K||x| + |b|)^2 for the floor norm
+        sc[tid] = ab2;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h) sc[tid] += sc[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) bpart[(int64_t)k * ra.Ns + s] = sc[0];
     }
 }
 
@@ -110,7 +128,7 @@ constexpr int RES_B = 8;
 template <int RBT>
 __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const double *b, const double *x, double *r,
                                                      const double *sg, double *wpart) {
-    __shared__ double wred[4 * RBT];
+    __shared__ double wred[4 * RBT], ared[4 * RBT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t nsl = (ra.nA + 63) / 64;
     const int64_t sl = min((int64_t)blockIdx.x * 4 + (tid >> 6), nsl - 1);
@@ -181,26 +199,37 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
                 ab[q] += fabs(t);
             }
         }
-        double wq[RBT];
+        double wq[RBT], aq[RBT];
 #pragma unroll
         for (int q = 0; q < RBT; ++q) {
             wq[q] = 0.0;
+            aq[q] = 0.0;
             if (on && q < nr) {
                 r[(int64_t)(k0 + q) * ra.ntot + (int64_t)n * ra.nA + i] = b ? acc[q] : -acc[q];
                 if (ab[q] > 0.0) wq[q] = fabs(acc[q]) / ab[q];
                 else if (acc[q] != 0.0) wq[q] = INFINITY;
+                aq[q] = ab[q] * ab[q];
             }
         }
         if (wpart) {
+            // per workgroup: the largest componentwise error and the sum of
+            // (|K||x| + |b|)_i^2, both reduced in a fixed order
+            const int64_t nw = (int64_t)gridDim.x * gridDim.y;
+            double *apart = wpart + ra.nrhs * nw;
 #pragma unroll
             for (int q = 0; q < RBT; ++q) {
-                const double wm = wave_max(wq[q]);
-                if (lane == 0) wred[q * 4 + (tid >> 6)] = wm;
+                const double wm = wave_max(wq[q]), as = wave_sum(aq[q]);
+                if (lane == 0) {
+                    wred[q * 4 + (tid >> 6)] = wm;
+                    ared[q * 4 + (tid >> 6)] = as;
+                }
             }
             __syncthreads();
-            if (tid < nr)
-                wpart[(int64_t)(k0 + tid) * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] =
-                    fmax(fmax(wred[tid * 4 + 0], wred[tid * 4 + 1]), fmax(wred[tid * 4 + 2], wred[tid * 4 + 3]));
+            if (tid < nr) {
+                const int64_t o = (int64_t)(k0 + tid) * nw + blockIdx.y * gridDim.x + blockIdx.x;
+                wpart[o] = fmax(fmax(wred[tid * 4 + 0], wred[tid * 4 + 1]), fmax(wred[tid * 4 + 2], wred[tid * 4 + 3]));
+                apart[o] = (ared[tid * 4 + 0] + ared[tid * 4 + 1]) + (ared[tid * 4 + 2] + ared[tid * 4 + 3]);
+            }
             __syncthreads();
         }
     }
@@ -260,25 +289,34 @@ __global__ __launch_bounds__(256) void k_norm_partial(const double *r, const dou
     }
 }
 
+// norms[4k + 0..3] = ||r_k||_2, ||b_k||_2, max_i |r_i|/(|K||x| + |b|)_i and
+// || |K||x_k| + |b_k| ||_2 (the scale of the rounding error of r itself)
 __global__ __launch_bounds__(256) void k_norm_final(const double *part, const double *wpart, int64_t nw,
-                                                    double *norms) {
-    __shared__ double s1[256], s2[256], s3[256];
+                                                    const double *bpart, int64_t nb, int64_t nrhs, double *norms) {
+    __shared__ double s1[256], s2[256], s3[256], s4[256];
     const int k = blockIdx.x;
-    double a = 0.0, c = 0.0, w = 0.0;
+    const double *apart = wpart + nrhs * nw;
+    double a = 0.0, c = 0.0, w = 0.0, f = 0.0;
     for (int p = threadIdx.x; p < NPART; p += 256) {
         a += part[((int64_t)k * NPART + p) * 2 + 0];
         c += part[((int64_t)k * NPART + p) * 2 + 1];
     }
-    for (int64_t p = threadIdx.x; p < nw; p += 256) w = fmax(w, wpart[(int64_t)k * nw + p]);
+    for (int64_t p = threadIdx.x; p < nw; p += 256) {
+        w = fmax(w, wpart[(int64_t)k * nw + p]);
+        f += apart[(int64_t)k * nw + p];
+    }
+    for (int64_t p = threadIdx.x; p < nb; p += 256) f += bpart[(int64_t)k * nb + p];
     s1[threadIdx.x] = a;
     s2[threadIdx.x] = c;
     s3[threadIdx.x] = w;
+    s4[threadIdx.x] = f;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             s1[threadIdx.x] += s1[threadIdx.x + s];
             s2[threadIdx.x] += s2[threadIdx.x + s];
             s3[threadIdx.x] = fmax(s3[threadIdx.x], s3[threadIdx.x + s]);
+            s4[threadIdx.x] += s4[threadIdx.x + s];
         }
         __syncthreads();
     }
@@ -286,6 +324,7 @@ __global__ __launch_bounds__(256) void k_norm_final(const double *part, const do
         norms[4 * k + 0] = sqrt(s1[0]);
         norms[4 * k + 1] = sqrt(s2[0]);
         norms[4 * k + 2] = fmax(norms[4 * k + 2], s3[0]);
+        norms[4 * k + 3] = sqrt(s4[0]);
     }
 }
 
@@ -295,7 +334,9 @@ __global__ void k_zero_norms(double *norms, int nrhs) {
 }
 
 int64_t residual_work(int64_t N, int64_t nA, int64_t Ns, int64_t nrhs) {
-    return N * Ns * nrhs + 2 * NPART * nrhs + ((nA + 255) / 256) * N * nrhs + 8;
+    // sg, norm partials, per-workgroup max and floor partials, border partials
+    return std::max<int64_t>(N * Ns * nrhs, 1) + 2 * NPART * nrhs + 2 * ((nA + 255) / 256) * N * nrhs + Ns * nrhs +
+           8;
 }
 
 static void launch_res_periods(const ResidualArgs &ra, const double *b, const double *x, double *r, const double *sg,
@@ -314,12 +355,14 @@ void launch_residual(const ResidualArgs &ra, const double *b, const double *x, d
     double *part = work + std::max<int64_t>(ra.N * ra.Ns * ra.nrhs, 1);
     double *wpart = part + 2 * NPART * ra.nrhs;
     const int64_t nw = ((ra.nA + 255) / 256) * ra.N;
+    double *bpart = wpart + 2 * nw * ra.nrhs;
     if (ra.Ns > 0)
         hipLaunchKernelGGL(k_res_border, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra, b, x, r, sg,
-                           norms);
+                           norms, bpart);
     launch_res_periods(ra, b, x, r, sg, wpart, st);
     hipLaunchKernelGGL(k_norm_partial, dim3(NPART, (unsigned)ra.nrhs), dim3(256), 0, st, r, b, ra.ntot, part);
-    hipLaunchKernelGGL(k_norm_final, dim3((unsigned)ra.nrhs), dim3(256), 0, st, part, wpart, nw, norms);
+    hipLaunchKernelGGL(k_norm_final, dim3((unsigned)ra.nrhs), dim3(256), 0, st, part, wpart, nw, bpart, ra.Ns,
+                       ra.nrhs, norms);
 }
 
 // y = K x (no norms)
@@ -327,7 +370,7 @@ void launch_matvec(const ResidualArgs &ra, const double *x, double *y, double *w
     double *sg = work;
     if (ra.Ns > 0)
         hipLaunchKernelGGL(k_res_border, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra,
-                           (const double *)nullptr, x, y, sg, (double *)nullptr);
+                           (const double *)nullptr, x, y, sg, (double *)nullptr, (double *)nullptr);
     launch_res_periods(ra, nullptr, x, y, sg, nullptr, st);
 }
 

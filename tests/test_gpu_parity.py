@@ -279,3 +279,21 @@ def test_parity_structured_ring30_wide_barrier():
     assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == \
         (out[pk.KKT_SCHUR_DENSE][1]["n_pos"], out[pk.KKT_SCHUR_DENSE][1]["n_neg"], 0)
     assert _rel(xs, out[pk.KKT_SCHUR_DENSE][0]) <= 1e-6
+
+
+def test_residual_floor_reported():
+    """rel_floor = eps || |K||x| + |b| ||_2 / ||b||_2 of the returned x, from
+    the oracle's assembled K (the GPU sums in another order: 1e-6 relative)."""
+    import paper_1907_05420_amd as pk
+    inst = kktgen.make_workload(1, rep=1, barrier=(1e-8, 1e8), nrhs=4)
+    K = ah.assemble(inst)
+    d = pk.device_inputs(inst)
+    s = pk.Solver(inst)
+    s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
+    x, _, info = s.solve(d["b"])
+    x = x.cpu().numpy()
+    s.close()
+    scale = np.abs(K) @ np.abs(x).T + np.abs(inst.b).T
+    ref = max(2.220446049250313e-16 * np.linalg.norm(scale[:, k]) / np.linalg.norm(inst.b[k])
+              for k in range(inst.b.shape[0]))
+    assert abs(info["rel_floor"] - ref) <= 1e-6 * ref, (info["rel_floor"], ref)
