@@ -371,42 +371,68 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
     }
     // step j: wave j/16 (which holds column j) takes the pivot from its lane
     // j, forms the multipliers of column j and publishes both through LDS;
-    // then every wave applies the rank-1 update of F and the row operation
-    // on X (branch-free so that the LDS reads of a step are issued together)
-#pragma unroll
+    // then the rank-1 update of F applies to the columns right of j and the
+    // row operation on X to the columns up to j. Which of the two a wave's
+    // columns need is uniform over the wave (left of the pivot wave: X only,
+    // right of it: F only), so the three kinds of wave run separate,
+    // select-free step loops with the same barriers.
+#pragma unroll 1
     for (int jb = 0; jb < 4; ++jb) {
+        if (16 * jb >= nb) break;
+        if (w == jb) {
 #pragma unroll
-        for (int kj = 0; kj < 16; ++kj) {
-            const int j = 16 * jb + kj;
-            if (j >= nb) break;
-            const int ph = j & 1;
-            if (w == jb) {
-                const double tj = lane_value(my_tau, j);
-                const int sj = lane_value(my_sgn, j);
-                int cls, pert;
-                const T dj = (T)pivot_rule((double)lane_value(R[kj], j), tj > 0.0 ? tj : tfb, sj, cls, pert);
-                if (i == j) {
-                    tl.add(cls, pert);
-                    R[kj] = dj;
+            for (int kj = 0; kj < 16; ++kj) {
+                const int j = 16 * jb + kj;
+                if (j < nb) {
+                    const int ph = kj & 1;
+                    const double tj = lane_value(my_tau, j);
+                    const int sj = lane_value(my_sgn, j);
+                    int cls, pert;
+                    const T dj = (T)pivot_rule((double)lane_value(R[kj], j), tj > 0.0 ? tj : tfb, sj, cls, pert);
+                    if (i == j) {
+                        tl.add(cls, pert);
+                        R[kj] = dj;
+                    }
+                    const T l = (i > j && i < nb) ? R[kj] / dj : T(0);
+                    if (i > j) R[kj] = l;
+                    col[ph][i] = l;
+                    if (i == 0) piv[ph] = dj;
+                    __syncthreads();
+                    const T li = col[ph][i];
+                    const T ld = li * piv[ph];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        if (k > kj) R[k] -= ld * col[ph][16 * w + k];
+                        else X[k] -= li * lane_value(X[k], j);
+                    }
                 }
-                const T l = (i > j && i < nb) ? R[kj] / dj : T(0);
-                if (i > j) R[kj] = l;
-                col[ph][i] = l;
-                if (i == 0) piv[ph] = dj;
             }
-            __syncthreads();
-            const T dj = piv[ph];
-            const T li = col[ph][i];
-            const T ld = li * dj;
-            T cq[16];
+        } else if (w > jb) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) cq[k] = col[ph][16 * w + k];
+            for (int kj = 0; kj < 16; ++kj) {
+                const int j = 16 * jb + kj;
+                if (j < nb) {
+                    const int ph = kj & 1;
+                    __syncthreads();
+                    const T ld = col[ph][i] * piv[ph];
+                    T cq[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int q = 16 * w + k;
-                const T xj = lane_value(X[k], j);
-                R[k] = q > j ? R[k] - ld * cq[k] : R[k];
-                X[k] = (q <= j && i > j) ? X[k] - li * xj : X[k];
+                    for (int k = 0; k < 16; ++k) cq[k] = col[ph][16 * w + k];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) R[k] -= ld * cq[k];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kj = 0; kj < 16; ++kj) {
+                const int j = 16 * jb + kj;
+                if (j < nb) {
+                    const int ph = kj & 1;
+                    __syncthreads();
+                    const T li = col[ph][i];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) X[k] -= li * lane_value(X[k], j);
+                }
             }
         }
     }
