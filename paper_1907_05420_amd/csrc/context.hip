@@ -36,11 +36,12 @@ namespace {
 
 // kind 0-6: launches (see StepDev); SYNC_TO_SIDE: the side stream waits for
 // the main stream's work so far; SYNC_TO_MAIN: the main stream waits for the
-// side stream's work so far.
-constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101;
+// side stream's work so far; SYNC_TO_INV / SYNC_INV_TO_MAIN: the same between
+// the main stream and the stream of the diagonal-block inverses.
+constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101, SYNC_TO_INV = 102, SYNC_INV_TO_MAIN = 103;
 struct StepHost {
     int kind, win, t0, pe, nf, ntasks;
-    int side;                 // 1: enqueued on the side stream
+    int side;                 // 0: main stream, 1: side stream, 2: inverse stream
     int64_t fl_off, pre_off;  // offsets (int32 elements) into the task buffer
 };
 
@@ -119,6 +120,8 @@ struct kkt_ctx {
     // side stream and events of the lookahead
     hipStream_t side = nullptr;
     hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    hipStream_t inv = nullptr;  // inverses of the dense factor's diagonal blocks
+    hipEvent_t ev_inv_main = nullptr, ev_inv = nullptr;
     // timing
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -233,29 +236,41 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
         // the next sub-panel's columns in one rank-inner_w product.
         for (int s0 = k; s0 < std::min(pe, cmax); s0 += inner_w) {
             const int se = std::min(s0 + inner_w, pe);
+            // with lookahead (the dense Schur factor, whose pivot blocks run
+            // beside the side stream's updates) the 64-column steps stay
+            // inside the sub-panel's diagonal block, and the rows below it
+            // take all of the sub-panel's columns in one launch
             for (int j0 = s0; j0 < std::min(se, cmax); j0 += 64) {
                 add(0, j0, se);
-                add(1, j0, se);
-                add(2, j0, se);
+                add(1, j0, se, lookahead ? 3 : 0);
+                add(2, j0, se, lookahead ? 3 : 0);
             }
+            if (lookahead) add(7, s0, se);
             if (se < std::min(pe, cmax)) add(big_from(s0, se) ? 4 : 3, s0, se, 1, 0);
         }
-        // the next panel's columns: the side stream's update from the
-        // previous panel must be done before this panel's update of them
-        if (lookahead && k > 0) sync(SYNC_TO_MAIN);
         const int big = big_from(k, pe);
         if (!lookahead) {
             add(big ? 4 : 3, k, pe);
             continue;
         }
-        add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
+        // the panel is factored: the side stream may update the columns
+        // beyond the next panel with it (after its own previous update), and
+        // the inverse stream may invert its diagonal blocks, which only the
+        // dense solves use and no later step of the factorisation reads
         sync(SYNC_TO_SIDE);
-        for (int j0 = k; j0 < std::min(pe, cmax); j0 += INV_W)
-            add(5, j0, pe, 0, 1);       // inverses of the panel's diagonal blocks (dense solves)
-        if (outer_w == 2 * INV_W) add(6, k, pe, 0, 1);  // and of the whole panel's diagonal block
+        sync(SYNC_TO_INV);
+        for (int j0 = k; j0 < std::min(pe, cmax); j0 += INV_W) add(5, j0, pe, 0, 2);
+        if (outer_w == 2 * INV_W) add(6, k, pe, 0, 2);  // and of the whole panel's diagonal block
+        // the next panel's columns: the side stream's update from the
+        // previous panel must be done before this panel's update of them
+        if (k > 0) sync(SYNC_TO_MAIN);
+        add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
         add(big ? 4 : 3, k, pe, 2, 1);  // the rest, side stream
     }
-    if (lookahead) sync(SYNC_TO_MAIN);
+    if (lookahead) {
+        sync(SYNC_TO_MAIN);
+        sync(SYNC_INV_TO_MAIN);
+    }
 }
 
 StepDev step_dev(const StepHost &s, const int32_t *base) {
@@ -705,8 +720,14 @@ int factor_schur(kkt_ctx *ctx) {
         } else if (s.kind == SYNC_TO_MAIN) {
             HIPCHK(hipEventRecord(ctx->ev_side, ctx->side));
             HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
+        } else if (s.kind == SYNC_TO_INV) {
+            HIPCHK(hipEventRecord(ctx->ev_inv_main, st));
+            HIPCHK(hipStreamWaitEvent(ctx->inv, ctx->ev_inv_main, 0));
+        } else if (s.kind == SYNC_INV_TO_MAIN) {
+            HIPCHK(hipEventRecord(ctx->ev_inv, ctx->inv));
+            HIPCHK(hipStreamWaitEvent(st, ctx->ev_inv, 0));
         } else {
-            hipStream_t ss = s.side ? ctx->side : st;
+            hipStream_t ss = s.side == 2 ? ctx->inv : s.side ? ctx->side : st;
             const bool timed = ctx->timing && s.kind == 4;
             if (timed) {
                 if ((size_t)(2 * ctx->kcount + 2) > ctx->kev.size()) {
@@ -853,7 +874,10 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return KKT_ERR_HIP; }
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->inv, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_inv_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_inv, hipEventDisableTiming) != hipSuccess) {
         kkt_destroy(ctx);
         return KKT_ERR_HIP;
     }
@@ -1383,8 +1407,12 @@ extern "C" void kkt_destroy(kkt_ctx *ctx) {
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->kev) (void)hipEventDestroy(e);
+    if (ctx->inv) (void)hipStreamSynchronize(ctx->inv);
     if (ctx->ev_main) (void)hipEventDestroy(ctx->ev_main);
     if (ctx->ev_side) (void)hipEventDestroy(ctx->ev_side);
+    if (ctx->ev_inv_main) (void)hipEventDestroy(ctx->ev_inv_main);
+    if (ctx->ev_inv) (void)hipEventDestroy(ctx->ev_inv);
+    if (ctx->inv) (void)hipStreamDestroy(ctx->inv);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }

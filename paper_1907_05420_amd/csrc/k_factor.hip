@@ -38,7 +38,13 @@ __device__ inline double pivot_rule(double raw, double t, int sgn, int &cls, int
 // per-thread tallies of pivot signs, flushed with one atomic per counter
 struct PivTally {
     int c[4] = {0, 0, 0, 0};
-    __device__ void add(int cls, int pert) { c[cls]++; c[3] += pert; }
+    // no dynamic index: the counters stay in registers
+    __device__ void add(int cls, int pert) {
+        c[0] += cls == 0;
+        c[1] += cls == 1;
+        c[2] += cls == 2;
+        c[3] += pert;
+    }
 };
 
 // expected sign of pivot gpiv (dual pivots and the Schur complement: -1)
@@ -242,8 +248,9 @@ __device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q);
 // first store.
 template <typename T, int NJ>
 __device__ inline void rmw_sub_row(T *P, T *Ub, int m, int c, int r, int qb, int j0, int js, int qhi, const T *sC,
-                                   int ldc) {
-    const int rc = min(r, m - 1);
+                                   int ldc, int rlim = -1) {
+    const int rl = rlim < 0 ? m : rlim;  // rows below rl are not updated
+    const int rc = min(r, rl - 1);
     const int lim = min(rc, qhi - 1);
     T o[NJ];
 #pragma unroll
@@ -251,7 +258,7 @@ __device__ inline void rmw_sub_row(T *P, T *Ub, int m, int c, int r, int qb, int
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
         const int j = j0 + js * jj, q = qb + j;
-        if (r < m && q <= r && q < qhi) *front_addr(P, Ub, m, c, r, q) = o[jj] - sC[j * ldc];
+        if (r < rl && q <= r && q < qhi) *front_addr(P, Ub, m, c, r, q) = o[jj] - sC[j * ldc];
     }
 }
 
@@ -343,11 +350,9 @@ __device__ inline int lane_value(int v, int lane) { return __builtin_amdgcn_read
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int t0) {
-    // multipliers and pivot of step j in buffer j % 2: the wave that owns
-    // column j + 1 may write the next step's while the others still read
-    // this one's, so one barrier per step suffices
-    __shared__ T col[2][NB];
-    __shared__ T piv[2];
+    // multipliers and pivots of a 16-column block, double-buffered by block
+    __shared__ T Ls[2][16][NB];
+    __shared__ T Ds[2][16];
     const FrontDesc d = sd[fl[blockIdx.x]];
     const int n = blockIdx.y, i = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nb = min(NB, d.c - t0), m = d.m;
@@ -369,22 +374,23 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
             X[k] = (q == i) ? T(1) : T(0);
         }
     }
-    // step j: wave j/16 (which holds column j) takes the pivot from its lane
-    // j, forms the multipliers of column j and publishes both through LDS;
-    // then the rank-1 update of F applies to the columns right of j and the
-    // row operation on X to the columns up to j. Which of the two a wave's
-    // columns need is uniform over the wave (left of the pivot wave: X only,
-    // right of it: F only), so the three kinds of wave run separate,
-    // select-free step loops with the same barriers.
+    // Block jb of 16 columns belongs to wave jb (lane = row). That wave
+    // eliminates its 16 columns alone, with cross-lane reads and no barrier:
+    // step j takes the pivot from lane j, forms the multipliers of column j
+    // for all rows and updates its own later columns. It publishes the
+    // block's multipliers and pivots once; then the waves right of it apply
+    // the block's 16 rank-1 updates to their columns, and the waves up to it
+    // the block's row operations on X = L^-1, both in step order (the same
+    // operations in the same order as one step at a time).
 #pragma unroll 1
     for (int jb = 0; jb < 4; ++jb) {
         if (16 * jb >= nb) break;
+        const int bf = jb & 1;
         if (w == jb) {
 #pragma unroll
             for (int kj = 0; kj < 16; ++kj) {
                 const int j = 16 * jb + kj;
                 if (j < nb) {
-                    const int ph = kj & 1;
                     const double tj = lane_value(my_tau, j);
                     const int sj = lane_value(my_sgn, j);
                     int cls, pert;
@@ -395,31 +401,35 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
                     }
                     const T l = (i > j && i < nb) ? R[kj] / dj : T(0);
                     if (i > j) R[kj] = l;
-                    col[ph][i] = l;
-                    if (i == 0) piv[ph] = dj;
-                    __syncthreads();
-                    const T li = col[ph][i];
-                    const T ld = li * piv[ph];
+                    Ls[bf][kj][i] = l;
+                    if (i == 0) Ds[bf][kj] = dj;
+                    const T ld = l * dj;
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        if (k > kj) R[k] -= ld * col[ph][16 * w + k];
-                        else X[k] -= li * lane_value(X[k], j);
-                    }
+                    for (int k = kj + 1; k < 16; ++k) R[k] -= ld * lane_value(l, 16 * jb + k);
                 }
             }
-        } else if (w > jb) {
+        }
+        __syncthreads();
+        if (w > jb) {
+#pragma unroll
+            for (int kj = 0; kj < 16; ++kj) {
+                if (16 * jb + kj < nb) {
+                    const T ld = Ls[bf][kj][i] * Ds[bf][kj];
+                    T cq[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) cq[k] = Ls[bf][kj][16 * w + k];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) R[k] -= ld * cq[k];
+                }
+            }
+        } else if (w < jb) {
 #pragma unroll
             for (int kj = 0; kj < 16; ++kj) {
                 const int j = 16 * jb + kj;
                 if (j < nb) {
-                    const int ph = kj & 1;
-                    __syncthreads();
-                    const T ld = col[ph][i] * piv[ph];
-                    T cq[16];
+                    const T li = Ls[bf][kj][i];
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) cq[k] = col[ph][16 * w + k];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) R[k] -= ld * cq[k];
+                    for (int k = 0; k < 16; ++k) X[k] -= li * lane_value(X[k], j);
                 }
             }
         } else {
@@ -427,11 +437,9 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
             for (int kj = 0; kj < 16; ++kj) {
                 const int j = 16 * jb + kj;
                 if (j < nb) {
-                    const int ph = kj & 1;
-                    __syncthreads();
-                    const T li = col[ph][i];
+                    const T li = Ls[bf][kj][i];
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) X[k] -= li * lane_value(X[k], j);
+                    for (int k = 0; k <= kj; ++k) X[k] -= li * lane_value(X[k], j);
                 }
             }
         }
@@ -492,7 +500,7 @@ __device__ inline void tile_stage(T *sC, typename Acc<T>::type (&acc)[2][2], int
 // per 64-row tile (L11^-1 is stored in the pivot block).
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
-                                              const int32_t *pre, int nf, int t0) {
+                                              const int32_t *pre, int nf, int t0, int pe, int win) {
     typedef typename Acc<T>::type acc_t;
     __shared__ T sA[NB * LDS_LD];
     __shared__ T sB[NB * LDS_LD];
@@ -501,12 +509,13 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
     const FrontDesc d = sd[fl[fi]];
     const int n = blockIdx.y, tid = threadIdx.x;
     const int nb = min(NB, d.c - t0), m = d.m;
+    const int mr = win == 3 ? min(pe, d.c) : m;  // rows below mr are left to k_panel_trsm
     const int R0 = t0 + nb + (blockIdx.x - pre[fi]) * 64;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     {
         // clamped addresses, all loads issued before the first use
         const int row = tid & 63, kk = tid >> 6;
-        const T *Pa = P + min(R0 + row, m - 1) + (int64_t)t0 * m;
+        const T *Pa = P + min(R0 + row, mr - 1) + (int64_t)t0 * m;
         const T *Pb = P + (t0 + min(row, nb - 1)) + (int64_t)t0 * m;
         T va[16], vb[16];
 #pragma unroll
@@ -519,7 +528,7 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int k = kk + 4 * j;
-            sA[k * LDS_LD + row] = (k < nb && R0 + row < m) ? va[j] : T(0);
+            sA[k * LDS_LD + row] = (k < nb && R0 + row < mr) ? va[j] : T(0);
             // B[q = row][k] = (L11^-1)[row][k]
             sB[k * LDS_LD + row] = (row < nb && k < nb) ? (k < row ? vb[j] : (k == row ? T(1) : T(0))) : T(0);
         }
@@ -539,8 +548,134 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
     __syncthreads();
     const int row = tid & 63;
     const int r = R0 + row;
-    if (r < m)
+    if (r < mr)
         for (int q = tid >> 6; q < nb; q += 4) P[r + (int64_t)(t0 + q) * m] = sC[row + q * LDT] / Ds[q];
+}
+
+// Rows below a factored sub-panel (columns [t0, cend), cend = min(pe, c), at
+// most 4 pivot blocks of 64): L21 = A21 L11^-T D^-1 for the rows [cend, m),
+// one 64-row tile per workgroup. For column block b of the sub-panel,
+//   V_b = A21_b - sum_{c<b} L21_c D_c L_bc^T,   L21_b = V_b X_b^T D_b^-1,
+// with L_bc the factored diagonal block's sub-block and X_b the stored
+// inverse of its unit lower 64x64 diagonal block b: the per-block triangular
+// solves and in-panel updates of the rows below, done for one row tile at a
+// time (one launch per sub-panel instead of two per pivot block). The tile's
+// finished blocks L21_c stay in registers (accumulator layout) and pass
+// through LDS as MFMA operands.
+__device__ inline void acc_to_kmajor(double *sA, const v4d (&acc)[2][2], const double *scale, int lane, int w) {
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int r = wr + bi * 16 + mfma_row(0.0, lk, rr), k = wc + bj * 16 + li;
+                sA[k * LDS_LD + r] = acc[bi][bj][rr] * (scale ? scale[k] : 1.0);
+            }
+}
+
+__global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl,
+                                                    const int32_t *pre, int nf, int t0, int pe) {
+    __shared__ double sA[NB * LDS_LD];
+    __shared__ double sB[NB * LDS_LD];
+    __shared__ double sD[4 * NB];
+    const int fi = find_front(pre, nf, blockIdx.x);
+    const FrontDesc d = sd[fl[fi]];
+    const int n = blockIdx.y, tid = threadIdx.x;
+    const int m = d.m, cend = min(pe, d.c), W = cend - t0;
+    const int R0 = cend + (blockIdx.x - pre[fi]) * 64;
+    double *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
+    const int lane = tid & 63, w = tid >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
+    const int row = tid & 63, kk = tid >> 6;
+    for (int k = tid; k < 4 * NB; k += 256) sD[k] = k < W ? P[(t0 + k) + (int64_t)(t0 + k) * m] : 1.0;
+    const int rowc = min(R0 + row, m - 1);  // clamped row of this thread's loads
+    v4d Lr[4][2][2];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) Lr[b][bi][bj] = v4d{0, 0, 0, 0};
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int cb = t0 + 64 * b;
+        if (cb < cend) {
+            const int nbb = min(64, cend - cb);
+            v4d acc[2][2];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0, 0, 0, 0};
+            // acc = sum_{c<b} L21_c D_c L_bc^T (blocks c < b are full 64 wide)
+#pragma unroll
+            for (int c = 0; c < b; ++c) {
+                double vb[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    vb[j] = P[(cb + min(row, nbb - 1)) + (int64_t)(t0 + 64 * c + kk + 4 * j) * m];
+                acc_to_kmajor(sA, Lr[c], sD + 64 * c, lane, w);
+#pragma unroll
+                for (int j = 0; j < 16; ++j) sB[(kk + 4 * j) * LDS_LD + row] = row < nbb ? vb[j] : 0.0;
+                __syncthreads();
+                tile_mma<double>(sA, sB, acc, lane, w);
+                __syncthreads();
+            }
+            // V = A21_b - acc, k-major in sA; X_b^T operand in sB
+            {
+                double va[16], vx[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int k = min(kk + 4 * j, nbb - 1);
+                    va[j] = P[rowc + (int64_t)(cb + k) * m];
+                    vx[j] = P[(cb + min(row, nbb - 1)) + (int64_t)(cb + k) * m];
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int k = kk + 4 * j;
+                    sA[k * LDS_LD + row] = (k < nbb && R0 + row < m) ? va[j] : 0.0;
+                    // sB[k][q] = X_b(q, k): unit lower, stored strictly below the diagonal
+                    sB[k * LDS_LD + row] = (row < nbb && k < nbb) ? (k < row ? vx[j] : (k == row ? 1.0 : 0.0)) : 0.0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int r = wr + bi * 16 + mfma_row(0.0, lk, rr), k = wc + bj * 16 + li;
+                        sA[k * LDS_LD + r] -= acc[bi][bj][rr];
+                    }
+            __syncthreads();
+            v4d res[2][2];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) res[bi][bj] = v4d{0, 0, 0, 0};
+            tile_mma<double>(sA, sB, res, lane, w);
+            // L21_b = V X_b^T D_b^-1
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int q = wc + bj * 16 + li;
+                        Lr[b][bi][bj][rr] = res[bi][bj][rr] / sD[64 * b + q];
+                    }
+            __syncthreads();
+            // coalesced store through LDS
+            tile_stage<double>(sA, Lr[b], lane, w);
+            __syncthreads();
+            if (R0 + row < m)
+                for (int q = kk; q < nbb; q += 4) P[(R0 + row) + (int64_t)(cb + q) * m] = sA[row + q * LDT];
+            __syncthreads();
+        }
+    }
 }
 
 // Geometry of an update after the pivot columns [t0, t0+K): target rows and
@@ -558,6 +693,7 @@ __host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int
         g.K = (c - t0) < NB ? (c - t0) : NB;
         g.lo = t0 + g.K;
         g.qhi = cend;
+        (void)win;  // win 3 (rows below the panel left out) is applied by the caller's row limit
     } else {
         g.K = cend - t0;
         g.lo = cend;
@@ -604,7 +740,8 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
     const int n = blockIdx.y, tid = threadIdx.x;
     const int m = d.m, c = d.c;
     const UpdGeom g = upd_geom(kind, t0, pe, c, m, win);
-    const int Tr = (m - g.lo + 63) / 64;
+    const int mr = (kind == 2 && win == 3) ? g.qhi : m;  // rows below mr are left to k_panel_trsm
+    const int Tr = (mr - g.lo + 63) / 64;
     int ti, tj;
     trap_decode(blockIdx.x - pre[fi], Tr, ti, tj);
     const int R0 = g.lo + 64 * ti, Q0 = g.lo + 64 * tj;
@@ -644,7 +781,7 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
     T *sC = sA;
     tile_stage<T>(sC, acc, lane, w);
     __syncthreads();
-    rmw_sub_row<T, 16>(P, Ub, m, c, R0 + row, Q0, kk, 4, g.qhi, sC + row, LDT);
+    rmw_sub_row<T, 16>(P, Ub, m, c, R0 + row, Q0, kk, 4, g.qhi, sC + row, LDT, mr);
 }
 
 // Trailing update after an outer panel (kind 3) on 128x128 tiles: four waves
@@ -1043,7 +1180,12 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
             break;
         case 1:
             hipLaunchKernelGGL(k_trsm<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre, s.nf,
-                               s.t0);
+                               s.t0, s.pe, s.win);
+            break;
+        case 7:
+            if constexpr (std::is_same<T, double>::value)
+                hipLaunchKernelGGL(k_panel_trsm, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
+                                   s.nf, s.t0, s.pe);
             break;
         case 4:
             hipLaunchKernelGGL(k_update_big<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
@@ -1067,12 +1209,17 @@ int step_tasks(int kind, int t0, int pe, int c, int m, int win) {
     if (kind == 0) return c > t0 ? 1 : 0;
     if (kind == 1) {
         const int nb = std::min(NB, c - t0);
-        const int rows = m - t0 - nb;
+        const int rows = (win == 3 ? std::min(pe, c) : m) - t0 - nb;
         return rows > 0 ? (rows + 63) / 64 : 0;
+    }
+    if (kind == 7) {
+        const int rows = m - std::min(pe, c);
+        return c > t0 && rows > 0 ? (rows + 63) / 64 : 0;
     }
     const UpdGeom g = upd_geom(kind, t0, pe, c, m, win);
     if (g.K <= 0 || g.qhi <= g.lo) return 0;
-    const int Tr = (m - g.lo + 63) / 64, Tc = (g.qhi - g.lo + 63) / 64;
+    const int mr = (kind == 2 && win == 3) ? g.qhi : m;
+    const int Tr = (mr - g.lo + 63) / 64, Tc = (g.qhi - g.lo + 63) / 64;
     return Tc * Tr - Tc * (Tc - 1) / 2;
 }
 
