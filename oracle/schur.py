@@ -1,7 +1,7 @@
 """Algorithm 1: Schur-complement decomposition of the arrowhead KKT system
 (test infrastructure only; section 4.2, Eqs. SCform, SCsolve, SCsolve1, and
 the MPOPF local Schur structure of section 4.3, Eqs. LocalSchurBs,
-LocalSchurBs3).
+LocalSchurBs3), and the structured elimination of S of section 4.3.
 
 Readings of the paper (the equations win where the algorithm listing differs):
   * Sign convention: S = C - sum_i B_i A_i^-1 B_i^T (Eq. SCform); the
@@ -129,6 +129,55 @@ def algorithm1(inst, b=None, structured: bool = True, dense_limit: int = 2500, e
     return dict(x=x, S=S, Sbar=Sbar if structured else None, r=r, ug=ug, factors=factors,
                 inertia=inertia, schur_d=ds,
                 n_perturbed=sum(f.n_perturbed for f in factors) + npert_s)
+
+
+def structured_schur_solve(S, N: int, ns: int, rhs, eps: float = 1e-20):
+    """Solve S x = rhs by block elimination over the N block columns of S
+    (section 4.3, Eq. GlobalSchur): every block below the diagonal of block
+    column j is the same N_s x N_s matrix S_o[j] (the block just below the
+    diagonal), so eliminating columns 0..j-1 subtracts one common matrix U_j
+    from every trailing block. Reading (the paper states the structure and
+    the complexity, not these steps): with U_0 = 0,
+        A_j = S_jj - U_j,  B_j = S_o[j] - U_j,  U_{j+1} = U_j + B_j A_j^-1 B_j^T,
+    A_j = L_j D_j L_j^T (the oracle's LDL^T and pivot rule), and every block of
+    the block factor below the diagonal of column j equals
+    W_j = B_j L_j^-T D_j^-1. Forward: z_j = L_j^-1 (r_j - s_j) with the running
+    sum s_{j+1} = s_j + W_j z_j; then w = z / D; backward:
+    x_j = L_j^-T (w_j - W_j^T t_j) with t_j = sum_{m>j} x_m.
+    Returns x ([nrhs, N ns]), the inertia (sum over the pivot blocks) and the
+    list of U_j."""
+    rhs = np.atleast_2d(np.asarray(rhs, dtype=np.float64))
+    blk = lambda a, i, j: a[i * ns:(i + 1) * ns, j * ns:(j + 1) * ns]
+    U = np.zeros((ns, ns))
+    Ls, ds, Ws, Us, raws = [], [], [], [], []
+    for j in range(N):
+        Us.append(U.copy())
+        A = blk(S, j, j) - U
+        L, d, _, raw = ldlt(A, signs=-np.ones(ns), eps=eps, return_raw=True)
+        Ls.append(L)
+        ds.append(d)
+        raws.append(raw)
+        if j + 1 < N:
+            B = blk(S, j + 1, j) - U
+            # W = B L^-T D^-1, i.e. W D L^T = B
+            W = np.linalg.solve(L, B.T).T / d
+            Ws.append(W)
+            U = U + (W * d) @ W.T
+    x = np.zeros_like(rhs)
+    z = np.zeros_like(rhs)
+    s = np.zeros((rhs.shape[0], ns))
+    for j in range(N):
+        z[:, j * ns:(j + 1) * ns] = np.linalg.solve(Ls[j], (rhs[:, j * ns:(j + 1) * ns] - s).T).T
+        if j + 1 < N:
+            s = s + (Ws[j] @ z[:, j * ns:(j + 1) * ns].T).T
+    t = np.zeros((rhs.shape[0], ns))
+    for j in range(N - 1, -1, -1):
+        w = z[:, j * ns:(j + 1) * ns] / ds[j]
+        v = w - (Ws[j].T @ t.T).T if j + 1 < N else w
+        x[:, j * ns:(j + 1) * ns] = np.linalg.solve(Ls[j].T, v.T).T
+        t = t + x[:, j * ns:(j + 1) * ns]
+    inertia = tuple(int(sum(inertia_from_d(r)[k] for r in raws)) for k in range(3))
+    return x, inertia, Us
 
 
 def solve_mono(inst, b=None, dense_limit: int = 4000):

@@ -522,6 +522,9 @@ __global__ void k_scatter_x(double *x, int64_t ntot, int64_t nA, const int32_t *
 
 // bh = b_C - r, r block m = C_1 y_m + sum_{n<m} C_0 y_n; the border node's
 // update vector of period n holds -(C_1 y_n, C_0 y_n).
+// (the running sums walk the periods in order; the loads of PB periods are
+// issued together)
+constexpr int PB = 16;
 __global__ void k_schur_rhs(const double *b, int64_t ntot, int64_t nA, SolveArgs sa, int64_t Ns,
                             int64_t uoff_border, double *bh) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -529,11 +532,22 @@ __global__ void k_schur_rhs(const double *b, int64_t ntot, int64_t nA, SolveArgs
     if (i >= Ns) return;
     const int64_t ng = sa.N * Ns;
     double acc = 0.0;
-    for (int64_t m = 0; m < sa.N; ++m) {
-        const double *ub = sa.uv + ((int64_t)m * sa.nrhs + k) * sa.usz + uoff_border;
-        const double bc = b[(int64_t)k * ntot + sa.N * nA + m * Ns + i];
-        bh[(int64_t)k * ng + m * Ns + i] = bc + ub[i] + acc;
-        acc += ub[Ns + i];
+    for (int64_t m0 = 0; m0 < sa.N; m0 += PB) {
+        double u0[PB], u1[PB], bc[PB];
+#pragma unroll
+        for (int t = 0; t < PB; ++t) {
+            const int64_t m = min(m0 + t, sa.N - 1);
+            const double *ub = sa.uv + ((int64_t)m * sa.nrhs + k) * sa.usz + uoff_border;
+            u0[t] = ub[i];
+            u1[t] = ub[Ns + i];
+            bc[t] = b[(int64_t)k * ntot + sa.N * nA + m * Ns + i];
+        }
+#pragma unroll
+        for (int t = 0; t < PB; ++t)
+            if (m0 + t < sa.N) {
+                bh[(int64_t)k * ng + (m0 + t) * Ns + i] = bc[t] + u0[t] + acc;
+                acc += u1[t];
+            }
     }
 }
 
@@ -544,11 +558,18 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
     if (i >= Ns) return;
     const int64_t ng = sa.N * Ns;
     double acc = 0.0;
-    for (int64_t n = sa.N - 1; n >= 0; --n) {
-        double *x = sa.xp + ((int64_t)n * sa.nrhs + k) * sa.nv;
-        x[nA + i] = xg[(int64_t)k * ng + n * Ns + i];
-        x[nA + Ns + i] = acc;
-        acc += xg[(int64_t)k * ng + n * Ns + i];
+    for (int64_t n1 = sa.N - 1; n1 >= 0; n1 -= PB) {
+        double g[PB];
+#pragma unroll
+        for (int t = 0; t < PB; ++t) g[t] = xg[(int64_t)k * ng + max(n1 - t, (int64_t)0) * Ns + i];
+#pragma unroll
+        for (int t = 0; t < PB; ++t)
+            if (n1 - t >= 0) {
+                double *x = sa.xp + ((n1 - t) * sa.nrhs + k) * sa.nv;
+                x[nA + i] = g[t];
+                x[nA + Ns + i] = acc;
+                acc += g[t];
+            }
     }
 }
 

@@ -112,6 +112,53 @@ def test_structured_schur_equals_plain(case):
     pin_plain_equals_structured(inst)
 
 
+def pin_structured_elimination(inst):
+    """Section 4.3's block elimination of S (reading R21) solves S x = r like
+    LAPACK on the assembled S, finds its inertia (all negative: S is negative
+    definite here), and carries U_j = sum of the eliminated B A^-1 B^T: U_1
+    is B_0 A_0^-1 B_0^T computed directly."""
+    out = sc.algorithm1(inst)
+    S, N, ns = out["S"], inst.N, inst.ns
+    rhs = np.random.default_rng(7).standard_normal((3, inst.n_g))
+    x, inertia, Us = sc.structured_schur_solve(S, N, ns, rhs)
+    xref = np.linalg.solve(S, rhs.T).T
+    # two backward-stable solves differ by at most ~ eps cond(S) each
+    tol = 100 * np.finfo(float).eps * np.linalg.cond(S)
+    assert _rel(x, xref) < tol, (_rel(x, xref), tol)
+    assert inertia == (0, inst.n_g, 0) == inertia_eig(S)
+    if N > 1:
+        A0, B0 = S[:ns, :ns], S[ns:2 * ns, :ns]
+        U1 = B0 @ np.linalg.solve(A0, B0.T)
+        assert np.max(np.abs(Us[1] - U1)) <= 1e-10 * np.max(np.abs(U1))
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c["ns"] > 0])
+def test_structured_elimination_of_schur(case):
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    pin_structured_elimination(inst)
+
+
+def test_structured_elimination_of_schur_ring30():
+    pin_structured_elimination(kktgen.make_workload(1))
+
+
+def test_structured_elimination_needs_the_common_update():
+    """Dropping U_j (eliminating each diagonal block alone) is a plausible
+    mistake; it gives another solution."""
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **CASES[1])
+    S = sc.algorithm1(inst)["S"]
+    rhs = np.ones((1, inst.n_g))
+    ns = inst.ns
+    Sdrop = S.copy()
+    for j in range(inst.N):
+        for i in range(j + 2, inst.N):
+            # a matrix without the repeated blocks below the first sub-diagonal
+            Sdrop[i * ns:(i + 1) * ns, j * ns:(j + 1) * ns] = 0.0
+            Sdrop[j * ns:(j + 1) * ns, i * ns:(i + 1) * ns] = 0.0
+    x, _, _ = sc.structured_schur_solve(S, inst.N, ns, rhs)
+    assert _rel(x, np.linalg.solve(Sdrop, rhs.T).T) > 1e-6
+
+
 def pin_inertia_additivity(inst):
     out = sc.algorithm1(inst)
     K = ah.assemble(inst).toarray()
