@@ -132,8 +132,8 @@ typedef struct kkt_solve_info {
                          /* eps || |K||x| + |b| ||_2 / ||b||_2: the rounding    */
                          /* level of rel_res itself. FGMRES refinement does not */
                          /* restart after a converged cycle once every          */
-                         /* right-hand side is within 4x of its own floor       */
-                         /* (KKT_WARN_REFINE when rel_res is above the target)  */
+                         /* right-hand side's relative residual is at or below  */
+                         /* its own floor (KKT_WARN_REFINE if above the target) */
 } kkt_solve_info;
 
 typedef struct kkt_symbolic_stats {

@@ -1106,9 +1106,8 @@ struct RefineState {
 
 // A residual evaluated in FP64 carries a rounding error of order
 // eps || |K||x| + |b| ||. A restart of the Krylov refinement whose previous
-// cycle converged is skipped once the true residual is within FLOOR_C times
-// that level.
-constexpr double FLOOR_C = 4.0;
+// cycle converged is skipped once the true residual is at that level.
+constexpr double FLOOR_C = 1.0;
 
 // true residual r = b - K x with its norms; returns false on a HIP error
 int true_residual(kkt_ctx *ctx, const ResidualArgs &ra, const double *b, const double *x, double *r, int64_t nrhs,
