@@ -160,10 +160,11 @@ __global__ void k_struct_uacc(const double *Ub, int64_t Ns, double *Uacc) {
 // workgroup walks them); everything else is per block column and parallel.
 constexpr int SC_T = 1024;  // threads of the recurrence kernels
 constexpr int SC_R = 4;     // right-hand sides per pass
+constexpr int SC_B = 40;    // loads in flight per thread in a chain product
 
 // y[i] (+)= sum_q M[i + q ld] x[q] for i < Ns, all threads of the workgroup:
 // thread (i, g) sums over its share of q, partial sums reduced through red
-__device__ inline void sc_matvec(const double *M, int64_t ld, int Ns, const double *x, double *red, double *acc_out,
+__device__ __forceinline__ void sc_matvec(const double *M, int64_t ld, int Ns, const double *x, double *red, double *acc_out,
                                  int nr, int tid) {
     const int G = max(1, min(16, SC_T / max(Ns, 1)));
     const int i = tid % Ns, g = tid / Ns;
@@ -171,12 +172,14 @@ __device__ inline void sc_matvec(const double *M, int64_t ld, int Ns, const doub
     double acc[SC_R] = {0.0, 0.0, 0.0, 0.0};
     if (on) {
         const int q0 = (int)((int64_t)Ns * g / G), q1 = (int)((int64_t)Ns * (g + 1) / G);
-        for (int qb = q0; qb < q1; qb += 16) {
-            double mv[16];
+        // batches of SC_B: at N_s = 200 (5 groups of 40 columns) all of a
+        // step's loads are in flight together
+        for (int qb = q0; qb < q1; qb += SC_B) {
+            double mv[SC_B];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) mv[u] = M[i + (int64_t)min(qb + u, q1 - 1) * ld];
+            for (int u = 0; u < SC_B; ++u) mv[u] = M[i + (int64_t)min(qb + u, q1 - 1) * ld];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < SC_B; ++u) {
                 const int q = min(qb + u, q1 - 1);
                 const double a = qb + u < q1 ? mv[u] : 0.0;
 #pragma unroll
