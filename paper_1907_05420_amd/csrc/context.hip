@@ -239,7 +239,10 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
             // with lookahead (the dense Schur factor, whose pivot blocks run
             // beside the side stream's updates) the 64-column steps stay
             // inside the sub-panel's diagonal block, and the rows below it
-            // take all of the sub-panel's columns in one launch
+            // take all of the sub-panel's columns in one launch. Fronts with
+            // few rows below their panel (the period blocks, the structured
+            // Schur's 2 N_s x N_s fronts) keep the per-block steps: there the
+            // one-launch form's per-tile chain of products is the slower one.
             for (int j0 = s0; j0 < std::min(se, cmax); j0 += 64) {
                 add(0, j0, se);
                 add(1, j0, se, lookahead ? 3 : 0);

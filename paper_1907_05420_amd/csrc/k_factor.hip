@@ -553,7 +553,7 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
 }
 
 // Rows below a factored sub-panel (columns [t0, cend), cend = min(pe, c), at
-// most 4 pivot blocks of 64): L21 = A21 L11^-T D^-1 for the rows [cend, m),
+// most 4 pivot blocks of 64) of every listed front and period: L21 = A21 L11^-T D^-1 for the rows [cend, m),
 // one 64-row tile per workgroup. For column block b of the sub-panel,
 //   V_b = A21_b - sum_{c<b} L21_c D_c L_bc^T,   L21_b = V_b X_b^T D_b^-1,
 // with L_bc the factored diagonal block's sub-block and X_b the stored
@@ -562,7 +562,9 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
 // time (one launch per sub-panel instead of two per pivot block). The tile's
 // finished blocks L21_c stay in registers (accumulator layout) and pass
 // through LDS as MFMA operands.
-__device__ inline void acc_to_kmajor(double *sA, const v4d (&acc)[2][2], const double *scale, int lane, int w) {
+template <typename T>
+__device__ inline void acc_to_kmajor(T *sA, const typename Acc<T>::type (&acc)[2][2], const T *scale, int lane,
+                                     int w) {
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -570,62 +572,64 @@ __device__ inline void acc_to_kmajor(double *sA, const v4d (&acc)[2][2], const d
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                const int r = wr + bi * 16 + mfma_row(0.0, lk, rr), k = wc + bj * 16 + li;
-                sA[k * LDS_LD + r] = acc[bi][bj][rr] * (scale ? scale[k] : 1.0);
+                const int r = wr + bi * 16 + mfma_row(T(0), lk, rr), k = wc + bj * 16 + li;
+                sA[k * LDS_LD + r] = acc[bi][bj][rr] * scale[k];
             }
 }
 
-__global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl,
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
                                                     const int32_t *pre, int nf, int t0, int pe) {
-    __shared__ double sA[NB * LDS_LD];
-    __shared__ double sB[NB * LDS_LD];
-    __shared__ double sD[4 * NB];
+    typedef typename Acc<T>::type acc_t;
+    __shared__ T sA[NB * LDS_LD];
+    __shared__ T sB[NB * LDS_LD];
+    __shared__ T sD[4 * NB];
     const int fi = find_front(pre, nf, blockIdx.x);
     const FrontDesc d = sd[fl[fi]];
     const int n = blockIdx.y, tid = threadIdx.x;
     const int m = d.m, cend = min(pe, d.c), W = cend - t0;
     const int R0 = cend + (blockIdx.x - pre[fi]) * 64;
-    double *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
+    T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     const int lane = tid & 63, w = tid >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
     const int row = tid & 63, kk = tid >> 6;
-    for (int k = tid; k < 4 * NB; k += 256) sD[k] = k < W ? P[(t0 + k) + (int64_t)(t0 + k) * m] : 1.0;
+    for (int k = tid; k < 4 * NB; k += 256) sD[k] = k < W ? P[(t0 + k) + (int64_t)(t0 + k) * m] : T(1);
     const int rowc = min(R0 + row, m - 1);  // clamped row of this thread's loads
-    v4d Lr[4][2][2];
+    acc_t Lr[4][2][2];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) Lr[b][bi][bj] = v4d{0, 0, 0, 0};
+            for (int bj = 0; bj < 2; ++bj) Lr[b][bi][bj] = acc_t{0, 0, 0, 0};
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int cb = t0 + 64 * b;
         if (cb < cend) {
             const int nbb = min(64, cend - cb);
-            v4d acc[2][2];
+            acc_t acc[2][2];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0, 0, 0, 0};
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
             // acc = sum_{c<b} L21_c D_c L_bc^T (blocks c < b are full 64 wide)
 #pragma unroll
             for (int c = 0; c < b; ++c) {
-                double vb[16];
+                T vb[16];
 #pragma unroll
                 for (int j = 0; j < 16; ++j)
                     vb[j] = P[(cb + min(row, nbb - 1)) + (int64_t)(t0 + 64 * c + kk + 4 * j) * m];
-                acc_to_kmajor(sA, Lr[c], sD + 64 * c, lane, w);
+                acc_to_kmajor<T>(sA, Lr[c], sD + 64 * c, lane, w);
 #pragma unroll
-                for (int j = 0; j < 16; ++j) sB[(kk + 4 * j) * LDS_LD + row] = row < nbb ? vb[j] : 0.0;
+                for (int j = 0; j < 16; ++j) sB[(kk + 4 * j) * LDS_LD + row] = row < nbb ? vb[j] : T(0);
                 __syncthreads();
-                tile_mma<double>(sA, sB, acc, lane, w);
+                tile_mma<T>(sA, sB, acc, lane, w);
                 __syncthreads();
             }
             // V = A21_b - acc, k-major in sA; X_b^T operand in sB
             {
-                double va[16], vx[16];
+                T va[16], vx[16];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int k = min(kk + 4 * j, nbb - 1);
@@ -635,9 +639,9 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<double> fa, const
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int k = kk + 4 * j;
-                    sA[k * LDS_LD + row] = (k < nbb && R0 + row < m) ? va[j] : 0.0;
+                    sA[k * LDS_LD + row] = (k < nbb && R0 + row < m) ? va[j] : T(0);
                     // sB[k][q] = X_b(q, k): unit lower, stored strictly below the diagonal
-                    sB[k * LDS_LD + row] = (row < nbb && k < nbb) ? (k < row ? vx[j] : (k == row ? 1.0 : 0.0)) : 0.0;
+                    sB[k * LDS_LD + row] = (row < nbb && k < nbb) ? (k < row ? vx[j] : (k == row ? T(1) : T(0))) : T(0);
                 }
             }
             __syncthreads();
@@ -647,16 +651,16 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<double> fa, const
                 for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr) {
-                        const int r = wr + bi * 16 + mfma_row(0.0, lk, rr), k = wc + bj * 16 + li;
+                        const int r = wr + bi * 16 + mfma_row(T(0), lk, rr), k = wc + bj * 16 + li;
                         sA[k * LDS_LD + r] -= acc[bi][bj][rr];
                     }
             __syncthreads();
-            v4d res[2][2];
+            acc_t res[2][2];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) res[bi][bj] = v4d{0, 0, 0, 0};
-            tile_mma<double>(sA, sB, res, lane, w);
+                for (int bj = 0; bj < 2; ++bj) res[bi][bj] = acc_t{0, 0, 0, 0};
+            tile_mma<T>(sA, sB, res, lane, w);
             // L21_b = V X_b^T D_b^-1
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<double> fa, const
                     }
             __syncthreads();
             // coalesced store through LDS
-            tile_stage<double>(sA, Lr[b], lane, w);
+            tile_stage<T>(sA, Lr[b], lane, w);
             __syncthreads();
             if (R0 + row < m)
                 for (int q = kk; q < nbb; q += 4) P[(R0 + row) + (int64_t)(cb + q) * m] = sA[row + q * LDT];
@@ -1183,9 +1187,8 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
                                s.t0, s.pe, s.win);
             break;
         case 7:
-            if constexpr (std::is_same<T, double>::value)
-                hipLaunchKernelGGL(k_panel_trsm, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
-                                   s.nf, s.t0, s.pe);
+            hipLaunchKernelGGL(k_panel_trsm<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
+                               s.nf, s.t0, s.pe);
             break;
         case 4:
             hipLaunchKernelGGL(k_update_big<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
