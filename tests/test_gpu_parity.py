@@ -300,3 +300,29 @@ def test_residual_floor_reported():
     ref = max(2.220446049250313e-16 * np.linalg.norm(scale[:, k]) / np.linalg.norm(inst.b[k])
               for k in range(inst.b.shape[0]))
     assert 0.9 * ref <= info["rel_floor"] <= ref * (1 + 1e-9), (info["rel_floor"], ref)
+
+
+def test_parity_structured_wide_border():
+    """N_s = 260 > 256: the structured elimination inverts each pivot block
+    in two 256-wide halves and combines them, and the solve chains take
+    their products in several load batches. Checked by properties that hold
+    at any size (the full oracle solve takes half a minute here): residual
+    from the oracle's assembled K, exact inertia, and the dense path's
+    solution (which the small cases pin to the oracle)."""
+    import paper_1907_05420_amd as pk
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), nb=300, nextra=150, ng=10, ns=260, N=3, nrhs=2, seed=15)
+    K = ah.assemble(inst)
+    d = pk.device_inputs(inst)
+    expect = (inst.N * inst.n_primal, inst.N * (inst.n_A - inst.n_primal) + inst.n_g, 0)
+    xs = {}
+    for mode in (pk.KKT_SCHUR_DENSE, pk.KKT_SCHUR_STRUCTURED):
+        s = pk.Solver(inst, schur_mode=mode)
+        _, inn = s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
+        x, _, info = s.solve(d["b"])
+        xs[mode] = x.cpu().numpy()
+        s.close()
+        rel, _ = ah.rel_residual(inst, xs[mode], inst.b, K)
+        assert rel <= 1e-10, (mode, rel)
+        assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == expect, (mode, inn)
+        assert inn["n_perturbed"] == 0
+    assert _rel(xs[pk.KKT_SCHUR_STRUCTURED], xs[pk.KKT_SCHUR_DENSE]) <= 1e-9
