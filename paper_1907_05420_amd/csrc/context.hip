@@ -39,6 +39,7 @@ namespace {
 // side stream's work so far; SYNC_TO_INV / SYNC_INV_TO_MAIN: the same between
 // the main stream and the stream of the diagonal-block inverses.
 constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101, SYNC_TO_INV = 102, SYNC_INV_TO_MAIN = 103;
+constexpr int PANEL_ROWS = 1024;  // rows below a sub-panel from which its rows below take one launch
 struct StepHost {
     int kind, win, t0, pe, nf, ntasks;
     int side;                 // 0: main stream, 1: side stream, 2: inverse stream
@@ -236,19 +237,23 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
         // the next sub-panel's columns in one rank-inner_w product.
         for (int s0 = k; s0 < std::min(pe, cmax); s0 += inner_w) {
             const int se = std::min(s0 + inner_w, pe);
-            // with lookahead (the dense Schur factor, whose pivot blocks run
-            // beside the side stream's updates) the 64-column steps stay
-            // inside the sub-panel's diagonal block, and the rows below it
-            // take all of the sub-panel's columns in one launch. Fronts with
-            // few rows below their panel (the period blocks, the structured
-            // Schur's 2 N_s x N_s fronts) keep the per-block steps: there the
+            // where the fronts have many rows below the sub-panel (the dense
+            // Schur factor, the largest period fronts) the 64-column steps
+            // stay inside the sub-panel's diagonal block, and the rows below
+            // it take all of the sub-panel's columns in one launch. Fronts
+            // with few rows below (most period fronts, the structured Schur's
+            // 2 N_s x N_s fronts) keep the per-block steps: there the
             // one-launch form's per-tile chain of products is the slower one.
+            int below = 0;
+            for (int32_t f : fl)
+                if (fd[f].c > s0) below = std::max(below, fd[f].m - std::min(se, fd[f].c));
+            const bool one_launch = lookahead || below >= PANEL_ROWS;
             for (int j0 = s0; j0 < std::min(se, cmax); j0 += 64) {
                 add(0, j0, se);
-                add(1, j0, se, lookahead ? 3 : 0);
-                add(2, j0, se, lookahead ? 3 : 0);
+                add(1, j0, se, one_launch ? 3 : 0);
+                add(2, j0, se, one_launch ? 3 : 0);
             }
-            if (lookahead) add(7, s0, se);
+            if (one_launch) add(7, s0, se);
             if (se < std::min(pe, cmax)) add(big_from(s0, se) ? 4 : 3, s0, se, 1, 0);
         }
         const int big = big_from(k, pe);
