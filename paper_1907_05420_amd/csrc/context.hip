@@ -527,8 +527,9 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = dalloc(ctx, (void **)&ctx->d_sfront, 8 * ctx->N * 2 * ns * ns))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_sG, 8 * ctx->N * ns * ns))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_sGT, 8 * ctx->N * ns * ns))) return rc;
-        if ((rc = dalloc(ctx, (void **)&ctx->d_sU, 8 * ns * ns))) return rc;
-        if ((rc = dalloc(ctx, (void **)&ctx->d_sUb, 8 * ns * ns))) return rc;
+        // U and the fronts' update blocks, two of each (column parity)
+        if ((rc = dalloc(ctx, (void **)&ctx->d_sU, 8 * 2 * ns * ns))) return rc;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_sUb, 8 * 2 * ns * ns))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_ssa, 8 * 4 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_saa, 8 * 4 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_prefix, 8 * (ctx->N + 1) * S.Ns * S.Ns))) return rc;
@@ -673,18 +674,22 @@ int factor_schur_structured(kkt_ctx *ctx) {
     launch_struct_tau(ctx->d_U, S.Usize, uoff, N, ns, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_tauS, ctx->eps,
                       ctx->d_amaxS, st);
     mark(ctx, 2);
-    launch_zero<double>(ctx->d_sU, ns * ns, st);
+    // U_j and front j's update block (which holds -B_j A_j^-1 B_j^T) live in
+    // buffer j % 2; front j's assembly reads U_{j-1} and block j-1 from the
+    // other one (both zero for j = 0) and forms U_j on the way
+    launch_zero<double>(ctx->d_sU, 2 * ns * ns, st);
+    launch_zero<double>(ctx->d_sUb, 2 * ns * ns, st);
     FactorArgs<double> fa = schur_args(ctx);
-    fa.U = ctx->d_sUb;
     for (int64_t j = 0; j < N; ++j) {
         const int last = j + 1 == N ? 1 : 0;
+        const int64_t cur = (j & 1) * ns * ns, prev = ((j + 1) & 1) * ns * ns;
         double *Fj = ctx->d_sfront + j * 2 * ns * ns;
-        launch_struct_front(ctx->d_U, S.Usize, uoff, ns, j, last, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_sU,
-                            Fj, ctx->d_sUb, st);
+        launch_struct_front(ctx->d_U, S.Usize, uoff, ns, j, last, ctx->opt.precision, ctx->d_prefix, corner,
+                            ctx->d_sU + prev, ctx->d_sUb + prev, ctx->d_sU + cur, Fj, ctx->d_sUb + cur, st);
         fa.L = Fj;
+        fa.U = ctx->d_sUb + cur;
         fa.tau = ctx->d_tauS + j * ns;
         for (const StepHost &s : ctx->sf_steps[last]) launch_step<double>(fa, ctx->d_sfd, step_dev(s, ctx->d_sftasks), 1, st);
-        if (!last) launch_struct_uacc(ctx->d_sUb, ns, ctx->d_sU, st);
         // the front is final: its inverse and G_j on the side stream
         HIPCHK(hipEventRecord(ctx->ev_main, st));
         HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_main, 0));

@@ -117,35 +117,34 @@ __global__ void k_struct_tau(const T *U, int64_t Ustride, int64_t uoff, int64_t 
 
 template <typename T>
 __global__ void k_struct_front(const T *U, int64_t Ustride, int64_t uoff, int64_t Ns, int64_t j, int last,
-                               const double *prefix, const double *corner, const double *Uacc, double *F,
-                               double *Ub) {
+                               const double *prefix, const double *corner, const double *Uprev,
+                               const double *Ubprev, double *Uout, double *F, double *Ubz) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // row of the front
     const int64_t q = blockIdx.y;                                        // pivot column
     const int64_t mj = last ? Ns : 2 * Ns;
     const T *Sb = U + j * Ustride + uoff;
     const double *Pj = prefix + j * Ns * Ns;
+    // U_j = U_{j-1} + B A^-1 B^T of the previous column; the update block of
+    // that column's front holds -(B A^-1 B^T), lower triangle
+    auto u_at = [&](int64_t i) {
+        return Uprev[i + q * Ns] - (i >= q ? Ubprev[i + q * Ns] : Ubprev[q + i * Ns]);
+    };
     if (r < mj) {
         double v = 0.0;
         if (r < Ns) {
+            const double u = u_at(r);
+            Uout[r + q * Ns] = u;
             if (r >= q) {
-                v = sbar_at(Sb, 2 * Ns, r, q) + Pj[r + q * Ns] - Uacc[r + q * Ns];
+                v = sbar_at(Sb, 2 * Ns, r, q) + Pj[r + q * Ns] - u;
                 if (r == q && corner) v += corner[j * Ns + r];
             }
         } else {
             const int64_t i = r - Ns;
-            v = sbar_at(Sb, 2 * Ns, Ns + i, q) + Pj[i + q * Ns] - Uacc[i + q * Ns];
+            v = sbar_at(Sb, 2 * Ns, Ns + i, q) + Pj[i + q * Ns] - u_at(i);
         }
         F[r + q * mj] = v;
     }
-    if (!last && r < Ns) Ub[r + q * Ns] = 0.0;
-}
-
-// U += B A^-1 B^T = -(update matrix, lower triangle in Ub): kept full
-__global__ void k_struct_uacc(const double *Ub, int64_t Ns, double *Uacc) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Ns * Ns) return;
-    const int64_t i = idx % Ns, q = idx / Ns;
-    Uacc[idx] -= i >= q ? Ub[i + q * Ns] : Ub[q + i * Ns];
+    if (!last && r < Ns) Ubz[r + q * Ns] = 0.0;
 }
 
 // Solves with the structured factor. With Linv_j the inverse of front j's
@@ -306,20 +305,16 @@ void launch_struct_tau(const void *U, int64_t Ustride, int64_t uoff, int64_t N, 
 }
 
 void launch_struct_front(const void *U, int64_t Ustride, int64_t uoff, int64_t Ns, int64_t j, int last, int precision,
-                         const double *prefix, const double *corner, const double *Uacc, double *F, double *Ub,
-                         hipStream_t st) {
+                         const double *prefix, const double *corner, const double *Uprev, const double *Ubprev,
+                         double *Uout, double *F, double *Ubz, hipStream_t st) {
     const int64_t mj = last ? Ns : 2 * Ns;
     const dim3 g((unsigned)((mj + 255) / 256), (unsigned)Ns);
     if (precision == 1)
         hipLaunchKernelGGL(k_struct_front<float>, g, dim3(256), 0, st, (const float *)U, Ustride, uoff, Ns, j, last,
-                           prefix, corner, Uacc, F, Ub);
+                           prefix, corner, Uprev, Ubprev, Uout, F, Ubz);
     else
-        hipLaunchKernelGGL(k_struct_front<double>, g, dim3(256), 0, st, (const double *)U, Ustride, uoff, Ns, j, last,
-                           prefix, corner, Uacc, F, Ub);
-}
-
-void launch_struct_uacc(const double *Ub, int64_t Ns, double *Uacc, hipStream_t st) {
-    hipLaunchKernelGGL(k_struct_uacc, dim3((unsigned)((Ns * Ns + 255) / 256)), dim3(256), 0, st, Ub, Ns, Uacc);
+        hipLaunchKernelGGL(k_struct_front<double>, g, dim3(256), 0, st, (const double *)U, Ustride, uoff, Ns, j,
+                           last, prefix, corner, Uprev, Ubprev, Uout, F, Ubz);
 }
 
 // bh [nrhs][ng] -> xg [nrhs][ng]; sa, aa: [SC_R][N][Ns] workspace

@@ -124,9 +124,8 @@ void launch_struct_tau(const void *U, int64_t Ustride, int64_t uoff, int64_t N, 
                        const double *prefix, const double *corner, double *tau_s, double eps, double *amax_s,
                        hipStream_t st);
 void launch_struct_front(const void *U, int64_t Ustride, int64_t uoff, int64_t Ns, int64_t j, int last, int precision,
-                         const double *prefix, const double *corner, const double *Uacc, double *F, double *Ub,
-                         hipStream_t st);
-void launch_struct_uacc(const double *Ub, int64_t Ns, double *Uacc, hipStream_t st);
+                         const double *prefix, const double *corner, const double *Uprev, const double *Ubprev,
+                         double *Uout, double *F, double *Ubz, hipStream_t st);
 void launch_struct_g(const double *F, int m, int ns, double *G, double *GT, hipStream_t st);
 void launch_struct_solve(const double *F, const double *G, const double *GT, int64_t N, int64_t Ns, const double *bh,
                          double *xg, double *sa, double *aa, int64_t nrhs, hipStream_t st);
