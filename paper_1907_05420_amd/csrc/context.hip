@@ -104,6 +104,7 @@ struct kkt_ctx {
     // recurrences; two planned fronts (full, last) and their launch sequences
     bool structured = false;
     double *d_sfront = nullptr, *d_sG = nullptr, *d_sGT = nullptr, *d_sU = nullptr, *d_sUb = nullptr;
+    double *d_sM = nullptr, *d_sMT = nullptr, *d_sce = nullptr;  // column pairs of the structured solves
     double *d_ssa = nullptr, *d_saa = nullptr;
     FrontDesc *d_sfd = nullptr;
     int32_t *d_sftasks = nullptr;
@@ -532,6 +533,11 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = dalloc(ctx, (void **)&ctx->d_sUb, 8 * 2 * ns * ns))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_ssa, 8 * 4 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_saa, 8 * 4 * ctx->ng))) return rc;
+        if (struct_pairs(ctx->N)) {
+            if ((rc = dalloc(ctx, (void **)&ctx->d_sM, 8 * (ctx->N / 2) * ns * ns))) return rc;
+            if ((rc = dalloc(ctx, (void **)&ctx->d_sMT, 8 * (ctx->N / 2) * ns * ns))) return rc;
+            if ((rc = dalloc(ctx, (void **)&ctx->d_sce, 8 * 4 * (ctx->N / 2) * ns))) return rc;
+        }
         if ((rc = dalloc(ctx, (void **)&ctx->d_prefix, 8 * (ctx->N + 1) * S.Ns * S.Ns))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_tauS, 8 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_amaxS, 256))) return rc;
@@ -704,6 +710,8 @@ int factor_schur_structured(kkt_ctx *ctx) {
     }
     HIPCHK(hipEventRecord(ctx->ev_side, ctx->side));
     HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
+    // pair matrices of the solves' two-column chain steps
+    if (struct_pairs(N)) launch_struct_pair(ctx->d_sG, (int)ns, (int)N, ctx->d_sM, ctx->d_sMT, st);
     return KKT_OK;
 }
 
@@ -804,8 +812,8 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
     if (ctx->ng > 0) {
         launch_schur_rhs(b, ctx->ntot, S.nA, sa, S.Ns, S.relptr[S.border_sn], ctx->d_bh, st);
         if (ctx->structured) {
-            launch_struct_solve(ctx->d_sfront, ctx->d_sG, ctx->d_sGT, ctx->N, S.Ns, ctx->d_bh, ctx->d_xg, ctx->d_ssa,
-                                ctx->d_saa, nrhs, st);
+            launch_struct_solve(ctx->d_sfront, ctx->d_sG, ctx->d_sGT, ctx->d_sM, ctx->d_sMT, ctx->N, S.Ns, ctx->d_bh,
+                                ctx->d_xg, ctx->d_ssa, ctx->d_saa, ctx->d_sce, nrhs, st);
         } else {
             launch_dense_fwd(ctx->d_S, ctx->ng, ctx->d_bh, ctx->d_y, nrhs, st);
             launch_dense_bwd(ctx->d_S, ctx->ng, ctx->d_y, ctx->d_xg, nrhs, st);

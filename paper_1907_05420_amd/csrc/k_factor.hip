@@ -1117,6 +1117,57 @@ void launch_struct_g(const double *F, int m, int ns, double *G, double *GT, hipS
     hipLaunchKernelGGL(k_struct_g, dim3((unsigned)(nt * nt)), dim3(256), 0, st, F, m, ns, G, GT);
 }
 
+// Pairs of block columns of the structured factor (the solves take the
+// recurrences two columns per step): for pair p (columns 2p, 2p + 1)
+//   M_p = (I - G_{2p+1}) (I - G_{2p}) = I - G_{2p} - G_{2p+1} + G_{2p+1} G_{2p}
+// and its transpose; G_{N-1} = 0 (the last column has no block below).
+// 64x64 tiles, grid (tiles, pairs).
+__global__ __launch_bounds__(256) void k_struct_pair(const double *G, int ns, int N, double *M, double *MT) {
+    typedef Acc<double>::type acc_t;
+    __shared__ double sA[NB * LDS_LD];
+    __shared__ double sB[NB * LDS_LD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int row = tid & 63, kk = tid >> 6;
+    const int nt = (ns + 63) / 64;
+    const int ti = blockIdx.x / nt, tq = blockIdx.x % nt, pr = blockIdx.y;
+    const int64_t nn = (int64_t)ns * ns;
+    const double *G0 = G + (int64_t)(2 * pr) * nn;
+    const bool has1 = 2 * pr + 1 <= N - 2;
+    const double *G1 = G + (int64_t)(2 * pr + 1) * nn;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+    if (has1)
+        for (int k = 0; k < nt; ++k) {
+            __syncthreads();
+            load_tile64(sA, G1, ns, 64 * ti, 64 * k, ns, ns, true, false, row, kk);   // G_{2p+1}[I][K]
+            load_tile64(sB, G0, ns, 64 * k, 64 * tq, ns, ns, false, false, row, kk);  // G_{2p}[K][Q]
+            __syncthreads();
+            tile_mma<double>(sA, sB, acc, lane, w);
+        }
+    __syncthreads();
+    tile_stage<double>(sA, acc, lane, w);
+    __syncthreads();
+    const int i = 64 * ti + row;
+    if (i < ns)
+        for (int c = kk; c < 64; c += 4) {
+            const int q = 64 * tq + c;
+            if (q < ns) {
+                const int64_t at = i + (int64_t)q * ns;
+                const double v = (i == q ? 1.0 : 0.0) - G0[at] - (has1 ? G1[at] : 0.0) + sA[row + c * LDT];
+                M[(int64_t)pr * nn + at] = v;
+                MT[(int64_t)pr * nn + q + (int64_t)i * ns] = v;
+            }
+        }
+}
+
+void launch_struct_pair(const double *G, int ns, int N, double *M, double *MT, hipStream_t st) {
+    const int nt = (ns + 63) / 64;
+    hipLaunchKernelGGL(k_struct_pair, dim3((unsigned)(nt * nt), (unsigned)(N / 2)), dim3(256), 0, st, G, ns, N, M, MT);
+}
+
 int step_tasks_big(int t0, int pe, int c, int m, int win) {
     const UpdGeom g = upd_geom(3, t0, pe, c, m, win);
     if (g.K <= 0 || g.qhi <= g.lo) return 0;

@@ -317,10 +317,213 @@ void launch_struct_front(const void *U, int64_t Ustride, int64_t uoff, int64_t N
                            last, prefix, corner, Uprev, Ubprev, Uout, F, Ubz);
 }
 
+// ---- the recurrences two block columns per step (N even) --------------------
+// Both recurrences are affine, s_{j+1} = (I - G_j) s_j + G_j bh_j and
+// t_{j-1} = (I - G_j^T) t_j + a_j, so two steps fold into one with
+// M_p = (I - G_{2p+1})(I - G_{2p}) (formed at factorisation):
+//   s_{2p+2} = M_p s_{2p} + c_p,       c_p = y + G_{2p+1}(bh_{2p+1} - y), y = G_{2p} bh_{2p}
+//   t_{2p-1} = M_p^T t_{2p+1} + e_p,   e_p = a_{2p+1} - G_{2p}^T a_{2p+1} + a_{2p}
+// The off-chain terms c_p, e_p and the values at the columns in between,
+//   s_{2p+1} = s_{2p} + G_{2p}(bh_{2p} - s_{2p}),
+//   x_{2p+1} = a_{2p+1} - G_{2p+1}^T t_{2p+1},  t_{2p} = t_{2p+1} + x_{2p+1},
+//   x_{2p} = a_{2p} - G_{2p}^T t_{2p},
+// are per pair and parallel; only N/2 dependent products remain per chain.
+
+// The per-pair kernels run SC_T threads and take their products with
+// sc_matvec (red: its reduction buffer after x, y, z in LDS).
+// workgroup p: c_p (into c_all [SC_R][N/2][Ns])
+__global__ __launch_bounds__(SC_T) void k_pair_fwd_c(const double *G, int64_t N, int Ns, const double *bh, int64_t ng,
+                                                    double *c_all, int nrhs) {
+    extern __shared__ double sm[];
+    double *x = sm, *y = sm + (int64_t)Ns * SC_R, *z = y + (int64_t)Ns * SC_R, *red = z + (int64_t)Ns * SC_R;
+    const int64_t p = blockIdx.x, P = N / 2, nn = (int64_t)Ns * Ns;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) {
+        const int i = idx / SC_R, r = idx % SC_R;
+        x[idx] = r < nrhs ? bh[(int64_t)r * ng + 2 * p * Ns + i] : 0.0;
+    }
+    __syncthreads();
+    sc_matvec(G + 2 * p * nn, Ns, Ns, x, red, y, nrhs, tid);
+    __syncthreads();
+    const bool has1 = 2 * p + 1 <= N - 2;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) {
+        const int i = idx / SC_R, r = idx % SC_R;
+        z[idx] = r < nrhs ? bh[(int64_t)r * ng + (2 * p + 1) * Ns + i] - y[idx] : 0.0;
+    }
+    __syncthreads();
+    if (has1) sc_matvec(G + (2 * p + 1) * nn, Ns, Ns, z, red, x, nrhs, tid);
+    __syncthreads();
+    for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+        const int i = idx / nrhs, r = idx % nrhs;
+        c_all[((int64_t)r * P + p) * Ns + i] = y[i * SC_R + r] + (has1 ? x[i * SC_R + r] : 0.0);
+    }
+}
+
+// one workgroup: s_{2p} for every pair into s_all [SC_R][N][Ns]
+__global__ __launch_bounds__(SC_T) void k_pair_fwd_chain(const double *M, int64_t N, int Ns, const double *c_all,
+                                                         double *s_all, int nrhs) {
+    extern __shared__ double sm[];
+    double *s = sm, *pv = sm + (int64_t)Ns * SC_R, *red = pv + (int64_t)Ns * SC_R;
+    const int tid = threadIdx.x;
+    const int64_t P = N / 2, nn = (int64_t)Ns * Ns;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) s[idx] = 0.0;
+    __syncthreads();
+    for (int64_t p = 0; p < P; ++p) {
+        for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+            const int i = idx / nrhs, r = idx % nrhs;
+            s_all[((int64_t)r * N + 2 * p) * Ns + i] = s[i * SC_R + r];
+        }
+        __syncthreads();
+        if (p + 1 == P) break;
+        sc_matvec(M + p * nn, Ns, Ns, s, red, pv, nrhs, tid);
+        for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+            const int i = idx / nrhs, r = idx % nrhs;
+            s[i * SC_R + r] = pv[i * SC_R + r] + c_all[((int64_t)r * P + p) * Ns + i];
+        }
+        __syncthreads();
+    }
+}
+
+// workgroup p: s_{2p+1} = s_{2p} + G_{2p}(bh_{2p} - s_{2p})
+__global__ __launch_bounds__(SC_T) void k_pair_fwd_fill(const double *G, int64_t N, int Ns, const double *bh, int64_t ng,
+                                                       double *s_all, int nrhs) {
+    extern __shared__ double sm[];
+    double *x = sm, *y = sm + (int64_t)Ns * SC_R, *red = y + 2 * (int64_t)Ns * SC_R;
+    const int64_t p = blockIdx.x, nn = (int64_t)Ns * Ns;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) {
+        const int i = idx / SC_R, r = idx % SC_R;
+        x[idx] = r < nrhs ? bh[(int64_t)r * ng + 2 * p * Ns + i] - s_all[((int64_t)r * N + 2 * p) * Ns + i] : 0.0;
+    }
+    __syncthreads();
+    sc_matvec(G + 2 * p * nn, Ns, Ns, x, red, y, nrhs, tid);
+    __syncthreads();
+    for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+        const int i = idx / nrhs, r = idx % nrhs;
+        s_all[((int64_t)r * N + 2 * p + 1) * Ns + i] = s_all[((int64_t)r * N + 2 * p) * Ns + i] + y[i * SC_R + r];
+    }
+}
+
+// workgroup p - 1 (p >= 1): e_p = a_{2p+1} - G_{2p}^T a_{2p+1} + a_{2p}
+__global__ __launch_bounds__(SC_T) void k_pair_bwd_e(const double *GT, int64_t N, int Ns, const double *a_all,
+                                                    double *e_all, int nrhs) {
+    extern __shared__ double sm[];
+    double *x = sm, *y = sm + (int64_t)Ns * SC_R, *red = y + 2 * (int64_t)Ns * SC_R;
+    const int64_t p = blockIdx.x + 1, P = N / 2, nn = (int64_t)Ns * Ns;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) {
+        const int i = idx / SC_R, r = idx % SC_R;
+        x[idx] = r < nrhs ? a_all[((int64_t)r * N + 2 * p + 1) * Ns + i] : 0.0;
+    }
+    __syncthreads();
+    sc_matvec(GT + 2 * p * nn, Ns, Ns, x, red, y, nrhs, tid);
+    __syncthreads();
+    for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+        const int i = idx / nrhs, r = idx % nrhs;
+        e_all[((int64_t)r * P + p) * Ns + i] =
+            x[i * SC_R + r] - y[i * SC_R + r] + a_all[((int64_t)r * N + 2 * p) * Ns + i];
+    }
+}
+
+// one workgroup: t_{N-1} = 0 and t_{2p-1} for p = N/2 - 1 .. 1 into t_all
+__global__ __launch_bounds__(SC_T) void k_pair_bwd_chain(const double *MT, int64_t N, int Ns, const double *e_all,
+                                                         double *t_all, int nrhs) {
+    extern __shared__ double sm[];
+    double *t = sm, *pv = sm + (int64_t)Ns * SC_R, *red = pv + (int64_t)Ns * SC_R;
+    const int tid = threadIdx.x;
+    const int64_t P = N / 2, nn = (int64_t)Ns * Ns;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) t[idx] = 0.0;
+    for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+        const int i = idx / nrhs, r = idx % nrhs;
+        t_all[((int64_t)r * N + N - 1) * Ns + i] = 0.0;
+    }
+    __syncthreads();
+    for (int64_t p = P - 1; p >= 1; --p) {
+        sc_matvec(MT + p * nn, Ns, Ns, t, red, pv, nrhs, tid);
+        for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+            const int i = idx / nrhs, r = idx % nrhs;
+            const double v = pv[i * SC_R + r] + e_all[((int64_t)r * P + p) * Ns + i];
+            t[i * SC_R + r] = v;
+            t_all[((int64_t)r * N + 2 * p - 1) * Ns + i] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// workgroup p: x_{2p+1}, t_{2p}, x_{2p} into xg
+__global__ __launch_bounds__(SC_T) void k_pair_bwd_fill(const double *GT, int64_t N, int Ns, const double *a_all,
+                                                       const double *t_all, double *xg, int64_t ng, int nrhs) {
+    extern __shared__ double sm[];
+    double *x = sm, *y = sm + (int64_t)Ns * SC_R, *red = y + 2 * (int64_t)Ns * SC_R;
+    const int64_t p = blockIdx.x, nn = (int64_t)Ns * Ns;
+    const int tid = threadIdx.x;
+    const bool has1 = 2 * p + 1 <= N - 2;
+    for (int idx = tid; idx < Ns * SC_R; idx += SC_T) {
+        const int i = idx / SC_R, r = idx % SC_R;
+        x[idx] = r < nrhs ? t_all[((int64_t)r * N + 2 * p + 1) * Ns + i] : 0.0;
+    }
+    __syncthreads();
+    if (has1) sc_matvec(GT + (2 * p + 1) * nn, Ns, Ns, x, red, y, nrhs, tid);
+    __syncthreads();
+    // x_{2p+1} = a_{2p+1} - G_{2p+1}^T t_{2p+1}; t_{2p} = t_{2p+1} + x_{2p+1} (into x)
+    for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+        const int i = idx / nrhs, r = idx % nrhs;
+        const double x1 = a_all[((int64_t)r * N + 2 * p + 1) * Ns + i] - (has1 ? y[i * SC_R + r] : 0.0);
+        xg[(int64_t)r * ng + (2 * p + 1) * Ns + i] = x1;
+        x[i * SC_R + r] += x1;
+    }
+    __syncthreads();
+    sc_matvec(GT + 2 * p * nn, Ns, Ns, x, red, y, nrhs, tid);
+    __syncthreads();
+    for (int idx = tid; idx < Ns * nrhs; idx += SC_T) {
+        const int i = idx / nrhs, r = idx % nrhs;
+        xg[(int64_t)r * ng + 2 * p * Ns + i] = a_all[((int64_t)r * N + 2 * p) * Ns + i] - y[i * SC_R + r];
+    }
+}
+
+bool struct_pairs(int64_t N) { return N >= 4 && N % 2 == 0; }
+
 // bh [nrhs][ng] -> xg [nrhs][ng]; sa, aa: [SC_R][N][Ns] workspace
-void launch_struct_solve(const double *F, const double *G, const double *GT, int64_t N, int64_t Ns, const double *bh,
-                         double *xg, double *sa, double *aa, int64_t nrhs, hipStream_t st) {
+void launch_struct_solve(const double *F, const double *G, const double *GT, const double *M, const double *MT,
+                         int64_t N, int64_t Ns, const double *bh, double *xg, double *sa, double *aa, double *ce,
+                         int64_t nrhs, hipStream_t st) {
     const int64_t ng = N * Ns;
+    if (struct_pairs(N)) {
+        const int Gm = std::max(1, std::min(16, SC_T / (int)std::max<int64_t>(Ns, 1)));
+        const size_t lds_c = sizeof(double) * ((size_t)2 * Ns * SC_R + (size_t)Gm * Ns * SC_R);
+        const size_t lds_w = sizeof(double) * ((size_t)3 * Ns * SC_R + (size_t)Gm * Ns * SC_R);
+        const size_t lds_k = sizeof(double) * ((size_t)2 * Ns * SC_R);
+        if (lds_c > 64 * 1024) {
+            (void)hipFuncSetAttribute((const void *)k_pair_fwd_chain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds_c);
+            (void)hipFuncSetAttribute((const void *)k_pair_bwd_chain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds_c);
+        }
+        if (lds_k > 64 * 1024)
+            (void)hipFuncSetAttribute((const void *)k_struct_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds_k);
+        if (lds_w > 64 * 1024)
+            for (const void *kf : {(const void *)k_pair_fwd_c, (const void *)k_pair_fwd_fill,
+                                   (const void *)k_pair_bwd_e, (const void *)k_pair_bwd_fill})
+                (void)hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_w);
+        const unsigned P = (unsigned)(N / 2);
+        for (int64_t k0 = 0; k0 < nrhs; k0 += SC_R) {
+            const int nr = (int)std::min<int64_t>(SC_R, nrhs - k0);
+            hipLaunchKernelGGL(k_pair_fwd_c, dim3(P), dim3(SC_T), lds_w, st, G, N, (int)Ns, bh + k0 * ng, ng, ce, nr);
+            hipLaunchKernelGGL(k_pair_fwd_chain, dim3(1), dim3(SC_T), lds_c, st, M, N, (int)Ns, (const double *)ce, sa,
+                               nr);
+            hipLaunchKernelGGL(k_pair_fwd_fill, dim3(P), dim3(SC_T), lds_w, st, G, N, (int)Ns, bh + k0 * ng, ng, sa, nr);
+            hipLaunchKernelGGL(k_struct_blocks, dim3((unsigned)N), dim3(256), lds_k, st, F, N, (int)Ns, bh + k0 * ng,
+                               ng, (const double *)sa, aa, nr);
+            hipLaunchKernelGGL(k_pair_bwd_e, dim3(P - 1), dim3(SC_T), lds_w, st, GT, N, (int)Ns, (const double *)aa, ce,
+                               nr);
+            hipLaunchKernelGGL(k_pair_bwd_chain, dim3(1), dim3(SC_T), lds_c, st, MT, N, (int)Ns, (const double *)ce, sa,
+                               nr);
+            hipLaunchKernelGGL(k_pair_bwd_fill, dim3(P), dim3(SC_T), lds_w, st, GT, N, (int)Ns, (const double *)aa,
+                               (const double *)sa, xg + k0 * ng, ng, nr);
+        }
+        return;
+    }
     const int Gm = std::max(1, std::min(16, SC_T / (int)std::max<int64_t>(Ns, 1)));
     const size_t lds_f = sizeof(double) * ((size_t)3 * Ns * SC_R + (size_t)Gm * Ns * SC_R);
     const size_t lds_b = sizeof(double) * ((size_t)2 * Ns * SC_R + (size_t)Gm * Ns * SC_R);

@@ -127,8 +127,14 @@ void launch_struct_front(const void *U, int64_t Ustride, int64_t uoff, int64_t N
                          const double *prefix, const double *corner, const double *Uprev, const double *Ubprev,
                          double *Uout, double *F, double *Ubz, hipStream_t st);
 void launch_struct_g(const double *F, int m, int ns, double *G, double *GT, hipStream_t st);
-void launch_struct_solve(const double *F, const double *G, const double *GT, int64_t N, int64_t Ns, const double *bh,
-                         double *xg, double *sa, double *aa, int64_t nrhs, hipStream_t st);
+// M_p = (I - G_{2p+1})(I - G_{2p}) and its transpose for the N/2 column pairs
+void launch_struct_pair(const double *G, int ns, int N, double *M, double *MT, hipStream_t st);
+// structured solves; with N even (N >= 4) two block columns per chain step
+// (M, MT from launch_struct_pair; ce: [4][N/2][Ns] workspace)
+bool struct_pairs(int64_t N);
+void launch_struct_solve(const double *F, const double *G, const double *GT, const double *M, const double *MT,
+                         int64_t N, int64_t Ns, const double *bh, double *xg, double *sa, double *aa, double *ce,
+                         int64_t nrhs, hipStream_t st);
 // inverse of the 2*INV_W diagonal block at j0 from its two INV_W inverses
 // (tmp: INV_W x INV_W doubles)
 void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, int c, double *tmp,
