@@ -67,7 +67,8 @@ def cpu_baseline(sample_periods=14):
 
 
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "k_update_big_mesh2000_N96_counters.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1907_05420_amd", "csrc", "k_factor.hip")
+# the dominant kernel's source: the kernel file and its tile-order header
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1907_05420_amd", "csrc", f) for f in ("k_factor.hip", "tile_order.hpp")]
 
 
 def git_blob_sha1(path):
@@ -80,7 +81,7 @@ def git_blob_sha1(path):
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when the kernel source changed after the counters were
-    taken (the summary records the source's blob hash)."""
+    taken (the summary records the blob hashes of its source files)."""
     if not os.path.exists(PROFILE_COUNTERS):
         return None
     vals = {}
@@ -88,7 +89,7 @@ def measured_traffic():
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha1") != git_blob_sha1(KERNEL_SOURCE):
+    if vals.get("source_sha1") != " ".join(git_blob_sha1(p) for p in KERNEL_SOURCES):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
