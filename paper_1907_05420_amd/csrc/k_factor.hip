@@ -405,8 +405,13 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
                     Ls[bf][kj][i] = l;
                     if (i == 0) Ds[bf][kj] = dj;
                     const T ld = l * dj;
+                    // the block's later multipliers, read back as LDS
+                    // broadcasts: LDS operations of one wave complete in
+                    // order, and the wavefront-scope fence keeps the compiler
+                    // from moving these reads above the store of other lanes
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-                    for (int k = kj + 1; k < 16; ++k) R[k] -= ld * lane_value(l, 16 * jb + k);
+                    for (int k = kj + 1; k < 16; ++k) R[k] -= ld * Ls[bf][kj][16 * jb + k];
                 }
             }
         }
