@@ -653,9 +653,17 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
     const int i = blockIdx.x * 16 + rl;
     const int q0 = min(BK_C * g, nbw - 1);
     const double *rowp = S + j0 + min(i, nbw - 1) + (j0 + q0) * ng;
+    // only the groups with a column on the used side of the diagonal read
+    // the factor (the strict lower or upper triangle: half of the block)
+    const bool used = upper ? BK_C * g + BK_C - 1 > i : BK_C * g < i;
     double l[BK_C];
+    if (used) {
 #pragma unroll
-    for (int u = 0; u < BK_C; ++u) l[u] = rowp[(int64_t)min(u, nbw - 1 - q0) * ng];
+        for (int u = 0; u < BK_C; ++u) l[u] = rowp[(int64_t)min(u, nbw - 1 - q0) * ng];
+    } else {
+#pragma unroll
+        for (int u = 0; u < BK_C; ++u) l[u] = 0.0;
+    }
     for (int k0r = 0; k0r < nrhs; k0r += RB) {
         const int nr = min(RB, nrhs - k0r);
         for (int idx = tid; idx < DBW * RB; idx += 256) {
