@@ -338,7 +338,7 @@ def main():
         print(json.dumps(cpu_baseline()))
         return 0
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         return 2
     if args.copy_probe:
         copy_probe()
