@@ -29,7 +29,7 @@ as the block duals) unless asked to be zero.
 Values: off-diagonal Hessian and Jacobian entries ~ N(0,1). The (theta,V)
 Hessian diagonal is the row's absolute off-diagonal sum plus a barrier term
 drawn log-uniformly, so Ht is positive definite and every A_n has the inertia
-the IPM requires (section 2.4): (n_primal, n_dual, 0).
+the IPM requires (section 2.3): (n_primal, n_dual, 0).
 """
 from __future__ import annotations
 

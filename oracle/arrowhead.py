@@ -95,6 +95,38 @@ def rel_residual(inst, x, b, K=None):
     return float(np.max(np.linalg.norm(r, axis=-1) / np.linalg.norm(b, axis=-1))), K
 
 
+def residual_ld(inst, x, b, K=None):
+    """r = b - K x with the products and sums in extended precision
+    (numpy.longdouble, a 64-bit significand on x86), rounded to FP64 at the
+    end, and the relative residual ||r||_2 / ||b||_2 of every right-hand side
+    from the extended-precision r. This resolves the residual of an FP64 x
+    below the rounding error that a plain FP64 evaluation carries
+    (eps || |K||x| + |b| ||). Returns (r [nrhs, n], rel [nrhs])."""
+    K = (assemble(inst) if K is None else K).tocsr()
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    b = np.atleast_2d(np.asarray(b, dtype=np.float64))
+    data = K.data.astype(np.longdouble)
+    nonempty = np.diff(K.indptr) > 0
+    starts = K.indptr[:-1][nonempty]
+    r64 = np.empty_like(b)
+    rel = np.empty(b.shape[0])
+    for k in range(x.shape[0]):
+        prod = data * x[k, K.indices].astype(np.longdouble)
+        Kx = np.zeros(K.shape[0], dtype=np.longdouble)
+        Kx[nonempty] = np.add.reduceat(prod, starts)     # row sums, in row order
+        r = b[k].astype(np.longdouble) - Kx
+        r64[k] = r.astype(np.float64)
+        bl = b[k].astype(np.longdouble)
+        rel[k] = float(np.sqrt(np.sum(r * r)) / np.sqrt(np.sum(bl * bl)))
+    return r64, rel
+
+
+def rel_residual_ld(inst, x, b, K=None):
+    """max over right-hand sides of ||b - K x||_2 / ||b||_2 evaluated in
+    extended precision (see residual_ld)."""
+    return float(np.max(residual_ld(inst, x, b, K)[1]))
+
+
 def backward_error(inst, x, b, K=None):
     """Componentwise backward error omega = max_i |r_i| / (|K||x| + |b|)_i."""
     K = assemble(inst) if K is None else K

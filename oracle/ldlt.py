@@ -6,7 +6,7 @@ quasi-definite (positive definite Hessian part, negative definite dual part),
 so an LDL^T with 1x1 pivots exists in any symmetric order.
 
 The paper leaves the pivot perturbation to the sparse solver (section 2.1 lists
-scaling, matching and pivoting; section 2.4 the inertia). The reading used
+scaling, matching and pivoting; section 2.3 the inertia). The reading used
 here and in the library (static pivoting): pivot k is perturbed when
 |d_k| <= tau_k with tau_k = eps * |a_kk| (the original diagonal entry of the
 matrix being factored), or tau_k = eps * max|A| when a_kk = 0. The pivot keeps
@@ -15,7 +15,7 @@ d_k = 0) and takes the magnitude tau_k. The threshold is invariant under
 symmetric diagonal scaling. Inertia is counted from the computed pivots
 before perturbation, so a wrong-sign pivot is reported, not hidden.
 
-Inertia (section 2.4): the triple (n+, n-, n0) of eigenvalue signs; for
+Inertia (section 2.3): the triple (n+, n-, n0) of eigenvalue signs; for
 A = L D L^T it equals the sign count of D (Sylvester's law of inertia).
 """
 from __future__ import annotations

@@ -24,9 +24,13 @@ from .ldlt import ldlt, ldlt_solve, inertia_from_d
 class BlockFactor:
     """Factor of one diagonal block A_n: the oracle's own dense LDL^T for
     small blocks (with inertia), else SuperLU as a library solve primitive
-    (the solution A_n^-1 y is unique, inertia is then not reported)."""
+    (the solution A_n^-1 y is unique, inertia is then not reported): with
+    diagonal pivots by default, or with threshold partial pivoting
+    (pivot_thresh > 0, a stabler preconditioner for refinement on badly
+    scaled blocks)."""
 
-    def __init__(self, A: sp.spmatrix, n_primal: int, dense_limit: int = 2500, eps: float = 1e-20):
+    def __init__(self, A: sp.spmatrix, n_primal: int, dense_limit: int = 2500, eps: float = 1e-20,
+                 pivot_thresh: float = 0.0):
         n = A.shape[0]
         self.n = n
         if n <= dense_limit:
@@ -34,6 +38,11 @@ class BlockFactor:
             self.L, self.d, self.n_perturbed, raw = ldlt(A.toarray(), signs=signs, eps=eps, return_raw=True)
             self.inertia = inertia_from_d(raw)
             self.kind = "dense"
+        elif pivot_thresh > 0.0:
+            self.lu = spla.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=pivot_thresh)
+            self.inertia = None
+            self.n_perturbed = 0
+            self.kind = "splu"
         else:
             self.lu = spla.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A",
                                 diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
@@ -74,29 +83,70 @@ def place_local_schur(inst, n: int, Sbar: np.ndarray) -> np.ndarray:
     return Sn
 
 
+def assemble_schur_prefix(inst, Sbar) -> np.ndarray:
+    """S = C + sum_n S_n with each S_n placed as Eq. LocalSchurBs places it,
+    summed block by block instead of matrix by matrix: block (m, m) collects
+    S_11 of period m and S_00 of every earlier period; block (m, m') below
+    the diagonal (m > m') collects S_10 of period m' and S_00 of every period
+    before m' (Eq. GlobalSchur: the same matrix for every m > m'). Both
+    triangles are filled. O(n_g^2) memory without forming any S_n."""
+    ns, N = inst.ns, inst.N
+    S = np.zeros((inst.n_g, inst.n_g))
+    blk = lambda m: slice(m * ns, (m + 1) * ns)
+    P = np.zeros((ns, ns))                    # sum of S_00,n over n < m'
+    for mp in range(N):
+        S11, S10, S00 = Sbar[mp][:ns, :ns], Sbar[mp][ns:, :ns], Sbar[mp][ns:, ns:]
+        S[blk(mp), blk(mp)] = P + S11
+        below = P + S10
+        for m in range(mp + 1, N):
+            S[blk(m), blk(mp)] = below
+            S[blk(mp), blk(m)] = below.T
+        P = P + S00
+    S[np.diag_indices(inst.n_g)] += inst.corner_diag
+    return S
+
+
 def algorithm1(inst, b=None, structured: bool = True, dense_limit: int = 2500, eps: float = 1e-20,
-               factors=None):
+               factors=None, assembly: str = "place", schur_factor: str = "ldlt", pivot_thresh: float = 0.0,
+               schur=None):
     """Solve K x = b by Algorithm 1 on one process. Returns a dict with x
     ([nrhs, n_total]), S (dense n_g x n_g), Sbar ([N, 2Ns, 2Ns], structured
     only), r ([nrhs, n_g]), ug, the block factors, inertia (when every block
-    was factored densely) and the perturbed-pivot count."""
+    was factored densely) and the perturbed-pivot count.
+
+    assembly "place" adds every S_n as an n_g x n_g matrix; "prefix" sums the
+    same blocks per block position (assemble_schur_prefix), for large n_g.
+    schur_factor "ldlt" is the oracle's own LDL^T of S; "cholesky" is LAPACK's
+    Cholesky of -S (a library primitive; S is negative definite whenever
+    every A_n and K have the inertia the IPM expects, and the call fails
+    otherwise), for large n_g. A later call can pass the returned factors
+    and `schur` (the returned dict's "schur_fac") to solve other
+    right-hand sides without refactoring."""
     b = inst.b if b is None else np.atleast_2d(b)
     N, nA, ng = inst.N, inst.n_A, inst.n_g
     bparts, bC = ah.split(inst, b)              # [nrhs, N, nA], [nrhs, n_g]
     # step 2: factor every diagonal block
     if factors is None:
-        factors = [BlockFactor(ah.block(inst, n), inst.n_primal, dense_limit, eps) for n in range(N)]
+        factors = [BlockFactor(ah.block(inst, n), inst.n_primal, dense_limit, eps, pivot_thresh)
+                   for n in range(N)]
     # steps 3-6: Schur complement S = C - sum_n B_n A_n^-1 B_n^T
-    S = np.diag(inst.corner_diag).astype(np.float64)
     Sbar = np.zeros((N, 2 * inst.ns, 2 * inst.ns))
-    if ng:
+    if schur is not None:
+        S = None
+    elif assembly == "prefix":
         for n in range(N):
-            if structured:
-                Sbar[n] = local_schur_bar(inst, factors[n])
-                S += place_local_schur(inst, n, Sbar[n])
-            else:
-                Bn = ah.border(inst, n)
-                S -= Bn @ factors[n].solve(Bn.T.toarray())
+            Sbar[n] = local_schur_bar(inst, factors[n])
+        S = assemble_schur_prefix(inst, Sbar) if ng else np.zeros((0, 0))
+    else:
+        S = np.diag(inst.corner_diag).astype(np.float64)
+        if ng:
+            for n in range(N):
+                if structured:
+                    Sbar[n] = local_schur_bar(inst, factors[n])
+                    S += place_local_schur(inst, n, Sbar[n])
+                else:
+                    Bn = ah.border(inst, n)
+                    S -= Bn @ factors[n].solve(Bn.T.toarray())
     # steps 8-11: r = sum_n B_n A_n^-1 b_n
     y = np.stack([factors[n].solve(bparts[:, n, :].T).T.reshape(b.shape[0], nA) for n in range(N)], 1)
     r = np.zeros((b.shape[0], ng))
@@ -104,8 +154,21 @@ def algorithm1(inst, b=None, structured: bool = True, dense_limit: int = 2500, e
         for n in range(N):
             r += (ah.border(inst, n) @ y[:, n, :].T).T
     # steps 12-13: S = L_s D_s L_s^T, solve S du_g = b_C - r
-    if ng:
-        Ls, ds, npert_s, raw_s = ldlt(S, signs=-np.ones(ng), eps=eps, return_raw=True)
+    import scipy.linalg as sl
+    schur_fac = schur
+    if ng and (schur_factor == "cholesky" or (schur is not None and schur[0] == "cholesky")):
+        if schur_fac is None:
+            S *= -1.0                                # in place: -S, then its Cholesky factor
+            schur_fac = ("cholesky", sl.cho_factor(S, lower=True, overwrite_a=True, check_finite=False))
+            S = None
+        ug = -sl.cho_solve(schur_fac[1], (bC - r).T, check_finite=False).T
+        ds = raw_s = -np.ones(ng)                    # Cholesky of -S succeeded: S negative definite
+        npert_s = 0
+    elif ng:
+        if schur_fac is None:
+            Ls, ds, npert_s, raw_s = ldlt(S, signs=-np.ones(ng), eps=eps, return_raw=True)
+            schur_fac = ("ldlt", (Ls, ds, npert_s, raw_s))
+        Ls, ds, npert_s, raw_s = schur_fac[1]
         ug = ldlt_solve(Ls, ds, (bC - r).T).T
     else:
         ds = raw_s = np.zeros(0)
@@ -126,8 +189,8 @@ def algorithm1(inst, b=None, structured: bool = True, dense_limit: int = 2500, e
         zer = sum(f.inertia[2] for f in factors)
         ps, ns_, zs = inertia_from_d(raw_s)
         inertia = (pos + ps, neg + ns_, zer + zs)
-    return dict(x=x, S=S, Sbar=Sbar if structured else None, r=r, ug=ug, factors=factors,
-                inertia=inertia, schur_d=ds,
+    return dict(x=x, S=S, Sbar=Sbar if (structured or assembly == "prefix") else None, r=r, ug=ug,
+                factors=factors, inertia=inertia, schur_d=ds, schur_fac=schur_fac,
                 n_perturbed=sum(f.n_perturbed for f in factors) + npert_s)
 
 
@@ -193,15 +256,21 @@ def solve_mono(inst, b=None, dense_limit: int = 4000):
     return x, K
 
 
-def refine(inst, x, b, solve_fn, tol: float = 1e-12, maxit: int = 10, K=None):
-    """FP64 iterative refinement x <- x + solve(b - K x) until the relative
-    residual is below tol, stagnates (no 2x gain over two steps) or maxit.
-    Returns (x, history of relative residuals)."""
+def refine(inst, x, b, solve_fn, tol: float = 1e-12, maxit: int = 10, K=None, extended: bool = False):
+    """Iterative refinement x <- x + solve(b - K x) (section 2.1) until the
+    relative residual is below tol, stagnates (no 2x gain over two steps) or
+    maxit. The residual is evaluated in FP64, or with `extended` in extended
+    precision (arrowhead.residual_ld), which lets x approach the correctly
+    rounded FP64 solution. Returns (x, history of relative residuals)."""
     K = ah.assemble(inst) if K is None else K
     hist = []
     for it in range(maxit + 1):
-        r = b - (K @ x.T).T
-        rel = float(np.max(np.linalg.norm(r, axis=-1) / np.linalg.norm(b, axis=-1)))
+        if extended:
+            r, rels = ah.residual_ld(inst, x, b, K)
+            rel = float(np.max(rels))
+        else:
+            r = b - (K @ x.T).T
+            rel = float(np.max(np.linalg.norm(r, axis=-1) / np.linalg.norm(b, axis=-1)))
         hist.append(rel)
         if rel <= tol or it == maxit:
             break

@@ -4,18 +4,18 @@ section 2.1) to a small text fixture.
 
 The figure's panel prints every nonzero as an "x y" pair (1-based, nz = 576).
 This script only copies those printed numbers; it computes nothing.
-Run once from the repository root:  python tests/golden/extract_e1_pattern.py
+Run once with the LaTeX source of the paper as the argument:
+    python tests/golden/extract_e1_pattern.py <paper source .tex/.md>
 """
 import os
 import re
 import sys
 
-SRC = "/root/reference/PAPER.md"
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "e1_case9_kkt_pattern.txt")
 
 
-def main():
-    lines = open(SRC, encoding="utf-8").read().splitlines()
+def main(src):
+    lines = open(src, encoding="utf-8").read().splitlines()
     label = next(i for i, l in enumerate(lines) if r"\label{fig:KKTsystemOPF}" in l)
     start = max(i for i in range(label) if lines[i].startswith(r"\begin{figure}"))
     ax0 = next(i for i in range(start, label) if r"\begin{axis}" in lines[i])
@@ -42,4 +42,6 @@ def main():
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    if len(sys.argv) != 2:
+        sys.exit("usage: extract_e1_pattern.py <paper source>")
+    sys.exit(main(sys.argv[1]))

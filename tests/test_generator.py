@@ -75,7 +75,7 @@ def test_mesh2000_sizes_and_degree_cap():
 
 
 def test_block_inertia_is_kkt_correct():
-    """Values rule: each A_n has inertia (n_primal, n_dual, 0) (section 2.4)."""
+    """Values rule: each A_n has inertia (n_primal, n_dual, 0) (section 2.3)."""
     from oracle import arrowhead as ah
     inst = kktgen.make_workload(1)
     for n in range(inst.N):

@@ -112,6 +112,25 @@ def test_structured_schur_equals_plain(case):
     pin_plain_equals_structured(inst)
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[4]])
+def test_prefix_assembly_and_cholesky_path(case):
+    """The large-size route of the oracle: S summed per block position
+    (Eq. LocalSchurBs, prefix sums of the S_00 blocks) equals the sum of the
+    placed S_n; LAPACK's Cholesky of -S gives Algorithm 1 the same solution
+    as the oracle's own LDL^T of S; and the refinement with extended-precision
+    residuals reaches below 1e-14 like the FP64 one."""
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    a = sc.algorithm1(inst)
+    b = sc.algorithm1(inst, assembly="prefix", schur_factor="cholesky")
+    c = sc.algorithm1(inst, assembly="prefix")
+    assert np.max(np.abs(c["S"] - a["S"])) <= 1e-13 * np.max(np.abs(a["S"]))
+    assert _rel(b["x"], a["x"]) < 1e-11
+    K = ah.assemble(inst)
+    solve = lambda r: sc.algorithm1(inst, b=r, factors=b["factors"], schur=b["schur_fac"])["x"]
+    x, hist = sc.refine(inst, b["x"], inst.b, solve, tol=1e-15, K=K, extended=True)
+    assert hist[-1] < 1e-14 and _rel(x, sc.solve_mono(inst)[0]) < 1e-10
+
+
 def pin_structured_elimination(inst):
     """Section 4.3's block elimination of S (reading R21) solves S x = r like
     LAPACK on the assembled S, finds its inertia (all negative: S is negative
@@ -257,6 +276,116 @@ def test_refinement_reaches_tolerance_wide_barrier():
 
 
 # --------------------------------------------------------------------------
+# assembly, residuals and backward error
+# --------------------------------------------------------------------------
+
+def _dense_from_raw(inst):
+    """K built entry by entry from the instance's raw arrays, with none of the
+    oracle's code: every stored lower entry of A_n at (i, j) and (j, i), the
+    rows of C_1 in block row m = n of B_n and those of C_0 in every block row
+    m > n (Eq. B12N), the corner diagonal."""
+    nA, N, ns = inst.n_A, inst.N, inst.ns
+    K = np.zeros((inst.n_total, inst.n_total))
+    for p in range(N):
+        o = p * nA
+        for j in range(nA):
+            for q in range(inst.colptr[j], inst.colptr[j + 1]):
+                i = int(inst.rowind[q])
+                K[o + i, o + j] = inst.vals[p, q]
+                K[o + j, o + i] = inst.vals[p, q]
+    g0 = N * nA
+    for p in range(N):
+        for m in range(p, N):
+            rp, ci, cv = ((inst.C1_rowptr, inst.C1_colind, inst.C1_vals) if m == p
+                          else (inst.C0_rowptr, inst.C0_colind, inst.C0_vals))
+            for s_ in range(ns):
+                for q in range(rp[s_], rp[s_ + 1]):
+                    r_, c_ = g0 + m * ns + s_, p * nA + int(ci[q])
+                    K[r_, c_] += cv[q]
+                    K[c_, r_] += cv[q]
+    for g in range(inst.n_g):
+        K[g0 + g, g0 + g] = inst.corner_diag[g]
+    return K
+
+
+def pin_assembly_raw(inst):
+    """arrowhead.block / border / corner / assemble equal, bit for bit, the
+    matrix written out entry by entry from the raw CSC/CSR arrays (a doubled
+    or dropped diagonal, a transposed or misplaced C block, a wrong corner
+    all change an entry)."""
+    Kraw = _dense_from_raw(inst)
+    assert np.array_equal(ah.assemble(inst).toarray(), Kraw)
+    nA = inst.n_A
+    for n in range(inst.N):
+        assert np.array_equal(ah.block(inst, n).toarray(), Kraw[n * nA:(n + 1) * nA, n * nA:(n + 1) * nA])
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[3], CASES[4]])
+def test_assembly_matches_raw_arrays(case):
+    pin_assembly_raw(kktgen.make_small(barrier_range=(1e-2, 1e2), **case))
+
+
+def pin_backward_error_hand(inst=None):
+    """omega = max_i |r_i| / (|K||x| + |b|)_i on a 2x2 system worked by hand:
+    K = [[4, -1], [-1, -2]], x = (1, 2), b = (3, -6): K x = (2, -5),
+    r = (1, -1), |K||x| + |b| = (6 + 3, 5 + 6) = (9, 11), omega = 1/9. With
+    b = K x it is 0; a zero row (x = 0, b = 0) counts as 0; several
+    right-hand sides take the largest."""
+    import scipy.sparse as sp_
+    K = sp_.csr_matrix(np.array([[4.0, -1.0], [-1.0, -2.0]]))
+    assert ah.backward_error(None, np.array([[1.0, 2.0]]), np.array([[3.0, -6.0]]), K) == pytest.approx(1 / 9, rel=1e-15)
+    assert ah.backward_error(None, np.array([[1.0, 2.0]]), np.array([[2.0, -5.0]]), K) == 0.0
+    assert ah.backward_error(None, np.zeros((1, 2)), np.zeros((1, 2)), K) == 0.0
+    # x = (1, 0), b = (4, 0): K x = (4, -1), r = (0, 1), rows (4 + 4, 1 + 0): omega = 1
+    two = ah.backward_error(None, np.array([[1.0, 2.0], [1.0, 0.0]]), np.array([[3.0, -6.0], [4.0, 0.0]]), K)
+    assert two == 1.0
+
+
+def test_backward_error_hand_computed():
+    pin_backward_error_hand()
+
+
+def pin_residual_ld_exact(inst=None):
+    """rel_residual_ld against the exact residual in rational arithmetic
+    (fractions.Fraction, row by row) of an FP64 x near the solution of a
+    wide-barrier system, where a plain FP64 evaluation is off by a large
+    fraction of the residual itself."""
+    from fractions import Fraction
+    import math
+    w = kktgen.make_workload(1, rep=1, barrier=(1e-8, 1e8), nrhs=1)
+    out = sc.algorithm1(w)
+    K = ah.assemble(w).tocsr()
+
+    def exact_residual(x):
+        r = []
+        for i in range(K.shape[0]):
+            acc = Fraction(float(w.b[0, i]))
+            for q in range(K.indptr[i], K.indptr[i + 1]):
+                acc -= Fraction(float(K.data[q])) * Fraction(float(x[0, K.indices[q]]))
+            r.append(acc)
+        return r
+
+    # refine with exact residuals down to the rounding of x itself
+    x = out["x"]
+    for _ in range(3):
+        r = np.array([[float(v) for v in exact_residual(x)]])
+        x = x + sc.algorithm1(w, b=r, factors=out["factors"])["x"]
+    r = exact_residual(x)
+    exact = math.sqrt(sum(v * v for v in r) / sum(Fraction(float(v)) ** 2 for v in w.b[0]))
+    got = ah.rel_residual_ld(w, x, w.b, K)
+    # extended precision leaves ~ 1e-19 || |K||x| || / ||b|| (~ 1e-13 here):
+    # resolved 1000 times below the 1e-10 target
+    assert abs(got - exact) <= 2e-13, (got, exact)
+    # a plain FP64 evaluation misses it by far more at this level
+    fp64, _ = ah.rel_residual(w, x, w.b, K)
+    assert abs(fp64 - exact) > 0.05 * exact, (fp64, exact)
+
+
+def test_residual_ld_matches_exact_rational():
+    pin_residual_ld_exact()
+
+
+# --------------------------------------------------------------------------
 # planted mistakes: each must be caught by at least one pin
 # --------------------------------------------------------------------------
 
@@ -315,8 +444,46 @@ def _mut_ldlt_update(monkeypatch):
     monkeypatch.setattr(sc, "ldlt", wrong)
 
 
+def _mut_block_doubled_diagonal(monkeypatch):
+    orig = ah.block_lower
+
+    def wrong(inst, n):            # A_n = L + L^T without removing the diagonal once
+        import scipy.sparse as sp_
+        L = orig(inst, n)
+        return (L + L.T).tocsr()
+    monkeypatch.setattr(ah, "block", wrong)
+
+
+def _mut_corner_sign(monkeypatch):
+    import scipy.sparse as sp_
+    monkeypatch.setattr(ah, "corner", lambda inst: sp_.diags(-inst.corner_diag).tocsr())
+
+
+def _mut_inertia_sign(monkeypatch):
+    monkeypatch.setattr(sc, "inertia_from_d", lambda d: (int(np.sum(np.asarray(d) < 0)),
+                                                         int(np.sum(np.asarray(d) > 0)),
+                                                         int(np.sum(np.asarray(d) == 0))))
+
+
+def _mut_backward_error_no_b(monkeypatch):
+    def wrong(inst, x, b, K=None):   # |b| left out of the denominator
+        r = b - (K @ x.T).T
+        den = (abs(K) @ np.abs(x).T).T
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return float(np.max(np.where(den > 0, np.abs(r) / den, 0.0)))
+    monkeypatch.setattr(ah, "backward_error", wrong)
+
+
+def _mut_residual_ld_fp64(monkeypatch):
+    def wrong(inst, x, b, K=None):   # summed in FP64 after all
+        r = np.atleast_2d(b) - (K @ np.atleast_2d(x).T).T
+        return float(np.max(np.linalg.norm(r, axis=-1) / np.linalg.norm(np.atleast_2d(b), axis=-1)))
+    monkeypatch.setattr(ah, "rel_residual_ld", wrong)
+
+
 MUTANTS = [_mut_swap_c0_c1, _mut_border_transposed_periods, _mut_schur_sign, _mut_drop_s00,
-           _mut_local_solve_sign, _mut_ldlt_update]
+           _mut_local_solve_sign, _mut_ldlt_update, _mut_block_doubled_diagonal, _mut_corner_sign,
+           _mut_inertia_sign, _mut_backward_error_no_b, _mut_residual_ld_fp64]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS, ids=lambda f: f.__name__)
@@ -325,7 +492,7 @@ def test_pins_catch_planted_mistakes(mutant, monkeypatch):
     mutant(monkeypatch)
     caught = 0
     for pin in (pin_decomposed_equals_monolithic, pin_plain_equals_structured, pin_local_schur_blocks,
-                pin_inertia_additivity):
+                pin_inertia_additivity, pin_assembly_raw, pin_backward_error_hand, pin_residual_ld_exact):
         try:
             pin(inst)
         except (AssertionError, np.linalg.LinAlgError):
