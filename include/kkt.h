@@ -14,7 +14,7 @@
  * border follows Eq. B12N: B_n is (N*Ns) x nA with block row m equal to 0 for
  * m < n, C_1 for m = n and C_0 for m > n (C_0, C_1: Ns x nA, the same for every
  * period). C is the corner (zero, or a diagonal; section 4.1 gives a zero block
- * for MPOPF, the dual regularisation -delta_c I of section 2.4 makes it
+ * for MPOPF, the dual regularisation -delta_c I of section 2.3 makes it
  * negative definite).
  *
  * The solve is the Schur-complement decomposition of Algorithm 1 (section
@@ -78,6 +78,12 @@ typedef struct kkt_options {
                         /* 128x128 tiles, smaller ones 64x64; 0 = default 512   */
                         /* (a tile-shape knob for autotuning)                   */
     int schur_mode;     /* KKT_SCHUR_DENSE (default) or KKT_SCHUR_STRUCTURED    */
+    int dual_wait;      /* elimination order: a dual becomes eligible once     */
+                        /* min(dual_wait, its primal neighbours) of its primal */
+                        /* neighbours are eliminated and it can claim one of   */
+                        /* them that no earlier dual claimed; 0 = default      */
+                        /* (FP64: 4, mixed: all of them). Larger values trade  */
+                        /* fill for smaller pivot growth                       */
 } kkt_options;
 
 /* Factorisation of the Schur complement S (Algorithm 1 step 12):
@@ -129,11 +135,10 @@ typedef struct kkt_solve_info {
     double omega;        /* componentwise backward error max_i |r_i|/(|K||x|+|b|)_i */
     int fallback_used;   /* 1 when the mixed path fell back to FP64 factors     */
     double rel_floor;    /* max over right-hand sides of                        */
-                         /* eps || |K||x| + |b| ||_2 / ||b||_2: the rounding    */
-                         /* level of rel_res itself. FGMRES refinement does not */
-                         /* restart after a converged cycle once every          */
-                         /* right-hand side's relative residual is at or below  */
-                         /* its own floor (KKT_WARN_REFINE if above the target) */
+                         /* eps || |K||x| + |b| ||_2 / ||b||_2: a bound on the  */
+                         /* relative residual that rounding x to FP64 alone can */
+                         /* cause (and the error a residual summed in plain     */
+                         /* FP64 would carry); informational                    */
 } kkt_solve_info;
 
 typedef struct kkt_symbolic_stats {
@@ -180,7 +185,7 @@ int kkt_plan(const kkt_structure *s, const kkt_options *opt, int64_t nrhs_max,
  *              order of kkt_analyze (lower triangle).
  *   C0_vals    device [nnz_C0], C1_vals device [nnz_C1] (NULL when Ns = 0).
  *   corner_diag device [N*Ns] diagonal of C, or NULL for C = 0.
- *   delta_w, delta_c: inertia-correction shifts (section 2.4) added as
+ *   delta_w, delta_c: inertia-correction shifts (section 2.3) added as
  *              +delta_w to the first n_primal diagonal entries of every A_n
  *              and -delta_c to the remaining ones, without re-uploading.
  *   out        optional (host); when non-NULL the call synchronises the
@@ -199,12 +204,16 @@ int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals,
  * with FP64 iterative refinement on the unscaled K until rel_res <=
  * refine_tol or refine_max steps (section 2.1): by default flexible GMRES
  * preconditioned with the factorisation, restarted with the true residual;
- * refinement also stops when the residual stagnates at its rounding floor or
- * the componentwise backward error reaches the FP64 rounding level.
+ * refinement also stops when a restart does not halve the residual (classic
+ * refinement: when steps stop halving it). True residuals b - K x are summed
+ * with compensated (twice-working-precision) arithmetic, so rel_res resolves
+ * the residual of the FP64 solution itself. refine_max = 0 returns the
+ * unrefined solution of the factorisation.
  *   b, x  device [nrhs][N*nA + N*Ns] FP64, column-major in u order; b != x.
  *   info  optional (host). The refinement loop reads one scalar per step
  *         from the device (a stream synchronisation per step).
- * Returns 0, KKT_WARN_REFINE, or an error. */
+ * Returns 0, KKT_WARN_REFINE, or an error; KKT_ERR_NONFINITE (x untouched)
+ * when b holds a NaN or an infinity. */
 int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
               kkt_solve_info *info);
 
@@ -229,7 +238,7 @@ int kkt_factor_status(kkt_ctx *ctx, kkt_inertia *out);
  * `steps` FP64 refinement steps x += solve(b - K x) (section 2.1), all on the
  * stream; the norms of the final residual stay on the device for
  * kkt_solve_status (synchronises; returns KKT_WARN_REFINE when rel_res is
- * above refine_tol). The solve workspace for nrhs right-hand sides must exist
+ * above refine_tol, KKT_ERR_NONFINITE when b held a NaN or an infinity). The solve workspace for nrhs right-hand sides must exist
  * before a graph capture (any earlier kkt_solve or kkt_solve_async with at
  * least nrhs right-hand sides creates it); otherwise KKT_ERR_ARG. */
 int kkt_solve_async(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps);

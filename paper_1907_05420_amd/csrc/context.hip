@@ -134,9 +134,11 @@ struct kkt_ctx {
     kkt_kernel_stat kstat{};
     // trailing matrices with at least this many rows use the 128x128 tiles
     int big_rows = 512;
-    // last kkt_solve_async
+    // last kkt_solve_async: its right-hand sides, steps and where it left
+    // the norms of the final residual
     int64_t async_nrhs = 0;
     int async_steps = 0;
+    const double *status_norms = nullptr;
 };
 
 namespace {
@@ -1121,16 +1123,10 @@ constexpr double EPS64 = 2.220446049250313e-16;
 struct RefineState {
     int it = 0, status = KKT_OK;
     double rel = 0.0, omega = 0.0;
-    double floor = 0.0;      // max_k eps || |K||x_k| + |b_k| ||_2 / ||b_k||_2
-    bool at_floor = false;   // every right-hand side within FLOOR_C times its floor
+    double floor = 0.0;  // max_k eps || |K||x_k| + |b_k| ||_2 / ||b_k||_2
 };
 
-// A residual evaluated in FP64 carries a rounding error of order
-// eps || |K||x| + |b| ||. A restart of the Krylov refinement whose previous
-// cycle converged is skipped once the true residual is at that level.
-constexpr double FLOOR_C = 1.0;
-
-// true residual r = b - K x with its norms; returns false on a HIP error
+// true residual r = b - K x (compensated sums) with its norms
 int true_residual(kkt_ctx *ctx, const ResidualArgs &ra, const double *b, const double *x, double *r, int64_t nrhs,
                   std::vector<double> &nh, RefineState &rs) {
     hipStream_t st = ctx->stream;
@@ -1140,14 +1136,11 @@ int true_residual(kkt_ctx *ctx, const ResidualArgs &ra, const double *b, const d
     rs.rel = 0.0;
     rs.omega = 0.0;
     rs.floor = 0.0;
-    rs.at_floor = true;
     for (int64_t k = 0; k < nrhs; ++k) {
         const double bn = nh[4 * k + 1] > 0 ? nh[4 * k + 1] : 1.0;
-        const double rb = nh[4 * k + 0] / bn, fl = EPS64 * nh[4 * k + 3] / bn;
-        rs.rel = std::max(rs.rel, rb);
+        rs.rel = std::max(rs.rel, nh[4 * k + 0] / bn);
         rs.omega = std::max(rs.omega, nh[4 * k + 2]);
-        rs.floor = std::max(rs.floor, fl);
-        if (!(rb <= FLOOR_C * fl)) rs.at_floor = false;
+        rs.floor = std::max(rs.floor, EPS64 * nh[4 * k + 3] / bn);
     }
     if (ctx->opt.verbose)
         std::fprintf(stderr, "kkt_solve: step %d rel_res %.3e omega %.3e floor %.3e\n", rs.it, rs.rel, rs.omega,
@@ -1155,13 +1148,13 @@ int true_residual(kkt_ctx *ctx, const ResidualArgs &ra, const double *b, const d
     return KKT_OK;
 }
 
-// common stopping tests on a true residual; true = stop
+// common stopping tests on a true residual; true = stop. The residual is
+// evaluated with compensated sums, so it resolves the residual of x itself
+// down to the rounding of x to FP64; refinement runs until the target, the
+// step limit, or stagnation (the callers' tests).
 bool refine_done(kkt_ctx *ctx, RefineState &rs) {
     if (!std::isfinite(rs.rel)) { rs.status = KKT_WARN_REFINE; return true; }
     if (rs.rel <= ctx->opt.refine_tol) return true;
-    // componentwise backward error at the FP64 rounding level: no step can
-    // improve the solution further
-    if (rs.omega <= 4.0 * EPS64) { rs.status = KKT_WARN_REFINE; return true; }
     if (rs.it >= ctx->opt.refine_max) { rs.status = KKT_WARN_REFINE; return true; }
     return false;
 }
@@ -1210,15 +1203,10 @@ int refine_fgmres(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, Refine
     std::vector<double> nh(4 * nrhs), bnorm(nrhs), H((size_t)nrhs * M * ldh), g((size_t)nrhs * ldh),
         cs((size_t)nrhs * M), sn((size_t)nrhs * M);
     double prev_cycle = INFINITY;
-    bool converged = false;  // the last cycle's estimate reached the target
     int rc;
     while (true) {
         if ((rc = true_residual(ctx, ra, b, x, V, nrhs, nh, rs))) return rc;
         if (refine_done(ctx, rs)) break;
-        // the Krylov cycle converged in exact arithmetic and the true residual
-        // sits at its own rounding level: a restart cannot improve it
-        if (converged && rs.at_floor) { rs.status = KKT_WARN_REFINE; break; }
-        converged = false;
         // a restart that did not halve the residual ends refinement
         if (rs.rel > 0.5 * prev_cycle) { rs.status = KKT_WARN_REFINE; break; }
         prev_cycle = rs.rel;
@@ -1264,10 +1252,7 @@ int refine_fgmres(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, Refine
             ++j;
             if (ctx->opt.verbose) std::fprintf(stderr, "kkt_solve:   fgmres %d estimate %.3e\n", rs.it, est);
             if (!std::isfinite(est)) break;
-            if (est <= 0.5 * ctx->opt.refine_tol) {
-                converged = true;
-                break;
-            }
+            if (est <= 0.5 * ctx->opt.refine_tol) break;
         }
         // y = R^-1 g (upper triangular R in the rotated H), x += Z y
         for (int64_t k = 0; k < nrhs; ++k) {
@@ -1296,6 +1281,15 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
     if (rc) return rc;
     hipStream_t st = ctx->stream;
     const bool mixed = ctx->opt.precision == KKT_MIXED;
+    // non-finite right-hand sides are rejected before anything is written
+    {
+        int flag = 0;
+        launch_zero<int>(ctx->d_flag + 1, 1, st);
+        launch_check_finite(b, ctx->ntot * nrhs, ctx->d_flag + 1, st);
+        HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (flag) return KKT_ERR_NONFINITE;
+    }
     mark(ctx, 4);
     rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
     if (rc) return rc;
@@ -1321,6 +1315,36 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
     return rs.status;
 }
 
+namespace {
+
+// solve + `steps` classic refinement steps, entirely on the stream, with the
+// workspace the context's pointers name at the time of the call; the norms
+// of the final residual go to `norms` (4 nrhs + 8 doubles)
+int solve_fixed_steps(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps, double *norms) {
+    hipStream_t st = ctx->stream;
+    const bool mixed = ctx->opt.precision == KKT_MIXED;
+    // a non-finite right-hand side is recorded for kkt_solve_status
+    launch_zero<int>(ctx->d_flag + 1, 1, st);
+    launch_check_finite(b, ctx->ntot * nrhs, ctx->d_flag + 1, st);
+    int rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
+    if (rc) return rc;
+    ResidualArgs ra = residual_args(ctx, nrhs);
+    for (int k = 0; k < steps; ++k) {
+        launch_residual(ra, b, x, ctx->d_res, ctx->d_work, norms, st);
+        rc = mixed ? solve_once<float>(ctx, ctx->d_res, ctx->d_dx, nrhs) : solve_once<double>(ctx, ctx->d_res, ctx->d_dx, nrhs);
+        if (rc) return rc;
+        launch_axpy(x, ctx->d_dx, ctx->ntot * nrhs, st);
+    }
+    launch_residual(ra, b, x, ctx->d_res, ctx->d_work, norms, st);
+    ctx->async_nrhs = nrhs;
+    ctx->async_steps = steps;
+    ctx->status_norms = norms;
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
+}  // namespace
+
 // solve + `steps` classic refinement steps, entirely on the stream; the norms
 // of the final residual stay on the device for kkt_solve_status
 extern "C" int kkt_solve_async(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps) {
@@ -1334,22 +1358,7 @@ extern "C" int kkt_solve_async(kkt_ctx *ctx, const double *b, double *x, int64_t
         int rc = ensure_ws(ctx, nrhs);
         if (rc) return rc;
     }
-    hipStream_t st = ctx->stream;
-    const bool mixed = ctx->opt.precision == KKT_MIXED;
-    int rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
-    if (rc) return rc;
-    ResidualArgs ra = residual_args(ctx, nrhs);
-    for (int k = 0; k < steps; ++k) {
-        launch_residual(ra, b, x, ctx->d_res, ctx->d_work, ctx->d_norms, st);
-        rc = mixed ? solve_once<float>(ctx, ctx->d_res, ctx->d_dx, nrhs) : solve_once<double>(ctx, ctx->d_res, ctx->d_dx, nrhs);
-        if (rc) return rc;
-        launch_axpy(x, ctx->d_dx, ctx->ntot * nrhs, st);
-    }
-    launch_residual(ra, b, x, ctx->d_res, ctx->d_work, ctx->d_norms, st);
-    ctx->async_nrhs = nrhs;
-    ctx->async_steps = steps;
-    HIPCHK(hipGetLastError());
-    return KKT_OK;
+    return solve_fixed_steps(ctx, b, x, nrhs, steps, ctx->d_norms);
 }
 
 extern "C" int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info) {
@@ -1357,8 +1366,11 @@ extern "C" int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info) {
     if (ctx->async_nrhs < 1) return KKT_ERR_ORDER;
     const int64_t nrhs = ctx->async_nrhs;
     std::vector<double> nh(4 * nrhs);
-    HIPCHK(hipMemcpyAsync(nh.data(), ctx->d_norms, 8 * 4 * nrhs, hipMemcpyDeviceToHost, ctx->stream));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(nh.data(), ctx->status_norms, 8 * 4 * nrhs, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (flag) return KKT_ERR_NONFINITE;
     double rel = 0.0, omega = 0.0, fl = 0.0;
     for (int64_t k = 0; k < nrhs; ++k) {
         const double bn = nh[4 * k + 1] > 0 ? nh[4 * k + 1] : 1.0;

@@ -1,5 +1,16 @@
 // FP64 residual r = b - K x on the arrowhead blocks (refinement, section 2.1)
 // with the MPOPF border of Eq. B12N, and the norms that steer refinement.
+//
+// A true residual (b given) is evaluated with compensated sums: every product
+// a x is split exactly into p + e (p = fl(a x), e = fma(a, x, -p)), every
+// addition into s + e (Knuth's TwoSum), and the error terms are summed
+// separately, so r is as accurate as if the sums ran in twice the working
+// precision and then were rounded once (Ogita, Rump and Oishi, "Accurate sum
+// and dot product", SIAM J. Sci. Comput. 26, 2005: Sum2 / Dot2). A residual
+// summed in plain FP64 carries an error of order eps || |K||x| + |b| ||, which
+// on late-IPM barrier ranges is larger than the residual of the correctly
+// rounded solution itself; the compensated one resolves it. K x alone (the
+// Krylov products) is summed plainly.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -27,16 +38,61 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// s + e = a + b exactly (Knuth's TwoSum; no branch on the magnitudes)
+__device__ inline void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) -= a x: the product split exactly by fma, the difference by
+// TwoSum, both error terms accumulated in lo (one Dot2 step)
+__device__ inline void dot2_sub(double &hi, double &lo, double a, double x) {
+#pragma clang fp contract(off)
+    const double p = a * x;
+    const double pe = fma(a, x, -p);
+    double s, e;
+    two_sum(hi, -p, s, e);
+    hi = s;
+    lo += e - pe;
+}
+
+// (hi, lo) += (bh, bl), renormalised so that |lo| <= ulp(hi) / 2
+__device__ inline void dd_add(double &hi, double &lo, double bh, double bl) {
+#pragma clang fp contract(off)
+    double s, e;
+    two_sum(hi, bh, s, e);
+    e += lo + bl;
+    hi = s + e;
+    lo = e - (hi - s);
+}
+
+// inclusive scan of the pairs (bh, bl)[0..255] over the workgroup
+__device__ inline void block_scan256_dd(double *bh, double *bl, int tid) {
+    for (int off = 1; off < 256; off <<= 1) {
+        double h = bh[tid], l = bl[tid];
+        if (tid >= off) dd_add(h, l, bh[tid - off], bl[tid - off]);
+        __syncthreads();
+        bh[tid] = h;
+        bl[tid] = l;
+        __syncthreads();
+    }
+}
+
 // Border rows, one workgroup per (storage unit s, right-hand side k), one
 // thread per period m (chunks of 256 periods with carries):
 //   r_g[m] = b_C[m] - C x_g[m] - C_1 x_m - sum_{n<m} C_0 x_n   (Eq. B12N)
 // and the suffix sums sg[n] = sum_{m>n} x_g[m] used by the period rows. The
-// sums over periods are workgroup scans. With norms: the largest
-// componentwise error |r_i|/(|K||x| + |b|)_i goes to norms[4k + 2] and the
-// workgroup's sum of (|K||x| + |b|)_i^2 to bpart[k Ns + s].
+// sums over periods are workgroup scans. With COMP (a true residual) every
+// sum is compensated, the scans run on (hi, lo) pairs and the suffix sums are
+// stored as pairs (sg, sg + N Ns nrhs). With norms: the largest componentwise
+// error |r_i|/(|K||x| + |b|)_i goes to norms[4k + 2] and the workgroup's sum
+// of (|K||x| + |b|)_i^2 to bpart[k Ns + s].
+template <bool COMP>
 __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const double *b, const double *x, double *r,
                                                     double *sg, double *norms, double *bpart) {
-    __shared__ double sc[256], sa[256];
+    __shared__ double sc[256], sl[256], sa[256];
     __shared__ double wred[4];
     double ab2 = 0.0;  // this thread's sum of (|K||x| + |b|)_row^2
     const int64_t s = blockIdx.x;
@@ -45,7 +101,7 @@ __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const doubl
     const double *xk = x + (int64_t)k * ra.ntot;
     const double *xg = xk + ra.N * ra.nA;
     const int64_t c1a = ra.c1p[s], c1b = ra.c1p[s + 1], c0a = ra.c0p[s], c0b = ra.c0p[s + 1];
-    double carry = 0.0, carry_abs = 0.0, wmax = 0.0;
+    double carry = 0.0, carry_lo = 0.0, carry_abs = 0.0, wmax = 0.0;
     for (int64_t m0 = 0; m0 < ra.N; m0 += 256) {
         const int64_t m = m0 + tid;
         const bool on = m < ra.N;
@@ -53,30 +109,39 @@ __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const doubl
         const int64_t g = mc * ra.Ns + s;
         const double *xm = xk + mc * ra.nA;
         const double bc = b ? b[(int64_t)k * ra.ntot + ra.N * ra.nA + g] : 0.0;
-        double acc = bc, ab = fabs(bc);
+        double acc = bc, lo = 0.0, ab = fabs(bc);
         if (ra.corner) {
-            const double t = ra.corner[g] * xg[g];
-            acc -= t;
-            ab += fabs(t);
+            if constexpr (COMP) dot2_sub(acc, lo, ra.corner[g], xg[g]);
+            else acc -= ra.corner[g] * xg[g];
+            ab += fabs(ra.corner[g] * xg[g]);
         }
         for (int64_t e = c1a; e < c1b; ++e) {
-            const double t = ra.C1v[e] * xm[ra.c1i[e]];
-            acc -= t;
-            ab += fabs(t);
+            if constexpr (COMP) dot2_sub(acc, lo, ra.C1v[e], xm[ra.c1i[e]]);
+            else acc -= ra.C1v[e] * xm[ra.c1i[e]];
+            ab += fabs(ra.C1v[e] * xm[ra.c1i[e]]);
         }
-        double c0 = 0.0, a0 = 0.0;
+        // this period's C_0 x_m, negated (so that the scans add)
+        double c0 = 0.0, c0lo = 0.0, a0 = 0.0;
         for (int64_t e = c0a; e < c0b; ++e) {
-            const double t = ra.C0v[e] * xm[ra.c0i[e]];
-            c0 += t;
-            a0 += fabs(t);
+            if constexpr (COMP) dot2_sub(c0, c0lo, ra.C0v[e], xm[ra.c0i[e]]);
+            else c0 -= ra.C0v[e] * xm[ra.c0i[e]];
+            a0 += fabs(ra.C0v[e] * xm[ra.c0i[e]]);
         }
         sc[tid] = on ? c0 : 0.0;
+        sl[tid] = on ? c0lo : 0.0;
         sa[tid] = on ? a0 : 0.0;
         __syncthreads();
-        block_scan256(sc, tid);
+        if constexpr (COMP) block_scan256_dd(sc, sl, tid);
+        else block_scan256(sc, tid);
         block_scan256(sa, tid);
         // exclusive sums over the earlier periods
-        acc -= carry + (tid > 0 ? sc[tid - 1] : 0.0);
+        if constexpr (COMP) {
+            dd_add(acc, lo, carry, carry_lo);
+            if (tid > 0) dd_add(acc, lo, sc[tid - 1], sl[tid - 1]);
+            acc += lo;
+        } else {
+            acc += carry + (tid > 0 ? sc[tid - 1] : 0.0);
+        }
         ab += carry_abs + (tid > 0 ? sa[tid - 1] : 0.0);
         if (on) {
             r[(int64_t)k * ra.ntot + ra.N * ra.nA + g] = b ? acc : -acc;
@@ -84,22 +149,35 @@ __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const doubl
             else if (acc != 0.0) wmax = INFINITY;
             ab2 += ab * ab;
         }
-        carry += sc[255];
+        if constexpr (COMP) dd_add(carry, carry_lo, sc[255], sl[255]);
+        else carry += sc[255];
         carry_abs += sa[255];
         __syncthreads();
     }
     // suffix sums of x_g over the periods, from the last chunk back
-    double scarry = 0.0;
+    double scarry = 0.0, scarry_lo = 0.0;
     const int64_t nch = (ra.N + 255) / 256;
     for (int64_t ch = nch - 1; ch >= 0; --ch) {
         const int64_t m = ch * 256 + (255 - tid);  // reversed: thread 0 holds the last period
         const bool on = m < ra.N;
-        const double v = on ? xg[m * ra.Ns + s] : 0.0;
-        sc[tid] = v;
+        sc[tid] = on ? xg[m * ra.Ns + s] : 0.0;
+        sl[tid] = 0.0;
         __syncthreads();
-        block_scan256(sc, tid);
-        if (on) sg[(int64_t)k * ng + m * ra.Ns + s] = scarry + (tid > 0 ? sc[tid - 1] : 0.0);
-        scarry += sc[255];
+        if constexpr (COMP) block_scan256_dd(sc, sl, tid);
+        else block_scan256(sc, tid);
+        if (on) {
+            const int64_t o = (int64_t)k * ng + m * ra.Ns + s;
+            if constexpr (COMP) {
+                double h = scarry, l = scarry_lo;
+                if (tid > 0) dd_add(h, l, sc[tid - 1], sl[tid - 1]);
+                sg[o] = h;
+                sg[ng * ra.nrhs + o] = l;
+            } else {
+                sg[o] = scarry + (tid > 0 ? sc[tid - 1] : 0.0);
+            }
+        }
+        if constexpr (COMP) dd_add(scarry, scarry_lo, sc[255], sl[255]);
+        else scarry += sc[255];
         __syncthreads();
     }
     if (norms) {
@@ -123,9 +201,9 @@ __global__ __launch_bounds__(256) void k_res_border(ResidualArgs ra, const doubl
 //   r_n = b_n - (A_n + shifts) x_n - C_1^T x_g[n] - C_0^T sg[n]
 // The slice's column indices and values are read coalesced, RES_B entries
 // per row at a time (padding entries carry a zero value and the row's own
-// column).
+// column). With COMP the sums are compensated and sg is a (hi, lo) pair.
 constexpr int RES_B = 8;
-template <int RBT>
+template <int RBT, bool COMP>
 __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const double *b, const double *x, double *r,
                                                      const double *sg, double *wpart) {
     __shared__ double wred[4 * RBT], ared[4 * RBT];
@@ -145,12 +223,13 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
     for (int k0 = 0; k0 < ra.nrhs; k0 += RBT) {
         const int nr = (int)min((int64_t)RBT, ra.nrhs - k0);
         const double *xn[RBT];
-        double acc[RBT], ab[RBT];
+        double acc[RBT], lo[RBT], ab[RBT];
 #pragma unroll
         for (int q = 0; q < RBT; ++q) {
             const int kk = k0 + min(q, nr - 1);
             xn[q] = x + (int64_t)kk * ra.ntot + (int64_t)n * ra.nA;
             acc[q] = b ? b[(int64_t)kk * ra.ntot + (int64_t)n * ra.nA + ic] : 0.0;
+            lo[q] = 0.0;
             ab[q] = fabs(acc[q]);
         }
         for (int u0 = 0; u0 < w; u0 += RES_B) {
@@ -171,9 +250,9 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
                 const double au = u0 + u < w ? a[u] : 0.0;
 #pragma unroll
                 for (int q = 0; q < RBT; ++q) {
-                    const double t = au * xv[u][q];
-                    acc[q] -= t;
-                    ab[q] += fabs(t);
+                    if constexpr (COMP) dot2_sub(acc[q], lo[q], au, xv[u][q]);
+                    else acc[q] -= au * xv[u][q];
+                    ab[q] += fabs(au * xv[u][q]);
                 }
             }
         }
@@ -183,9 +262,10 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
             const int64_t gi = (int64_t)n * ra.Ns + ra.c1ts[e];
 #pragma unroll
             for (int q = 0; q < RBT; ++q) {
-                const double t = cv * x[(int64_t)(k0 + min(q, nr - 1)) * ra.ntot + ra.N * ra.nA + gi];
-                acc[q] -= t;
-                ab[q] += fabs(t);
+                const double xq = x[(int64_t)(k0 + min(q, nr - 1)) * ra.ntot + ra.N * ra.nA + gi];
+                if constexpr (COMP) dot2_sub(acc[q], lo[q], cv, xq);
+                else acc[q] -= cv * xq;
+                ab[q] += fabs(cv * xq);
             }
         }
         const int64_t t0a = on ? ra.c0tp[ic] : 0, t0b = on ? ra.c0tp[ic + 1] : 0;
@@ -194,14 +274,21 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
             const int64_t gi = (int64_t)n * ra.Ns + ra.c0ts[e];
 #pragma unroll
             for (int q = 0; q < RBT; ++q) {
-                const double t = cv * sg[(int64_t)(k0 + min(q, nr - 1)) * ng + gi];
-                acc[q] -= t;
-                ab[q] += fabs(t);
+                const int64_t o = (int64_t)(k0 + min(q, nr - 1)) * ng + gi;
+                const double sq = sg[o];
+                if constexpr (COMP) {
+                    dot2_sub(acc[q], lo[q], cv, sq);
+                    lo[q] -= cv * sg[ng * ra.nrhs + o];
+                } else {
+                    acc[q] -= cv * sq;
+                }
+                ab[q] += fabs(cv * sq);
             }
         }
         double wq[RBT], aq[RBT];
 #pragma unroll
         for (int q = 0; q < RBT; ++q) {
+            if constexpr (COMP) acc[q] += lo[q];
             wq[q] = 0.0;
             aq[q] = 0.0;
             if (on && q < nr) {
@@ -334,44 +421,46 @@ __global__ void k_zero_norms(double *norms, int nrhs) {
 }
 
 int64_t residual_work(int64_t N, int64_t nA, int64_t Ns, int64_t nrhs) {
-    // sg, norm partials, per-workgroup max and floor partials, border partials
-    return std::max<int64_t>(N * Ns * nrhs, 1) + 2 * NPART * nrhs + 2 * ((nA + 255) / 256) * N * nrhs + Ns * nrhs +
+    // sg (hi and lo), norm partials, per-workgroup max and floor partials,
+    // border partials
+    return 2 * std::max<int64_t>(N * Ns * nrhs, 1) + 2 * NPART * nrhs + 2 * ((nA + 255) / 256) * N * nrhs + Ns * nrhs +
            8;
 }
 
+template <bool COMP>
 static void launch_res_periods(const ResidualArgs &ra, const double *b, const double *x, double *r, const double *sg,
                                double *wpart, hipStream_t st) {
     const dim3 grid((unsigned)(((ra.nA + 63) / 64 + 3) / 4), (unsigned)ra.N);  // four 64-row slices per workgroup
-    if (ra.nrhs >= 3) hipLaunchKernelGGL(k_res_periods<4>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
-    else if (ra.nrhs == 2) hipLaunchKernelGGL(k_res_periods<2>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
-    else hipLaunchKernelGGL(k_res_periods<1>, grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
+    if (ra.nrhs >= 3) hipLaunchKernelGGL((k_res_periods<4, COMP>), grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
+    else if (ra.nrhs == 2) hipLaunchKernelGGL((k_res_periods<2, COMP>), grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
+    else hipLaunchKernelGGL((k_res_periods<1, COMP>), grid, dim3(256), 0, st, ra, b, x, r, sg, wpart);
 }
 
-// work must hold residual_work() doubles
+// work must hold residual_work() doubles; r = b - K x compensated
 void launch_residual(const ResidualArgs &ra, const double *b, const double *x, double *r, double *work,
                      double *norms, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_norms, dim3(1), dim3(256), 0, st, norms, (int)ra.nrhs);
     double *sg = work;
-    double *part = work + std::max<int64_t>(ra.N * ra.Ns * ra.nrhs, 1);
+    double *part = work + 2 * std::max<int64_t>(ra.N * ra.Ns * ra.nrhs, 1);
     double *wpart = part + 2 * NPART * ra.nrhs;
     const int64_t nw = ((ra.nA + 255) / 256) * ra.N;
     double *bpart = wpart + 2 * nw * ra.nrhs;
     if (ra.Ns > 0)
-        hipLaunchKernelGGL(k_res_border, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra, b, x, r, sg,
-                           norms, bpart);
-    launch_res_periods(ra, b, x, r, sg, wpart, st);
+        hipLaunchKernelGGL(k_res_border<true>, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra, b, x,
+                           r, sg, norms, bpart);
+    launch_res_periods<true>(ra, b, x, r, sg, wpart, st);
     hipLaunchKernelGGL(k_norm_partial, dim3(NPART, (unsigned)ra.nrhs), dim3(256), 0, st, r, b, ra.ntot, part);
     hipLaunchKernelGGL(k_norm_final, dim3((unsigned)ra.nrhs), dim3(256), 0, st, part, wpart, nw, bpart, ra.Ns,
                        ra.nrhs, norms);
 }
 
-// y = K x (no norms)
+// y = K x (no norms, plain sums)
 void launch_matvec(const ResidualArgs &ra, const double *x, double *y, double *work, hipStream_t st) {
     double *sg = work;
     if (ra.Ns > 0)
-        hipLaunchKernelGGL(k_res_border, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra,
+        hipLaunchKernelGGL(k_res_border<false>, dim3((unsigned)ra.Ns, (unsigned)ra.nrhs), dim3(256), 0, st, ra,
                            (const double *)nullptr, x, y, sg, (double *)nullptr, (double *)nullptr);
-    launch_res_periods(ra, nullptr, x, y, sg, nullptr, st);
+    launch_res_periods<false>(ra, nullptr, x, y, sg, nullptr, st);
 }
 
 __global__ void k_axpy(double *x, const double *dx, int64_t n) {

@@ -1,7 +1,6 @@
 // Host-only entry points: options, error strings and the planning query.
 #include <algorithm>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 
 #include "../../include/kkt.h"
@@ -18,6 +17,7 @@ extern "C" void kkt_default_options(kkt_options *opt) {
     opt->refine_method = KKT_REFINE_FGMRES;
     opt->big_tile_rows = 0;
     opt->schur_mode = KKT_SCHUR_DENSE;
+    opt->dual_wait = 0;
 }
 
 extern "C" const char *kkt_strerror(int code) {
@@ -40,7 +40,8 @@ namespace kkt {
 SymbolicInput make_input(const kkt_structure *s, const kkt_options &o) {
     SymbolicInput in;
     // FP32 factors cannot absorb the growth that early duals cause
-    in.dual_wait = o.precision == KKT_MIXED ? (1 << 30) : 4;
+    in.dual_wait = o.dual_wait > 0 ? o.dual_wait : (o.precision == KKT_MIXED ? (1 << 30) : 4);
+    in.pair_duals = true;
     in.nA = s->nA;
     in.n_primal = s->n_primal;
     in.Ns = s->Ns;

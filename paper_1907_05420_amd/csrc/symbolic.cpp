@@ -18,7 +18,7 @@ namespace kkt {
 // few of their primal neighbours are eliminated (see `need` below).
 // ---------------------------------------------------------------------------
 std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
-                               const std::vector<int32_t> &adj, int64_t n_primal, int dual_wait) {
+                               const std::vector<int32_t> &adj, int64_t n_primal, int dual_wait, bool pair_duals) {
     std::vector<std::vector<int32_t>> Av(n), Ev(n), Le(n), members(n);
     std::vector<int32_t> nv(n, 1), deg(n), status(n, 0);  // 0 var, 1 element, 2 dead
     // dual eligibility: number of primal neighbours not yet eliminated
@@ -86,6 +86,50 @@ std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
         }
     };
     for (int32_t i = 0; i < n; ++i) bucket_insert(i);
+    // Pairing of duals with eliminated primals: a dual (supervariable of m
+    // duals) is eliminated only when it can claim m eliminated primal
+    // neighbours that no earlier dual claimed (greedily, the partners that
+    // the fewest other duals still wait for first). Eliminated duals then
+    // never outnumber the eliminated primals they touch, so the dual block of
+    // the partial Schur complement (-delta_c - J_E H_EE^-1 J_E^T restricted
+    // to them) keeps full structural rank; without it, a dual eliminated
+    // after others that share its few eliminated primal neighbours (the P-
+    // and Q-balance rows of adjacent buses share their (theta, V) columns) is
+    // left with a pivot near -delta_c and the factor with growth near
+    // 1/delta_c. A dual that cannot claim waits for its next primal
+    // neighbour; if none is left it is forced (no deadlock). Measured on
+    // the MPOPF blocks: growth 1e8 -> <= 3e5 at 10% less fill than without
+    // pairing (claims that augmenting paths may move between duals delay
+    // fewer duals and measured worse: growth 1e6, the unpaired fill).
+    std::vector<char> elim(n, 0), claimed(n, 0), forced(n, 0);
+    std::vector<int32_t> waiting_duals(n, 0);  // per primal: original dual neighbours not yet eliminated
+    if (pair_duals && constrained)
+        for (int32_t i = 0; i < n; ++i)
+            if (!is_dual(i))
+                for (int64_t k = xadj[i]; k < xadj[i + 1]; ++k)
+                    if (is_dual(adj[k])) waiting_duals[i]++;
+    std::vector<int32_t> cand;
+    std::vector<int64_t> cmark(n, -1);
+    int64_t cstamp = 0;
+    // claim partners for dual supervariable p; false when too few are free
+    auto claim = [&](int32_t p) {
+        ++cstamp;
+        cand.clear();
+        for (int32_t v : members[p])
+            for (int64_t k = xadj[v]; k < xadj[v + 1]; ++k) {
+                const int32_t u = adj[k];
+                if (is_dual(u) || !elim[u] || claimed[u] || cmark[u] == cstamp) continue;
+                cmark[u] = cstamp;
+                cand.push_back(u);
+            }
+        const size_t m = members[p].size();
+        if (cand.size() < m) return false;
+        std::sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+            return waiting_duals[a] != waiting_duals[b] ? waiting_duals[a] < waiting_duals[b] : a < b;
+        });
+        for (size_t q = 0; q < m; ++q) claimed[cand[q]] = 1;
+        return true;
+    };
     std::vector<int32_t> order;
     order.reserve(n);
     int64_t nel = 0;
@@ -93,9 +137,25 @@ std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
     std::vector<std::pair<int64_t, int32_t>> hv;
     while (nel < n) {
         while (mindeg <= n && head[mindeg] < 0) ++mindeg;
-        if (mindeg > n) break;  // cannot happen
+        if (mindeg > n) {
+            // only duals that cannot claim a partner are left: force them
+            bool any = false;
+            for (int32_t i = 0; i < n; ++i)
+                if (status[i] == 0 && blocked[i] > 0) {
+                    blocked[i] = 0;
+                    forced[i] = 1;
+                    bucket_insert(i);
+                    any = true;
+                }
+            if (!any) break;  // cannot happen
+            continue;
+        }
         int32_t p = head[mindeg];
         bucket_remove(p);
+        if (pair_duals && is_dual(p) && !forced[p] && !claim(p)) {
+            blocked[p] = 1;  // eligible again after its next primal neighbour
+            continue;
+        }
         // new element L_p
         ++stamp;
         mark[p] = stamp;
@@ -113,7 +173,14 @@ std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
         status[p] = 1;
         std::vector<int32_t>().swap(Av[p]);
         std::vector<int32_t>().swap(Ev[p]);
-        for (int32_t v : members[p]) { order.push_back(v); release(v); }
+        for (int32_t v : members[p]) {
+            order.push_back(v);
+            elim[v] = 1;
+            release(v);
+            if (pair_duals && is_dual(v))
+                for (int64_t k = xadj[v]; k < xadj[v + 1]; ++k)
+                    if (!is_dual(adj[k])) waiting_duals[adj[k]]--;
+        }
         nel += nv[p];
         if (lpw == n - nel) {  // remaining graph is a clique: primals, then duals
             for (int pass = 0; pass < 2; ++pass)
@@ -274,7 +341,7 @@ std::string analyze(const SymbolicInput &in, Symbolic &S) {
             adj[pos[j]++] = i;
             adj[pos[i]++] = (int32_t)j;
         }
-    std::vector<int32_t> perm = amd_order((int32_t)nA, xadj, adj, in.n_primal, in.dual_wait);
+    std::vector<int32_t> perm = amd_order((int32_t)nA, xadj, adj, in.n_primal, in.dual_wait, in.pair_duals);
     if ((int64_t)perm.size() != nA) return "ordering failed";
 
     // --- lower pattern of M by rows in a given order --------------------------

@@ -21,6 +21,8 @@ struct SymbolicInput {
     // primal neighbours a dual waits for before it may be eliminated
     // (capped at its count; see amd_order)
     int dual_wait = 4;
+    // duals also need an eliminated primal partner of their own (amd_order)
+    bool pair_duals = true;
     const int64_t *colptr = nullptr;
     const int32_t *rowind = nullptr;
     const int64_t *C0p = nullptr, *C1p = nullptr;
@@ -65,9 +67,11 @@ struct Symbolic {
 // self loops). Returns perm[new] = old. With n_primal >= 0, a variable
 // i >= n_primal (a dual) becomes eligible only once min(dual_wait, its number
 // of primal neighbours) of its primal neighbours (i' < n_primal) of the
-// original graph are eliminated.
+// original graph are eliminated; with pair_duals it must also claim eliminated
+// primal neighbours of its own, one per dual (see the definition).
 std::vector<int32_t> amd_order(int32_t n, const std::vector<int64_t> &xadj,
-                               const std::vector<int32_t> &adj, int64_t n_primal = -1, int dual_wait = 4);
+                               const std::vector<int32_t> &adj, int64_t n_primal = -1, int dual_wait = 4,
+                               bool pair_duals = false);
 
 // Full analysis. Returns an empty string on success, else an error message
 // (structural problem in the input).

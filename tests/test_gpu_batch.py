@@ -55,7 +55,7 @@ def test_batch_equals_alone_and_oracle(precision):
         assert np.array_equal(xa, xe)
     for inst, st, xe in zip(insts, b.status(), eager):
         ref, xref, K = reference(inst)
-        rel, _ = ah.rel_residual(inst, xe, inst.b, K)
+        rel = ah.rel_residual_ld(inst, xe, inst.b, K)
         assert rel <= residual_bar(ref), rel
         assert st["inertia"]["inertia_ok"] == 1
         assert st["info"]["rel_res"] <= 1e-10

@@ -1,16 +1,26 @@
 """Parity at the full 2000-bus / 96-period / 4-RHS size, in the configuration
-the benchmark times: properties that hold at any size plus outputs the oracle
-computes one period at a time.
+the benchmark times, against the FP64 oracle's solution of the same instance
+(tests/golden/mesh2000_N96_reference.npz, written by
+tests/golden/make_mesh2000_reference.py from oracle/ and kktgen/ only):
 
-  * residual: ||b - K x||_2/||b||_2 from the oracle's assembled K (FP64, CPU)
-    must be <= max(1e-10, 16 eps ||(|K||x|)||_2/||b||_2): the second term is
-    the rounding floor of evaluating K x itself, which the barrier range
-    [1e-8, 1e8] lifts above 1e-10 on this instance (flagged when it does);
-  * componentwise backward error omega <= 1e-8 (FP64 refinement stops at the
-    normwise rounding floor; the componentwise error then sits near 1e-9);
+  * residual ||b - K x||_2/||b||_2 on the oracle's assembled K, evaluated in
+    extended precision: at most max(1e-10, 2 x the oracle's best), the bar of
+    the relative-residual reading; the oracle's correctly refined FP64
+    solution reaches 7.5e-11 to 8.3e-11 here, so the bar is 1.65e-10 and the
+    1e-10 target is reachable. The library's own (compensated) residual
+    agrees with the extended-precision one;
+  * sampled entries of x (4096 period rows, 2048 border rows per
+    right-hand side) against the oracle's, element by element: solutions
+    with residuals near 1e-10 differ from the refined one by about 1e-11 of
+    ||x||_inf and 1e-7 of an entry (measured on smaller instances of the same
+    barrier range), checked at 1e-9 ||x||_inf + 1e-5 |x_i|;
+  * six 64 x 64 corners of blocks of S against the oracle's S (the unique
+    Schur complement) within 1e-8 of the block's largest entry;
   * S_bar_n (Eq. LocalSchurBs3) of sampled periods vs the oracle's sparse solve;
   * Eq. GlobalSchur on sampled block columns of the GPU's S;
   * inertia (96*5200, 96*4000 + 19200, 0) exactly."""
+import os
+
 import numpy as np
 import pytest
 
@@ -20,10 +30,22 @@ from oracle import schur as sc
 
 pytestmark = pytest.mark.gpu
 EPS = 2.220446049250313e-16
+REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mesh2000_N96_reference.npz")
 
 
 @pytest.fixture(scope="module")
-def mesh2000():
+def golden():
+    z = np.load(REF, allow_pickle=False)
+    return {k: z[k] for k in z.files}
+
+
+def instance_sums(inst):
+    return np.array([inst.vals.sum(), np.abs(inst.vals).sum(), inst.b.sum(), np.abs(inst.b).sum(),
+                     inst.C0_vals.sum(), inst.C1_vals.sum()])
+
+
+@pytest.fixture(scope="module")
+def mesh2000(golden):
     import torch
     import paper_1907_05420_amd as pk
     inst = kktgen.make_workload(2)
@@ -39,7 +61,9 @@ def mesh2000():
         for m in (mp, mp + 1, mp + 2, inst.N - 1):
             if m < inst.N:
                 picks[(m, mp)] = S[m * ns:(m + 1) * ns, mp * ns:(mp + 1) * ns].cpu().numpy()
-    out = dict(inst=inst, x=x.cpu().numpy(), rc_f=rc_f, inn=inn, info=info, footprint=s.footprint(),
+    for m, mp in golden["S_blocks"]:
+        picks[(int(m), int(mp))] = S[m * ns:(m + 1) * ns, mp * ns:(mp + 1) * ns].cpu().numpy()
+    out = dict(inst=inst, x=x.cpu().numpy(), rc_f=rc_f, rc_s=rc_s, inn=inn, info=info, footprint=s.footprint(),
                sbar={n: sbar[n].cpu().numpy() for n in (0, 47, 95)}, S=picks)
     del S, sbar
     torch.cuda.synchronize()
@@ -47,20 +71,39 @@ def mesh2000():
     return out
 
 
-def test_fullsize_residual_and_backward_error(mesh2000):
+def test_fullsize_same_instance_as_reference(golden):
+    inst = kktgen.make_workload(2)
+    assert np.allclose(instance_sums(inst), golden["sums"], rtol=1e-14, atol=0)
+
+
+def test_fullsize_residual_and_backward_error(mesh2000, golden):
     inst, x = mesh2000["inst"], mesh2000["x"]
     K = ah.assemble(inst)
-    r = inst.b - (K @ x.T).T
-    rel = float(np.max(np.linalg.norm(r, axis=1) / np.linalg.norm(inst.b, axis=1)))
-    floor = float(np.max(np.linalg.norm((abs(K) @ np.abs(x).T).T, axis=1) / np.linalg.norm(inst.b, axis=1)))
-    bar = max(1e-10, 16 * EPS * floor)
-    if bar > 1e-10:
-        print(f"[flagged] rounding floor of K x lifts the bar to {bar:.2e}; rel_res {rel:.2e}")
-    assert rel <= bar, (rel, bar)
+    _, rel = ah.residual_ld(inst, x, inst.b, K)
+    bar = max(1e-10, 2.0 * float(np.max(golden["best_rel"])))
+    print(f"rel_res (extended) {rel}, oracle best {golden['best_rel']}, bar {bar:.2e}, "
+          f"refine_iters {mesh2000['info']['refine_iters']}, rc {mesh2000['rc_s']}")
+    assert np.max(rel) <= bar, (rel, bar)
     assert ah.backward_error(inst, x, inst.b, K) <= 1e-8
-    # the library's own FP64 residual agrees up to the rounding of K x (a
-    # different summation order at the rounding floor)
-    assert 0.5 * rel <= mesh2000["info"]["rel_res"] <= 2.0 * rel
+    # the library's compensated residual is the residual (not its FP64 rounding)
+    assert abs(mesh2000["info"]["rel_res"] - np.max(rel)) <= 1e-2 * np.max(rel)
+
+
+def test_fullsize_x_matches_oracle_samples(mesh2000, golden):
+    x = mesh2000["x"][:, golden["idx"]]
+    xr = golden["x"]
+    tol = 1e-9 * golden["x_inf"][:, None] + 1e-5 * np.abs(xr)
+    err = np.abs(x - xr)
+    worst = np.unravel_index(np.argmax(err / tol), err.shape)
+    assert np.all(err <= tol), (worst, x[worst], xr[worst], tol[worst])
+
+
+def test_fullsize_schur_blocks_match_oracle(mesh2000, golden):
+    for q, (m, mp) in enumerate(golden["S_blocks"]):
+        g = mesh2000["S"][(int(m), int(mp))][:64, :64]
+        ref = golden["S"][q]
+        err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-8, ((m, mp), err)
 
 
 def test_fullsize_inertia(mesh2000):
@@ -111,10 +154,9 @@ def test_fullsize_structured_schur(mesh2000, mesh2000_structured):
     r = mesh2000_structured
     inst, x = r["inst"], r["x"]
     K = ah.assemble(inst)
-    res = inst.b - (K @ x.T).T
-    rel = float(np.max(np.linalg.norm(res, axis=1) / np.linalg.norm(inst.b, axis=1)))
-    floor = float(np.max(np.linalg.norm((abs(K) @ np.abs(x).T).T, axis=1) / np.linalg.norm(inst.b, axis=1)))
-    assert rel <= max(1e-10, 16 * EPS * floor), rel
+    rel = ah.rel_residual_ld(inst, x, inst.b, K)
+    golden = np.load(REF, allow_pickle=False)
+    assert rel <= max(1e-10, 2.0 * float(np.max(golden["best_rel"]))), rel
     assert ah.backward_error(inst, x, inst.b, K) <= 1e-8
     inn = r["inn"]
     assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == (96 * 5200, 96 * 4000 + 19200, 0)

@@ -1,12 +1,15 @@
 """GPU parity: the HIP path (called through the C-ABI) against the FP64 oracle.
 
 Tolerances (FP64 path): the relative residual max_k ||b_k - K x_k||_2/||b_k||_2,
-computed on the CPU from the oracle's assembled K, must be <= 1e-10 (the
-target of the workload definition); the forward error against the oracle's
-refined solution is bounded by cond(K) * 1e-16-level backward errors, so it is
-checked at 1e-9 on well-conditioned inputs (barrier range [1e-2, 1e2]) and at
-1e-6 on the wide barrier ranges. Schur complements are unique and are compared
-elementwise relative to max|S| (1e-9 well-conditioned). Inertia is exact."""
+computed on the CPU from the oracle's assembled K in extended precision, must
+be <= 1e-10 (the target of the workload definition), or twice the best the
+oracle's refined FP64 solution reaches where that is more (flagged). On the
+well-conditioned inputs (barrier range [1e-2, 1e2]) x is compared with the
+oracle's element by element (1e-10 ||x||_inf + 1e-7 |x_i|), both unrefined
+(refine_max = 0, against the oracle's unrefined Algorithm 1) and refined (at
+most one refinement step); on the wide barrier ranges normwise at 1e-6.
+Schur complements are unique and are compared elementwise relative to max|S|
+(1e-9 well-conditioned). Inertia is exact."""
 import numpy as np
 import pytest
 
@@ -26,13 +29,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_gpu(inst, precision=0, want_schur=True, delta_w=0.0, delta_c=0.0, vals=None):
+def run_gpu(inst, precision=0, want_schur=True, delta_w=0.0, delta_c=0.0, vals=None, refine_max=20, dual_wait=0):
     torch = _torch()
     import paper_1907_05420_amd as pk
     d = pk.device_inputs(inst)
     if vals is not None:
         d["vals"] = torch.as_tensor(vals).cuda()
-    s = pk.Solver(inst, precision=precision)
+    s = pk.Solver(inst, precision=precision, refine_max=refine_max, dual_wait=dual_wait)
     rc_f, inertia = s.factor(d["vals"], d["C0"], d["C1"], d["corner"], delta_w, delta_c)
     x, rc_s, info = s.solve(d["b"])
     out = dict(x=x.cpu().numpy(), rc_factor=rc_f, rc_solve=rc_s, inertia=inertia, info=info,
@@ -46,10 +49,13 @@ def run_gpu(inst, precision=0, want_schur=True, delta_w=0.0, delta_c=0.0, vals=N
 
 
 def reference(inst):
+    """The oracle's Algorithm 1, refined with extended-precision residuals
+    (section 2.1) until they stop improving; best_rel is the smallest
+    relative residual along the way (what an FP64 solution can reach)."""
     out = sc.algorithm1(inst)
     K = ah.assemble(inst)
-    solve = lambda r: sc.algorithm1(inst, b=r, factors=out["factors"])["x"]
-    x, hist = sc.refine(inst, out["x"], inst.b, solve, tol=1e-14, K=K)
+    solve = lambda r: sc.algorithm1(inst, b=r, factors=out["factors"], schur=out["schur_fac"])["x"]
+    x, hist = sc.refine(inst, out["x"], inst.b, solve, tol=1e-16, K=K, extended=True)
     out["best_rel"] = min(hist)
     return out, x, K
 
@@ -80,15 +86,65 @@ SMALL = [
 ]
 
 
+def assert_x_close(x, xref, atol_inf, rtol):
+    """Element by element: |x_i - xref_i| <= atol_inf ||xref||_inf + rtol |xref_i|
+    (per right-hand side)."""
+    xinf = np.max(np.abs(xref), axis=-1, keepdims=True)
+    err = np.abs(x - xref)
+    tol = atol_inf * xinf + rtol * np.abs(xref)
+    worst = np.unravel_index(np.argmax(err / tol), err.shape)
+    assert np.all(err <= tol), (worst, x[worst], xref[worst], err[worst] / xinf[worst[0], 0])
+
+
+GROWTH_FREE = 1 << 30   # dual_wait: every dual waits for all its primal neighbours
+
+
+@pytest.mark.parametrize("case", SMALL)
+def test_parity_small_unrefined(case):
+    """refine_max = 0: the factorisation's own solution (Algorithm 1 with no
+    refinement step), so refinement cannot hide a wrong factor.
+
+    In the elimination order where every dual waits for all its primal
+    neighbours (no pivot growth on these blocks; the same kernels as every
+    other order) the unrefined solution meets the oracle pin's 1e-11
+    residual bar and matches the oracle's unrefined Algorithm 1 element by
+    element: two FP64 solves of these well-conditioned systems in different
+    elimination orders differ by at most 2e-12 ||x||_inf and 1e-8 of an
+    entry (oracle against the LAPACK solve of the assembled K), checked at
+    1e-10 ||x||_inf + 1e-7 |x_i|.
+
+    In the default order (dual wait 4 with pairing) these blocks show pivot
+    growth up to 3e5 (measured with the oracle's LDL^T in that order), so the
+    unrefined residual is held to 1e-9 there."""
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    ora = sc.algorithm1(inst)
+    K = ah.assemble(inst)
+    assert ah.rel_residual_ld(inst, ora["x"], inst.b, K) <= 1e-11
+    g = run_gpu(inst, want_schur=False, refine_max=0, dual_wait=GROWTH_FREE)
+    rel = ah.rel_residual_ld(inst, g["x"], inst.b, K)
+    assert rel <= 1e-11, rel
+    assert g["info"]["refine_iters"] == 0
+    assert g["rc_solve"] == 0
+    assert abs(g["info"]["rel_res"] - rel) <= 1e-2 * rel + 1e-17
+    assert_x_close(g["x"], ora["x"], 1e-10, 1e-7)
+    inn = g["inertia"]
+    assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == ora["inertia"] and inn["n_perturbed"] == 0
+    d = run_gpu(inst, want_schur=False, refine_max=0)
+    rel_d = ah.rel_residual_ld(inst, d["x"], inst.b, K)
+    assert rel_d <= 1e-9, rel_d
+    assert d["info"]["refine_iters"] == 0
+
+
 @pytest.mark.parametrize("case", SMALL)
 def test_parity_small(case):
     inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
     ref, xref, K = reference(inst)
     g = run_gpu(inst)
-    rel, _ = ah.rel_residual(inst, g["x"], inst.b, K)
+    rel = ah.rel_residual_ld(inst, g["x"], inst.b, K)
     assert rel <= 1e-10, rel
-    assert _rel(g["x"], xref) <= 1e-9, _rel(g["x"], xref)
+    assert_x_close(g["x"], xref, 1e-10, 1e-7)
     assert g["info"]["rel_res"] <= 1e-10
+    assert g["info"]["refine_iters"] <= 1
     expect = (inst.N * inst.n_primal, inst.N * (inst.n_A - inst.n_primal) + inst.n_g, 0)
     inn = g["inertia"]
     assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == expect == ref["inertia"]
@@ -106,7 +162,7 @@ def test_parity_ring30():
     inst = kktgen.make_workload(1)
     ref, xref, K = reference(inst)
     g = run_gpu(inst)
-    rel, _ = ah.rel_residual(inst, g["x"], inst.b, K)
+    rel = ah.rel_residual_ld(inst, g["x"], inst.b, K)
     assert rel <= residual_bar(ref), rel
     assert _rel(g["x"], xref) <= 1e-6
     inn = g["inertia"]
@@ -118,8 +174,9 @@ def test_parity_ring30_wide_barrier():
     inst = kktgen.make_workload(1, rep=1, barrier=(1e-8, 1e8), nrhs=4)
     ref, xref, K = reference(inst)
     g = run_gpu(inst, want_schur=False)
-    rel, _ = ah.rel_residual(inst, g["x"], inst.b, K)
+    rel = ah.rel_residual_ld(inst, g["x"], inst.b, K)
     assert rel <= residual_bar(ref), rel
+    assert abs(g["info"]["rel_res"] - rel) <= 1e-2 * rel
     assert ah.backward_error(inst, g["x"], inst.b, K) <= 1e-14
     assert _rel(g["x"], xref) <= 1e-6
 
@@ -183,7 +240,7 @@ def test_call_order_and_nonfinite():
 
 def test_wrong_sign_barrier_reports_inertia():
     """A negative Hessian diagonal (wrong-sign barrier) leaves a wrong-sign pivot:
-    the factor reports the inertia warning instead of hiding it (section 2.4)."""
+    the factor reports the inertia warning instead of hiding it (section 2.3)."""
     inst = kktgen.make_small(nb=8, nextra=3, ng=2, ns=2, N=2, seed=0)
     vals = inst.vals.copy()
     kind = inst.meta["kind"]
@@ -204,7 +261,7 @@ def test_wrong_sign_barrier_reports_inertia():
 
 
 def test_inertia_correction_shifts():
-    """delta_w / delta_c (section 2.4) match the oracle on the shifted matrix."""
+    """delta_w / delta_c (section 2.3) match the oracle on the shifted matrix."""
     inst = kktgen.make_small(nb=12, nextra=6, ng=3, ns=3, N=4, nrhs=1, seed=1, barrier_range=(1e-2, 1e2))
     dw, dc = 0.25, 1e-4
     g = run_gpu(inst, delta_w=dw, delta_c=dc)
@@ -253,7 +310,7 @@ def test_parity_structured_schur(case):
     x, rc_s, info = s.solve(d["b"])
     x = x.cpu().numpy()
     s.close()
-    rel, _ = ah.rel_residual(inst, x, inst.b, K)
+    rel = ah.rel_residual_ld(inst, x, inst.b, K)
     assert rel <= 1e-10, rel
     assert _rel(x, xref) <= 1e-9, _rel(x, xref)
     assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == ref["inertia"]
@@ -273,7 +330,7 @@ def test_parity_structured_ring30_wide_barrier():
         out[mode] = (x.cpu().numpy(), inn, info)
         s.close()
     xs, inn, info = out[pk.KKT_SCHUR_STRUCTURED]
-    rel, _ = ah.rel_residual(inst, xs, inst.b, K)
+    rel = ah.rel_residual_ld(inst, xs, inst.b, K)
     assert rel <= residual_bar(ref), rel
     assert inn["inertia_ok"] == 1
     assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == \
@@ -321,7 +378,7 @@ def test_parity_structured_wide_border():
         x, _, info = s.solve(d["b"])
         xs[mode] = x.cpu().numpy()
         s.close()
-        rel, _ = ah.rel_residual(inst, xs[mode], inst.b, K)
+        rel = ah.rel_residual_ld(inst, xs[mode], inst.b, K)
         assert rel <= 1e-10, (mode, rel)
         assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == expect, (mode, inn)
         assert inn["n_perturbed"] == 0
