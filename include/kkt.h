@@ -53,6 +53,8 @@ extern "C" {
                                   /* unsorted/duplicate row index, bad C col  */
 #define KKT_ERR_HIP (-5)          /* HIP runtime error                        */
 #define KKT_ERR_NONFINITE (-6)    /* NaN/Inf in the values or the RHS         */
+#define KKT_ERR_TOOBIG (-7)       /* the system needs more workspace than the  */
+                                  /* fixed array of kkt_solve_noalloc holds    */
 #define KKT_WARN_PERTURBED 1      /* static pivots were perturbed             */
 #define KKT_WARN_INERTIA 2        /* inertia differs from (N*n_primal,        */
                                   /*   N*(nA-n_primal)+N*Ns, 0)              */
@@ -243,6 +245,27 @@ int kkt_factor_status(kkt_ctx *ctx, kkt_inertia *out);
  * least nrhs right-hand sides creates it); otherwise KKT_ERR_ARG. */
 int kkt_solve_async(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps);
 int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info);
+
+/* kkt_solve_noalloc: kkt_solve_async (the same kernels and arithmetic, so
+ * the same x bit for bit) for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. The call allocates nothing: its solve workspace is a fixed
+ * 32 MiB device array inside the library (one per device, held from the
+ * library's first use on that device until the process ends), and the norms
+ * of the final residual stay in the context (read them with
+ * kkt_solve_status). The caller passes b and x as for kkt_solve_async; the
+ * context must be analysed and factored (kkt_analyze / kkt_factor allocate as
+ * usual). Every call on a device shares that device's array and leaves its
+ * contents behind (each call writes all of the workspace it reads), so calls
+ * that overlap on one device, from any context or stream, race: the caller
+ * orders them (e.g. one stream, or an event between them).
+ * Returns KKT_ERR_TOOBIG, with nothing enqueued, when the workspace for
+ * nrhs right-hand sides exceeds the array: about
+ * 8 * nrhs * (3 N nA + N u + 9 N Ns) bytes plus 9 KB per right-hand side,
+ * with u the update-vector length of one period (a few times nA); e.g. 30
+ * buses, 8 periods and 4 right-hand sides need well under 1 MiB. Other
+ * errors as kkt_solve_async. */
+int kkt_solve_noalloc(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps);
 
 /* ---- uneven batches (many independent systems, one submission) ----------- */
 

@@ -18,7 +18,7 @@ import numpy as np
 
 from . import _abi
 from ._abi import (KKT_OK, KKT_ERR_ARG, KKT_ERR_NOMEM, KKT_ERR_ORDER, KKT_ERR_STRUCT, KKT_ERR_HIP,
-                   KKT_ERR_NONFINITE, KKT_WARN_PERTURBED, KKT_WARN_INERTIA, KKT_WARN_REFINE, KKT_FP64,
+                   KKT_ERR_NONFINITE, KKT_ERR_TOOBIG, KKT_WARN_PERTURBED, KKT_WARN_INERTIA, KKT_WARN_REFINE, KKT_FP64,
                    KKT_MIXED, KKT_REFINE_FGMRES, KKT_REFINE_CLASSIC, KKT_SCHUR_DENSE, KKT_SCHUR_STRUCTURED)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkkt.so")
@@ -188,6 +188,12 @@ def kkt_factor_status(ctx):
 
 def kkt_solve_async(ctx, b, x, nrhs, steps):
     return _check(load_library().kkt_solve_async(ctx, _ptr(b), _ptr(x), int(nrhs), int(steps)), "kkt_solve_async")
+
+
+def kkt_solve_noalloc(ctx, b, x, nrhs, steps):
+    """kkt_solve_async with its workspace in the library's fixed device array
+    (allocates nothing)."""
+    return _check(load_library().kkt_solve_noalloc(ctx, _ptr(b), _ptr(x), int(nrhs), int(steps)), "kkt_solve_noalloc")
 
 
 def kkt_solve_status(ctx):

@@ -8,6 +8,7 @@ KKT_ERR_ORDER = -3
 KKT_ERR_STRUCT = -4
 KKT_ERR_HIP = -5
 KKT_ERR_NONFINITE = -6
+KKT_ERR_TOOBIG = -7
 KKT_WARN_PERTURBED = 1
 KKT_WARN_INERTIA = 2
 KKT_WARN_REFINE = 3
@@ -75,6 +76,7 @@ SIGNATURES = {
                                    C.c_double, C.c_double]),
     "kkt_factor_status": (C.c_int, [C.c_void_p, C.POINTER(Inertia)]),
     "kkt_solve_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
+    "kkt_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
     "kkt_solve_status": (C.c_int, [C.c_void_p, C.POINTER(SolveInfo)]),
     "kkt_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     "kkt_batch_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

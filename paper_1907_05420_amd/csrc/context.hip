@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -134,10 +135,12 @@ struct kkt_ctx {
     kkt_kernel_stat kstat{};
     // trailing matrices with at least this many rows use the 128x128 tiles
     int big_rows = 512;
-    // last kkt_solve_async: its right-hand sides, steps and where it left
-    // the norms of the final residual
+    // last kkt_solve_async / kkt_solve_noalloc: its right-hand sides, steps
+    // and where it left the norms of the final residual (the workspace's
+    // norms, or d_snorms, a context-owned buffer for 64 right-hand sides)
     int64_t async_nrhs = 0;
     int async_steps = 0;
+    double *d_snorms = nullptr;
     const double *status_norms = nullptr;
 };
 
@@ -521,6 +524,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
     if ((rc = dalloc(ctx, (void **)&ctx->d_amax, 8 * (ctx->N + 1)))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_cnt, 8 * 4 * (ctx->N + 1)))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_flag, 256))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_snorms, 8 * (4 * 64 + 8)))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_A, 8 * S.nnzA * ctx->N))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_C0, 8 * std::max<int64_t>(S.nnzC0, 1)))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_C1, 8 * std::max<int64_t>(S.nnzC1, 1)))) return rc;
@@ -1359,6 +1363,89 @@ extern "C" int kkt_solve_async(kkt_ctx *ctx, const double *b, double *x, int64_t
         if (rc) return rc;
     }
     return solve_fixed_steps(ctx, b, x, nrhs, steps, ctx->d_norms);
+}
+
+// ---------------------------------------------------------------------------
+// kkt_solve_noalloc: kkt_solve_async with its workspace in a fixed device
+// array instead of memory the context allocates. Each device holds its own
+// copy of the array (from the library's load until the process ends); host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device, never through the array's name.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t SCRATCH_DOUBLES = (int64_t)4 << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_dev[MAX_DEVICES] = {};
+
+// the array's device address on the current device, looked up once per device
+int scratch_base(kkt_ctx *ctx, double **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return KKT_ERR_ARG;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        scratch_dev[dev] = (double *)p;
+    }
+    *out = scratch_dev[dev];
+    return KKT_OK;
+}
+
+struct WsPtrs {
+    double *xp, *uv, *bh, *y, *xg, *res, *dx, *norms, *work;
+};
+WsPtrs save_ws(const kkt_ctx *ctx) {
+    return WsPtrs{ctx->d_xp, ctx->d_uv, ctx->d_bh, ctx->d_y, ctx->d_xg, ctx->d_res, ctx->d_dx, ctx->d_norms, ctx->d_work};
+}
+void restore_ws(kkt_ctx *ctx, const WsPtrs &w) {
+    ctx->d_xp = w.xp;
+    ctx->d_uv = w.uv;
+    ctx->d_bh = w.bh;
+    ctx->d_y = w.y;
+    ctx->d_xg = w.xg;
+    ctx->d_res = w.res;
+    ctx->d_dx = w.dx;
+    ctx->d_norms = w.norms;
+    ctx->d_work = w.work;
+}
+
+}  // namespace
+
+extern "C" int kkt_solve_noalloc(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, int steps) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->analyzed || !ctx->factored) return KKT_ERR_ORDER;
+    if (!b || !x || b == x || nrhs < 1 || nrhs > 64 || steps < 0 || ctx->timing) return KKT_ERR_ARG;
+    const Symbolic &S = ctx->sy;
+    // the workspace of kkt_solve_async, carved from the array in 256-byte
+    // aligned pieces: xp, uv, bh, y, xg, res, dx, work
+    const int64_t count[8] = {(S.nA + S.nbord) * ctx->N * nrhs, S.Usize_vec() * ctx->N * nrhs, ctx->ng * nrhs,
+                              ctx->ng * nrhs, ctx->ng * nrhs, ctx->ntot * nrhs, ctx->ntot * nrhs,
+                              residual_work(ctx->N, S.nA, S.Ns, nrhs)};
+    int64_t off[8], used = 0;
+    for (int q = 0; q < 8; ++q) {
+        off[q] = used;
+        used += (int64_t)(align_up(8 * std::max<int64_t>(count[q], 1)) / 8);
+    }
+    if (used > SCRATCH_DOUBLES) {
+        if (ctx->opt.verbose)
+            std::fprintf(stderr, "kkt_solve_noalloc: needs %lld bytes of workspace, the fixed array holds %lld\n",
+                         (long long)(8 * used), (long long)(8 * SCRATCH_DOUBLES));
+        return KKT_ERR_TOOBIG;
+    }
+    double *base = nullptr;
+    int rc = scratch_base(ctx, &base);
+    if (rc) return rc;
+    const WsPtrs saved = save_ws(ctx);
+    WsPtrs w{base + off[0], base + off[1], base + off[2], base + off[3], base + off[4],
+             base + off[5], base + off[6], ctx->d_snorms, base + off[7]};
+    restore_ws(ctx, w);
+    rc = solve_fixed_steps(ctx, b, x, nrhs, steps, ctx->d_snorms);
+    restore_ws(ctx, saved);
+    return rc;
 }
 
 extern "C" int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info) {

@@ -29,6 +29,7 @@ extern "C" const char *kkt_strerror(int code) {
         case KKT_ERR_STRUCT: return "structural problem in the pattern";
         case KKT_ERR_HIP: return "HIP runtime error";
         case KKT_ERR_NONFINITE: return "non-finite input";
+        case KKT_ERR_TOOBIG: return "workspace larger than the fixed array of kkt_solve_noalloc";
         case KKT_WARN_PERTURBED: return "warning: pivots perturbed";
         case KKT_WARN_INERTIA: return "warning: inertia differs from the expected one";
         case KKT_WARN_REFINE: return "warning: refinement stopped above tolerance";
