@@ -163,7 +163,7 @@ def measure(args, inst, vals2, prec, log, schur_mode=0, steps=None, warmup=None)
     t0 = time.perf_counter()
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
-    s = pk.Solver(inst, precision=prec, schur_mode=schur_mode,
+    s = pk.Solver(inst, precision=prec, schur_mode=schur_mode, dual_wait=args.dual_wait,
                   refine_method=pk.KKT_REFINE_CLASSIC if args.refine == "classic" else pk.KKT_REFINE_FGMRES)
     t_analyze = time.perf_counter() - t0
     st = s.stats()
@@ -191,10 +191,12 @@ def measure(args, inst, vals2, prec, log, schur_mode=0, steps=None, warmup=None)
         log(f"step {i}: {lat[-1]*1e3:.2f} ms rc {rc} info {info}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    st["footprint_after"] = s.footprint()
     s.close()
     lat_ms = np.array(lat) * 1e3
     return dict(value=steps / elapsed, elapsed=elapsed, lat_ms=lat_ms, phases=np.array(phases).mean(0).tolist(),
-                infos=infos, kstats=kstats, rcs=rcs, analyze_ms=t_analyze * 1e3, stats=st)
+                infos=infos, kstats=kstats, rcs=rcs, analyze_ms=t_analyze * 1e3, stats=st,
+                x_last=x.cpu().numpy(), last_set=(steps - 1) % 2)
 
 
 def bench_batch(args, log):
@@ -374,6 +376,8 @@ def main():
     ap.add_argument("--serve-refine", default="tolerance", choices=["tolerance", "fixed"],
                     help="serve: refine every solve to 1e-10, or a fixed number of steps (--refine-steps)")
     ap.add_argument("--refine-steps", type=int, default=3, help="fixed refinement steps of a batch")
+    ap.add_argument("--dual-wait", type=int, default=0,
+                    help="elimination order: primal neighbours a dual waits for (0 = library default)")
     ap.add_argument("--schur", default="both", choices=["both", "dense", "structured"],
                     help="mesh2000_N96: factor S densely (the timed value), by structured block elimination, or "
                          "both (dense timed, structured reported beside it)")
@@ -453,7 +457,18 @@ def main():
                      "flops_per_launch": k_flops / launches if launches else 0.0,
                      "algorithmic_bytes_per_launch": k_bytes / launches if launches else 0.0},
     }
-    if args.schur == "both":
+    if prec == pk.KKT_MIXED:
+        # the same workload on the FP64 path: speed-up and forward error
+        m64 = measure(args, inst, vals2, pk.KKT_FP64, log, schur_mode=main_mode)
+        x64, xm = m64["x_last"], m["x_last"]
+        res["mixed"] = {
+            "fallback_used": [i["fallback_used"] for i in m["infos"]],
+            "fp64_value": m64["value"], "speedup_vs_fp64": m["value"] / m64["value"],
+            "forward_error_vs_fp64": float(np.linalg.norm(xm - x64) / np.linalg.norm(x64))
+            if m["last_set"] == m64["last_set"] else None,
+            "device_bytes": m["stats"]["footprint_after"], "device_bytes_fp64": m64["stats"]["footprint_after"],
+            "dual_wait": args.dual_wait}
+    if args.schur == "both" and prec == pk.KKT_FP64:
         # the same workload with S factored by structured block elimination
         ms = measure(args, inst, vals2, prec, log, schur_mode=pk.KKT_SCHUR_STRUCTURED)
         ps = ms["phases"]

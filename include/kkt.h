@@ -66,7 +66,15 @@ extern "C" {
                      /* refinement residual, FP64 dense Schur factorisation;   */
                      /* the elimination order then postpones every dual until  */
                      /* all its primal neighbours are eliminated (no growth     */
-                     /* from early duals, more fill than the FP64 order)        */
+                     /* from early duals, more fill than the FP64 order).       */
+                     /* FP64 fallback (kkt_factor, kkt_solve): when the FP32    */
+                     /* factor's inertia differs from the expected one or it   */
+                     /* perturbed pivots, or when refinement around it stops   */
+                     /* above refine_tol, the same values are factored in FP64 */
+                     /* (an internal FP64 analysis and factor, allocated on    */
+                     /* first use and counted by kkt_footprint) and solved     */
+                     /* with that factor; kkt_solve_info.fallback_used says so.*/
+                     /* The enqueue-only calls have no fallback.                */
 
 typedef struct kkt_options {
     int precision;      /* KKT_FP64 or KKT_MIXED                              */
@@ -135,7 +143,9 @@ typedef struct kkt_solve_info {
     double rel_res;      /* max over right-hand sides of ||b-Kx||_2/||b||_2,     */
                          /* FP64, on the unscaled K                             */
     double omega;        /* componentwise backward error max_i |r_i|/(|K||x|+|b|)_i */
-    int fallback_used;   /* 1 when the mixed path fell back to FP64 factors     */
+    int fallback_used;   /* 1 when the mixed path solved with FP64 factors of   */
+                         /* the same values (see KKT_MIXED); refine_iters then  */
+                         /* counts the steps of both attempts                  */
     double rel_floor;    /* max over right-hand sides of                        */
                          /* eps || |K||x| + |b| ||_2 / ||b||_2: a bound on the  */
                          /* relative residual that rounding x to FP64 alone can */
@@ -195,9 +205,11 @@ int kkt_plan(const kkt_structure *s, const kkt_options *opt, int64_t nrhs_max,
  * Pivoting is static: a pivot d_k with |d_k| <= tau_k, tau_k = pivot_eps *
  * |a_kk| (the diagonal entry of the matrix being factored; pivot_eps * max|A|
  * when a_kk = 0), keeps its sign and takes magnitude tau_k. Inertia counts
- * the computed pivots before perturbation.
+ * the computed pivots before perturbation. With KKT_MIXED the call always
+ * synchronises to read the FP32 factor's pivot counts, and reports the FP64
+ * factor's inertia when it fell back (see KKT_MIXED).
  * Returns 0, KKT_WARN_PERTURBED or KKT_WARN_INERTIA (warnings only when out
- * is non-NULL), or an error. */
+ * is non-NULL, or on a fallback), or an error. */
 int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals,
                const double *C1_vals, const double *corner_diag,
                double delta_w, double delta_c, kkt_inertia *out);

@@ -142,6 +142,15 @@ struct kkt_ctx {
     int async_steps = 0;
     double *d_snorms = nullptr;
     const double *status_norms = nullptr;
+    // FP64 fallback of the mixed path: a copy of the pattern, an FP64
+    // context created on first use (its own FP64 order and factors), whether
+    // the current values are factored there and the last solve used it
+    std::vector<int64_t> pat_colptr, pat_C0p, pat_C1p;
+    std::vector<int32_t> pat_rowind, pat_C0i, pat_C1i;
+    int64_t pat_n_primal = 0, pat_Ns = 0;
+    kkt_ctx *fb = nullptr;
+    bool fb_factored = false;
+    kkt_inertia fb_inertia{};
 };
 
 namespace {
@@ -957,6 +966,22 @@ extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
     ctx->ntot = s->N * s->nA + ctx->ng;
     int rc = build_device_symbolic(ctx, s);
     if (rc) { free_static(ctx); return rc; }
+    if (ctx->fb) { kkt_destroy(ctx->fb); ctx->fb = nullptr; }
+    ctx->fb_factored = false;
+    if (ctx->opt.precision == KKT_MIXED) {
+        // the pattern, for an FP64 fallback analysis
+        const int64_t nnz = s->A_colptr[s->nA];
+        ctx->pat_colptr.assign(s->A_colptr, s->A_colptr + s->nA + 1);
+        ctx->pat_rowind.assign(s->A_rowind, s->A_rowind + nnz);
+        ctx->pat_n_primal = s->n_primal;
+        ctx->pat_Ns = s->Ns;
+        if (s->Ns > 0) {
+            ctx->pat_C0p.assign(s->C0_rowptr, s->C0_rowptr + s->Ns + 1);
+            ctx->pat_C1p.assign(s->C1_rowptr, s->C1_rowptr + s->Ns + 1);
+            ctx->pat_C0i.assign(s->C0_colind, s->C0_colind + ctx->pat_C0p[s->Ns]);
+            ctx->pat_C1i.assign(s->C1_colind, s->C1_colind + ctx->pat_C1p[s->Ns]);
+        }
+    }
     ctx->analyzed = true;
     return KKT_OK;
 }
@@ -986,6 +1011,7 @@ int plan_device_bytes(const kkt_structure *s, const kkt_options &o, int64_t nrhs
 extern "C" int kkt_footprint(const kkt_ctx *ctx, size_t *bytes) {
     if (!ctx || !bytes) return KKT_ERR_ARG;
     *bytes = ctx->bytes_static + ctx->bytes_ws;
+    if (ctx->fb) *bytes += ctx->fb->bytes_static + ctx->fb->bytes_ws;
     return KKT_OK;
 }
 
@@ -1075,10 +1101,65 @@ int factor_readback(kkt_ctx *ctx, kkt_inertia *out) {
 
 }  // namespace
 
+namespace {
+
+// FP64 factorisation of the context's current values in its fallback
+// context (created, with its own FP64 analysis, on first use)
+int fallback_factor(kkt_ctx *ctx) {
+    if (!ctx->fb) {
+        kkt_options o = ctx->opt;
+        o.precision = KKT_FP64;
+        o.pivot_eps = 0.0;
+        o.dual_wait = 0;
+        kkt_ctx *fb = nullptr;
+        int rc = kkt_create(&fb, ctx->stream, &o);
+        if (rc) return rc;
+        kkt_structure st{};
+        st.nA = ctx->sy.nA;
+        st.n_primal = ctx->pat_n_primal;
+        st.N = ctx->N;
+        st.Ns = ctx->pat_Ns;
+        st.A_colptr = ctx->pat_colptr.data();
+        st.A_rowind = ctx->pat_rowind.data();
+        if (st.Ns > 0) {
+            st.C0_rowptr = ctx->pat_C0p.data();
+            st.C0_colind = ctx->pat_C0i.data();
+            st.C1_rowptr = ctx->pat_C1p.data();
+            st.C1_colind = ctx->pat_C1i.data();
+        }
+        rc = kkt_analyze(fb, &st);
+        if (rc) { kkt_destroy(fb); return rc; }
+        ctx->fb = fb;
+    }
+    ctx->fb->stream = ctx->stream;
+    int rc = kkt_factor(ctx->fb, ctx->d_A, ctx->d_C0, ctx->d_C1, ctx->has_corner ? ctx->d_corner : nullptr, ctx->dw,
+                        ctx->dc, &ctx->fb_inertia);
+    if (rc < 0) return rc;
+    ctx->fb_factored = true;
+    return rc;
+}
+
+}  // namespace
+
 extern "C" int kkt_factor(kkt_ctx *ctx, const double *A_vals, const double *C0_vals, const double *C1_vals,
                           const double *corner_diag, double delta_w, double delta_c, kkt_inertia *out) {
     int rc = factor_enqueue(ctx, A_vals, C0_vals, C1_vals, corner_diag, delta_w, delta_c, true);
     if (rc) return rc;
+    ctx->fb_factored = false;
+    if (ctx->opt.precision == KKT_MIXED) {
+        // An FP32 factor whose inertia differs from the expected one, or that
+        // needed perturbed pivots, cannot be trusted for the inertia test of
+        // the interior point method: the values are factored in FP64 as well
+        // and that factor's inertia is reported (and used by kkt_solve).
+        kkt_inertia in32{};
+        const int rc32 = factor_readback(ctx, &in32);
+        if (rc32 != KKT_OK) {
+            rc = fallback_factor(ctx);
+            if (rc < 0) return rc;
+            if (out) *out = ctx->fb_inertia;
+            return rc;
+        }
+    }
     hipStream_t st = ctx->stream;
     if (ctx->timing) {
         HIPCHK(hipStreamSynchronize(st));
@@ -1281,6 +1362,13 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
     if (!ctx) return KKT_ERR_ARG;
     if (!ctx->analyzed || !ctx->factored) return KKT_ERR_ORDER;
     if (!b || !x || b == x || nrhs < 1 || nrhs > 64) return KKT_ERR_ARG;
+    if (ctx->fb_factored) {
+        // the mixed path's values are factored in FP64 (see kkt_factor)
+        ctx->fb->stream = ctx->stream;
+        int rc = kkt_solve(ctx->fb, b, x, nrhs, info);
+        if (info && rc >= 0) info->fallback_used = 1;
+        return rc;
+    }
     int rc = ensure_ws(ctx, nrhs);
     if (rc) return rc;
     hipStream_t st = ctx->stream;
@@ -1308,6 +1396,21 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
     if (ctx->timing) {
         HIPCHK(hipStreamSynchronize(st));
         ctx->times[3] = elapsed(ctx, 4, 5);
+    }
+    if (mixed && rs.status == KKT_WARN_REFINE) {
+        // refinement around the FP32 factor stopped above the target:
+        // factor the same values in FP64 and solve again with that factor
+        rc = fallback_factor(ctx);
+        if (rc < 0) return rc;
+        kkt_solve_info fi{};
+        rc = kkt_solve(ctx->fb, b, x, nrhs, &fi);
+        if (rc < 0) return rc;
+        if (info) {
+            *info = fi;
+            info->refine_iters += rs.it;
+            info->fallback_used = 1;
+        }
+        return rc;
     }
     if (info) {
         info->refine_iters = rs.it;
@@ -1520,6 +1623,7 @@ extern "C" int kkt_dominant_kernel(kkt_ctx *ctx, kkt_kernel_stat *out) {
 extern "C" void kkt_destroy(kkt_ctx *ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->fb) kkt_destroy(ctx->fb);
     free_ws(ctx);
     free_static(ctx);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
