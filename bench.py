@@ -164,6 +164,7 @@ def measure(args, inst, vals2, prec, log, schur_mode=0, steps=None, warmup=None)
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
     s = pk.Solver(inst, precision=prec, schur_mode=schur_mode, dual_wait=args.dual_wait,
+                  recompute_periods=args.recompute_periods,
                   refine_method=pk.KKT_REFINE_CLASSIC if args.refine == "classic" else pk.KKT_REFINE_FGMRES)
     t_analyze = time.perf_counter() - t0
     st = s.stats()
@@ -376,6 +377,9 @@ def main():
     ap.add_argument("--serve-refine", default="tolerance", choices=["tolerance", "fixed"],
                     help="serve: refine every solve to 1e-10, or a fixed number of steps (--refine-steps)")
     ap.add_argument("--refine-steps", type=int, default=3, help="fixed refinement steps of a batch")
+    ap.add_argument("--recompute-periods", type=int, default=0,
+                    help="hold the factors of this many periods only and recompute them in every solve pass "
+                         "(0 = keep all)")
     ap.add_argument("--dual-wait", type=int, default=0,
                     help="elimination order: primal neighbours a dual waits for (0 = library default)")
     ap.add_argument("--schur", default="both", choices=["both", "dense", "structured"],
@@ -433,8 +437,9 @@ def main():
         "config": {"workload": w["name"], "buses": w["nb"], "lines": w["nlines"], "generators": w["ng"],
                    "storage": w["ns"], "periods": w["N"], "block_rows": inst.n_A, "schur_dim": ng,
                    "nrhs": w["nrhs"], "barrier_range": list(w["barrier"]), "precision": args.precision,
-                   "refine": args.refine,
+                   "refine": args.refine, "recompute_periods": args.recompute_periods,
                    "schur": "structured" if main_mode == pk.KKT_SCHUR_STRUCTURED else "dense"},
+        "device_bytes": m["stats"]["footprint_after"],
         "p50_ms": float(np.percentile(m["lat_ms"], 50)),
         "p99_ms": float(np.percentile(m["lat_ms"], 99)),
         "rel_res": max(i["rel_res"] for i in m["infos"]),

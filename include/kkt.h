@@ -88,6 +88,14 @@ typedef struct kkt_options {
                         /* 128x128 tiles, smaller ones 64x64; 0 = default 512   */
                         /* (a tile-shape knob for autotuning)                   */
     int schur_mode;     /* KKT_SCHUR_DENSE (default) or KKT_SCHUR_STRUCTURED    */
+    int recompute_periods; /* 0 (default): the factors and update matrices of */
+                        /* every period stay in device memory. P > 0: only P  */
+                        /* periods' are held at a time and the period factors */
+                        /* are recomputed, chunk by chunk, before the forward */
+                        /* and the backward sweep of every solve pass (the    */
+                        /* memory-saving variant of section 4.3): about       */
+                        /* N / P times less factor memory, two more block     */
+                        /* factorisations per solve pass                       */
     int dual_wait;      /* elimination order: a dual becomes eligible once     */
                         /* min(dual_wait, its primal neighbours) of its primal */
                         /* neighbours are eliminated and it can claim one of   */

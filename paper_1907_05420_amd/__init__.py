@@ -72,7 +72,7 @@ def _structure(nA, n_primal, N, Ns, colptr, rowind, C0p, C0i, C1p, C1i):
 
 
 def kkt_plan(nA, n_primal, N, Ns, colptr, rowind, C0p=None, C0i=None, C1p=None, C1i=None, precision=KKT_FP64,
-             nrhs_max=1, want_perm=False, schur_mode=KKT_SCHUR_DENSE, dual_wait=0):
+             nrhs_max=1, want_perm=False, schur_mode=KKT_SCHUR_DENSE, dual_wait=0, recompute_periods=0):
     """Host-only symbolic analysis; returns (stats dict, perm or None)."""
     lib = load_library()
     s, keep = _structure(nA, n_primal, N, Ns, colptr, rowind, C0p, C0i, C1p, C1i)
@@ -80,6 +80,7 @@ def kkt_plan(nA, n_primal, N, Ns, colptr, rowind, C0p=None, C0i=None, C1p=None, 
     o.precision = precision
     o.schur_mode = schur_mode
     o.dual_wait = dual_wait
+    o.recompute_periods = recompute_periods
     st = _abi.SymbolicStats()
     perm = np.zeros(nA, np.int32) if want_perm else None
     rc = lib.kkt_plan(C.byref(s), C.byref(o), int(nrhs_max), C.byref(st),
@@ -89,7 +90,7 @@ def kkt_plan(nA, n_primal, N, Ns, colptr, rowind, C0p=None, C0i=None, C1p=None, 
 
 
 def kkt_create(stream=None, precision=KKT_FP64, refine_tol=1e-10, refine_max=20, pivot_eps=0.0, verbose=0,
-               refine_method=KKT_REFINE_FGMRES, big_tile_rows=0, schur_mode=0, dual_wait=0):
+               refine_method=KKT_REFINE_FGMRES, big_tile_rows=0, schur_mode=0, dual_wait=0, recompute_periods=0):
     lib = load_library()
     o = kkt_default_options()
     o.precision, o.refine_tol, o.refine_max, o.pivot_eps, o.verbose = precision, refine_tol, refine_max, pivot_eps, verbose
@@ -97,6 +98,7 @@ def kkt_create(stream=None, precision=KKT_FP64, refine_tol=1e-10, refine_max=20,
     o.big_tile_rows = big_tile_rows
     o.schur_mode = schur_mode
     o.dual_wait = dual_wait
+    o.recompute_periods = recompute_periods
     h = C.c_void_p()
     if stream is None:
         import torch
@@ -244,10 +246,11 @@ class Solver:
     n_primal, N, ns, colptr, rowind, C0_/C1_rowptr/colind)."""
 
     def __init__(self, inst, precision=KKT_FP64, stream=None, refine_tol=1e-10, refine_max=20, pivot_eps=0.0,
-                 verbose=0, refine_method=KKT_REFINE_FGMRES, big_tile_rows=0, schur_mode=0, dual_wait=0):
+                 verbose=0, refine_method=KKT_REFINE_FGMRES, big_tile_rows=0, schur_mode=0, dual_wait=0,
+                 recompute_periods=0):
         self.inst = inst
         self.ctx = kkt_create(stream, precision, refine_tol, refine_max, pivot_eps, verbose, refine_method,
-                              big_tile_rows, schur_mode, dual_wait)
+                              big_tile_rows, schur_mode, dual_wait, recompute_periods)
         kkt_analyze(self.ctx, inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind,
                     inst.C0_rowptr, inst.C0_colind, inst.C1_rowptr, inst.C1_colind)
 

@@ -24,7 +24,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("pivot_eps", C.c_double), ("refine_tol", C.c_double),
                 ("refine_max", C.c_int), ("verbose", C.c_int), ("refine_method", C.c_int),
                 ("big_tile_rows", C.c_int),
-                ("schur_mode", C.c_int), ("dual_wait", C.c_int)]
+                ("schur_mode", C.c_int), ("recompute_periods", C.c_int), ("dual_wait", C.c_int)]
 
 
 class Structure(C.Structure):

@@ -66,6 +66,14 @@ struct kkt_ctx {
     bool analyzed = false, factored = false;
     Symbolic sy;
     int64_t N = 0, ng = 0, ntot = 0;
+    // periods whose factors and update matrices are held at a time: N, or
+    // fewer with recompute_periods (factors recomputed in every solve pass,
+    // the memory-saving variant of section 4.3); the chunk of periods whose
+    // factor the storage holds now (-1: none); the local Schur blocks of
+    // every period, copied out of the update storage chunk by chunk
+    int64_t P = 0;
+    int64_t resident = -1;
+    void *d_sbar = nullptr;
     double eps = 1e-14;
     std::vector<std::pair<void *, size_t>> allocs;  // static allocations
     size_t bytes_static = 0, bytes_ws = 0;
@@ -309,6 +317,20 @@ StepDev step_dev(const StepHost &s, const int32_t *base) {
     return d;
 }
 
+bool recomputes(const kkt_ctx *ctx) { return ctx->opt.recompute_periods > 0; }
+
+// where the local Schur blocks S_bar_n live: the border node's update matrix
+// in each period's update storage, or the copies of the recomputing mode
+struct SbarSrc {
+    const void *p;
+    int64_t stride, off;
+};
+SbarSrc sbar_src(const kkt_ctx *ctx) {
+    const Symbolic &S = ctx->sy;
+    if (recomputes(ctx)) return SbarSrc{ctx->d_sbar, S.nbord * S.nbord, 0};
+    return SbarSrc{ctx->d_U, S.Usize, S.Uoff[S.border_sn]};
+}
+
 TreeArgs tree_args(const kkt_ctx *ctx) {
     TreeArgs t;
     t.cptr = ctx->d_cptr;
@@ -527,11 +549,18 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
     }
     // numeric storage
     const size_t w = ctx->opt.precision == KKT_MIXED ? 4 : 8;
-    if ((rc = dalloc(ctx, &ctx->d_L, w * S.Lsize * ctx->N))) return rc;
-    if ((rc = dalloc(ctx, &ctx->d_U, w * std::max<int64_t>(S.Usize, 1) * ctx->N))) return rc;
-    if ((rc = dalloc(ctx, (void **)&ctx->d_tau, 8 * S.nA * ctx->N))) return rc;
-    if ((rc = dalloc(ctx, (void **)&ctx->d_amax, 8 * (ctx->N + 1)))) return rc;
-    if ((rc = dalloc(ctx, (void **)&ctx->d_cnt, 8 * 4 * (ctx->N + 1)))) return rc;
+    ctx->P = ctx->opt.recompute_periods > 0 ? std::min<int64_t>(ctx->opt.recompute_periods, ctx->N) : ctx->N;
+    ctx->resident = -1;
+    if ((rc = dalloc(ctx, &ctx->d_L, w * S.Lsize * ctx->P))) return rc;
+    if ((rc = dalloc(ctx, &ctx->d_U, w * std::max<int64_t>(S.Usize, 1) * ctx->P))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_tau, 8 * S.nA * ctx->P))) return rc;
+    if ((rc = dalloc(ctx, (void **)&ctx->d_amax, 8 * (ctx->P + 1)))) return rc;
+    // pivot counters of every period, then P more that refactorisations
+    // inside the solves count into (and nobody reads)
+    if ((rc = dalloc(ctx, (void **)&ctx->d_cnt, 8 * 4 * (ctx->N + 1 + ctx->P)))) return rc;
+    if (recomputes(ctx) && ctx->ng > 0 &&
+        (rc = dalloc(ctx, &ctx->d_sbar, w * S.nbord * S.nbord * ctx->N)))
+        return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_flag, 256))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_snorms, 8 * (4 * 64 + 8)))) return rc;
     if ((rc = dalloc(ctx, (void **)&ctx->d_A, 8 * S.nnzA * ctx->N))) return rc;
@@ -648,19 +677,20 @@ void mark(kkt_ctx *ctx, int i) {
     if (ctx->timing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
 }
 
+// numeric factorisation of periods [p0, p0 + np) into the factor storage
+// (which holds np <= P periods), pivot counters at cnt ([np][4])
 template <typename T>
-int factor_blocks(kkt_ctx *ctx) {
+int factor_range(kkt_ctx *ctx, int64_t p0, int64_t np, int64_t *cnt) {
     const Symbolic &S = ctx->sy;
     hipStream_t st = ctx->stream;
     FactorArgs<T> fa = factor_args<T>(ctx);
-    const int64_t N = ctx->N;
-    launch_zero<T>((T *)ctx->d_L, S.Lsize * N, st);
-    launch_zero<T>((T *)ctx->d_U, S.Usize * N, st);
-    launch_zero<double>(ctx->d_tau, S.nA * N, st);
-    launch_zero<double>(ctx->d_amax, N + 1, st);
-    launch_zero<int64_t>(ctx->d_cnt, 4 * (N + 1), st);
+    fa.cnt = cnt;
+    launch_zero<T>((T *)ctx->d_L, S.Lsize * np, st);
+    launch_zero<T>((T *)ctx->d_U, S.Usize * np, st);
+    launch_zero<double>(ctx->d_tau, S.nA * np, st);
+    launch_zero<double>(ctx->d_amax, np + 1, st);
     ScatterArgs sa;
-    sa.A = ctx->d_A;
+    sa.A = ctx->d_A + p0 * S.nnzA;
     sa.nnz = S.nnzA;
     sa.amap = ctx->d_amap;
     sa.adiag = ctx->d_adiag;
@@ -673,13 +703,34 @@ int factor_blocks(kkt_ctx *ctx) {
     sa.n1 = S.nnzC1;
     sa.c0map = ctx->d_c0map;
     sa.c1map = ctx->d_c1map;
-    launch_scatter<T>(sa, fa, N, st);
+    launch_scatter<T>(sa, fa, np, st);
     TreeArgs tr = tree_args(ctx);
     for (const LevelPlan &lp : ctx->levels) {
-        launch_small_fronts<T>(fa, ctx->d_sd, ctx->d_tasks + lp.small_off, lp.nsmall_cls, N, tr, st);
-        launch_extend_add<T>(fa, ctx->d_sd, (const RowTask *)(ctx->d_tasks + lp.ea_off), lp.nea, N, tr, st);
+        launch_small_fronts<T>(fa, ctx->d_sd, ctx->d_tasks + lp.small_off, lp.nsmall_cls, np, tr, st);
+        launch_extend_add<T>(fa, ctx->d_sd, (const RowTask *)(ctx->d_tasks + lp.ea_off), lp.nea, np, tr, st);
         for (int q = lp.step_begin; q < lp.step_end; ++q)
-            launch_step<T>(fa, ctx->d_sd, step_dev(ctx->steps[q], ctx->d_tasks), N, st);
+            launch_step<T>(fa, ctx->d_sd, step_dev(ctx->steps[q], ctx->d_tasks), np, st);
+    }
+    return KKT_OK;
+}
+
+// the factorisation of every period; with recompute_periods chunk by chunk,
+// each chunk's local Schur blocks copied out of the update storage
+template <typename T>
+int factor_blocks(kkt_ctx *ctx) {
+    const Symbolic &S = ctx->sy;
+    launch_zero<int64_t>(ctx->d_cnt, 4 * (ctx->N + 1 + ctx->P), ctx->stream);
+    for (int64_t p0 = 0; p0 < ctx->N; p0 += ctx->P) {
+        const int64_t np = std::min(ctx->P, ctx->N - p0);
+        int rc = factor_range<T>(ctx, p0, np, ctx->d_cnt + 4 * p0);
+        if (rc) return rc;
+        if (recomputes(ctx) && ctx->ng > 0) {
+            const size_t ub = S.nbord * S.nbord * sizeof(T);
+            HIPCHK(hipMemcpy2DAsync((T *)ctx->d_sbar + p0 * S.nbord * S.nbord, ub,
+                                    (const T *)ctx->d_U + S.Uoff[S.border_sn], S.Usize * sizeof(T), ub, np,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        ctx->resident = p0 / ctx->P;
     }
     return KKT_OK;
 }
@@ -690,9 +741,10 @@ int factor_blocks(kkt_ctx *ctx) {
 int factor_schur_structured(kkt_ctx *ctx) {
     hipStream_t st = ctx->stream;
     const Symbolic &S = ctx->sy;
-    const int64_t uoff = S.Uoff[S.border_sn], ns = S.Ns, N = ctx->N;
+    const int64_t ns = S.Ns, N = ctx->N;
     const double *corner = ctx->has_corner ? ctx->d_corner : nullptr;
-    launch_struct_tau(ctx->d_U, S.Usize, uoff, N, ns, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_tauS, ctx->eps,
+    const SbarSrc sb = sbar_src(ctx);
+    launch_struct_tau(sb.p, sb.stride, sb.off, N, ns, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_tauS, ctx->eps,
                       ctx->d_amaxS, st);
     mark(ctx, 2);
     // U_j and front j's update block (which holds -B_j A_j^-1 B_j^T) live in
@@ -705,7 +757,7 @@ int factor_schur_structured(kkt_ctx *ctx) {
         const int last = j + 1 == N ? 1 : 0;
         const int64_t cur = (j & 1) * ns * ns, prev = ((j + 1) & 1) * ns * ns;
         double *Fj = ctx->d_sfront + j * 2 * ns * ns;
-        launch_struct_front(ctx->d_U, S.Usize, uoff, ns, j, last, ctx->opt.precision, ctx->d_prefix, corner,
+        launch_struct_front(sb.p, sb.stride, sb.off, ns, j, last, ctx->opt.precision, ctx->d_prefix, corner,
                             ctx->d_sU + prev, ctx->d_sUb + prev, ctx->d_sU + cur, Fj, ctx->d_sUb + cur, st);
         fa.L = Fj;
         fa.U = ctx->d_sUb + cur;
@@ -734,15 +786,15 @@ int factor_schur(kkt_ctx *ctx) {
     if (ctx->ng == 0) return KKT_OK;
     hipStream_t st = ctx->stream;
     const Symbolic &S = ctx->sy;
-    const int64_t uoff = S.Uoff[S.border_sn];
+    const SbarSrc sb = sbar_src(ctx);
     launch_zero<double>(ctx->d_amaxS, 1, st);
     launch_zero<int64_t>(ctx->d_cntS, 4, st);
     if (ctx->structured) {
-        launch_schur_prefix(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
+        launch_schur_prefix(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
         return factor_schur_structured(ctx);
     }
-    launch_schur_prefix(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
-    launch_schur_assemble(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
+    launch_schur_prefix(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
+    launch_schur_assemble(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
                           ctx->has_corner ? ctx->d_corner : nullptr, ctx->d_S, ctx->d_tauS, ctx->eps,
                           ctx->d_amaxS, 0, st);
     mark(ctx, 2);
@@ -794,7 +846,11 @@ int factor_schur(kkt_ctx *ctx) {
 }
 
 // one pass of Algorithm 1's solve for the right-hand sides in `b` (device,
-// [nrhs][ntot]) into `x`
+// [nrhs][ntot]) into `x`. With recompute_periods the factor storage holds one
+// chunk of periods at a time: every chunk is factored again before its
+// forward sweep and before its backward sweep (the memory-saving variant of
+// section 4.3, which recomputes the period factors in the solve steps),
+// starting each sweep with the chunk that is still resident.
 template <typename T>
 int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
     const Symbolic &S = ctx->sy;
@@ -823,7 +879,36 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
         lt.maxc = lp.maxc_large;
         return lt;
     };
-    for (const LevelPlan &lp : ctx->levels) launch_fwd_level<T>(L, S.Lsize, ctx->d_sd, tasks_of(lp), tr, sa, st);
+    // the chunks of periods, the resident one first; each made resident
+    const int64_t nch = (ctx->N + ctx->P - 1) / ctx->P;
+    auto chunk_order = [&]() {
+        std::vector<int64_t> ord;
+        if (ctx->resident >= 0) ord.push_back(ctx->resident);
+        for (int64_t c = 0; c < nch; ++c)
+            if (c != ctx->resident) ord.push_back(c);
+        return ord;
+    };
+    auto make_resident = [&](int64_t c) -> int {
+        if (ctx->resident == c) return KKT_OK;
+        const int64_t p0 = c * ctx->P;
+        int rc = factor_range<T>(ctx, p0, std::min(ctx->P, ctx->N - p0), ctx->d_cnt + 4 * (ctx->N + 1));
+        ctx->resident = c;
+        return rc;
+    };
+    auto chunk_args = [&](int64_t c) {
+        SolveArgs sc = sa;
+        const int64_t p0 = c * ctx->P;
+        sc.N = std::min(ctx->P, ctx->N - p0);
+        sc.xp = sa.xp + p0 * nrhs * sa.nv;
+        sc.uv = sa.uv + p0 * nrhs * sa.usz;
+        return sc;
+    };
+    for (int64_t c : chunk_order()) {
+        int rc = make_resident(c);
+        if (rc) return rc;
+        const SolveArgs sc = chunk_args(c);
+        for (const LevelPlan &lp : ctx->levels) launch_fwd_level<T>(L, S.Lsize, ctx->d_sd, tasks_of(lp), tr, sc, st);
+    }
     if (ctx->ng > 0) {
         launch_schur_rhs(b, ctx->ntot, S.nA, sa, S.Ns, S.relptr[S.border_sn], ctx->d_bh, st);
         if (ctx->structured) {
@@ -835,9 +920,14 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
         }
         launch_border_values(ctx->d_xg, sa, S.nA, S.Ns, st);
     }
-    for (int l = (int)ctx->levels.size() - 1; l >= 0; --l) {
-        const LevelPlan &lp = ctx->levels[l];
-        launch_bwd_level<T>(L, S.Lsize, ctx->d_sd, tasks_of(lp), tr, sa, st);
+    for (int64_t c : chunk_order()) {
+        int rc = make_resident(c);
+        if (rc) return rc;
+        const SolveArgs sc = chunk_args(c);
+        for (int l = (int)ctx->levels.size() - 1; l >= 0; --l) {
+            const LevelPlan &lp = ctx->levels[l];
+            launch_bwd_level<T>(L, S.Lsize, ctx->d_sd, tasks_of(lp), tr, sc, st);
+        }
     }
     launch_scatter_x(x, ctx->ntot, S.nA, ctx->d_perm, sa, ctx->d_xg, ctx->ng, st);
     return KKT_OK;
@@ -897,7 +987,10 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     if (opt) ctx->opt = *opt;
     if (ctx->opt.precision != KKT_FP64 && ctx->opt.precision != KKT_MIXED) { delete ctx; return KKT_ERR_ARG; }
     if (ctx->opt.refine_tol <= 0) ctx->opt.refine_tol = 1e-10;
-    if (ctx->opt.big_tile_rows < 0) { delete ctx; return KKT_ERR_ARG; }
+    if (ctx->opt.big_tile_rows < 0 || ctx->opt.recompute_periods < 0 || ctx->opt.dual_wait < 0) {
+        delete ctx;
+        return KKT_ERR_ARG;
+    }
     if (ctx->opt.schur_mode != KKT_SCHUR_DENSE && ctx->opt.schur_mode != KKT_SCHUR_STRUCTURED) {
         delete ctx;
         return KKT_ERR_ARG;
@@ -1584,9 +1677,9 @@ extern "C" int kkt_schur(kkt_ctx *ctx, double *S_out) {
     if (!ctx->factored) return KKT_ERR_ORDER;
     if (ctx->ng == 0) return KKT_OK;
     const Symbolic &S = ctx->sy;
-    const int64_t uoff = S.Uoff[S.border_sn];
-    launch_schur_prefix(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, ctx->stream);
-    launch_schur_assemble(ctx->d_U, S.Usize, uoff, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
+    const SbarSrc sb = sbar_src(ctx);
+    launch_schur_prefix(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, ctx->stream);
+    launch_schur_assemble(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
                           ctx->has_corner ? ctx->d_corner : nullptr, S_out, nullptr, 0.0, nullptr, 1, ctx->stream);
     HIPCHK(hipGetLastError());
     return KKT_OK;
@@ -1597,7 +1690,8 @@ extern "C" int kkt_schur_blocks(kkt_ctx *ctx, double *out) {
     if (!ctx->factored) return KKT_ERR_ORDER;
     if (ctx->ng == 0) return KKT_OK;
     const Symbolic &S = ctx->sy;
-    launch_copy_sbar(ctx->d_U, S.Usize, S.Uoff[S.border_sn], ctx->N, S.nbord, ctx->opt.precision, out, ctx->stream);
+    const SbarSrc sb = sbar_src(ctx);
+    launch_copy_sbar(sb.p, sb.stride, sb.off, ctx->N, S.nbord, ctx->opt.precision, out, ctx->stream);
     HIPCHK(hipGetLastError());
     return KKT_OK;
 }

@@ -17,6 +17,7 @@ extern "C" void kkt_default_options(kkt_options *opt) {
     opt->refine_method = KKT_REFINE_FGMRES;
     opt->big_tile_rows = 0;
     opt->schur_mode = KKT_SCHUR_DENSE;
+    opt->recompute_periods = 0;
     opt->dual_wait = 0;
 }
 

@@ -383,3 +383,37 @@ def test_parity_structured_wide_border():
         assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == expect, (mode, inn)
         assert inn["n_perturbed"] == 0
     assert _rel(xs[pk.KKT_SCHUR_STRUCTURED], xs[pk.KKT_SCHUR_DENSE]) <= 1e-9
+
+
+@pytest.mark.parametrize("case", [SMALL[1], SMALL[5], SMALL[6], SMALL[11]])
+@pytest.mark.parametrize("schur_mode", [0, 1])
+def test_recompute_periods_equals_stored(case, schur_mode):
+    """The memory-saving variant (section 4.3): with the factors of only P
+    periods held and recomputed in every solve pass, the solution, the
+    inertia, S and the local Schur blocks equal those of the stored-factor
+    path bit for bit (each period's arithmetic is the same), and the
+    context holds less device memory; the planning query agrees."""
+    import paper_1907_05420_amd as pk
+    inst = kktgen.make_small(barrier_range=(1e-2, 1e2), **case)
+    d = pk.device_inputs(inst)
+    out = {}
+    for P in (0, 1, 2):
+        s = pk.Solver(inst, schur_mode=schur_mode, recompute_periods=P)
+        _, inn = s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
+        x, rc, info = s.solve(d["b"])
+        sb = s.schur_blocks().cpu().numpy() if inst.n_g else None
+        st, _ = pk.kkt_plan(inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind, inst.C0_rowptr,
+                            inst.C0_colind, inst.C1_rowptr, inst.C1_colind, nrhs_max=inst.b.shape[0],
+                            schur_mode=schur_mode, recompute_periods=P)
+        out[P] = (x.cpu().numpy(), inn, info, sb, s.footprint(), st["device_bytes"])
+        s.close()
+    x0, inn0, info0, sb0, f0, _ = out[0]
+    for P in (1, 2):
+        x, inn, info, sb, f, fplan = out[P]
+        assert np.array_equal(x, x0), P
+        assert inn == inn0 and info["refine_iters"] == info0["refine_iters"]
+        if sb0 is not None:
+            assert np.array_equal(sb, sb0)
+        assert f == fplan and f < f0, (P, f, f0)
+    K = ah.assemble(inst)
+    assert ah.rel_residual_ld(inst, out[1][0], inst.b, K) <= 1e-10
