@@ -148,8 +148,12 @@ class Instance:
         return int(self.b.shape[0])
 
 
-def _var_index(nb, ng, ns):
-    n_primal = 2 * nb + 2 * ng + 2 * ns
+def _var_index(nb, ng, ns, n_flow=0, n_keep=0):
+    """Row indices of every variable group of one period block:
+    x = (theta, V, Pg, Qg, Psd, Psc), the kept slacks, then the duals
+    lambda_E = (lamP, lamQ) and lambda_I (n_flow line-flow rows)."""
+    n_x = 2 * nb + 2 * ng + 2 * ns
+    n_primal = n_x + n_keep
     idx = dict(
         theta=np.arange(nb),
         V=nb + np.arange(nb),
@@ -157,19 +161,35 @@ def _var_index(nb, ng, ns):
         Qg=2 * nb + ng + np.arange(ng),
         Psd=2 * nb + 2 * ng + np.arange(ns),
         Psc=2 * nb + 2 * ng + ns + np.arange(ns),
+        slack=n_x + np.arange(n_keep),
         lamP=n_primal + np.arange(nb),
         lamQ=n_primal + nb + np.arange(nb),
+        lamI=n_primal + 2 * nb + np.arange(n_flow),
     )
-    return idx, n_primal, n_primal + 2 * nb
+    return idx, n_primal, n_primal + 2 * nb + n_flow
 
 
-def block_pattern(nb, lines, gen_bus, sto_bus):
+def block_pattern(nb, lines, gen_bus, sto_bus, line_flow=False, keep=None):
     """Lower-triangular CSC pattern of one period block and the role of every
     entry. Returns (n_A, n_primal, colptr, rowind, kind) where kind[k] is
     0 = Hessian (theta,V) off-diagonal, 1 = Hessian (theta,V) diagonal,
-    2 = barrier-only diagonal (gen / storage), 3 = Jacobian, 4 = dual diagonal."""
+    2 = barrier-only diagonal (gen / storage), 3 = Jacobian, 4 = dual diagonal,
+    5 = kept slack diagonal (L_s), 6 = kept slack link (-1).
+
+    With line_flow, every line l = (f, t) has two flow-limit rows in J_I (the
+    flow at its f end, then the flow at its t end; all f-end rows first, in
+    line order), each touching (theta_f, theta_t, V_f, V_t) (section 3.1's
+    line-flow constraints, pattern of Fig. KKTsystemOPF), with a slack each
+    (c_I(x) - s = 0, section 2). keep[j] (bool per flow row) keeps slack j as
+    a primal row of the block, linked to its flow row by -1 (Eq.
+    SCOPFhessianSymmetric); the other slacks are eliminated (Eq.
+    SCOPFhessianReduced) and only their flow row's diagonal stays."""
     ng, ns = len(gen_bus), len(sto_bus)
-    idx, n_primal, n_A = _var_index(nb, ng, ns)
+    n_flow = 2 * len(lines) if line_flow else 0
+    keep = np.zeros(n_flow, bool) if keep is None else np.asarray(keep, bool)
+    assert keep.shape == (n_flow,)
+    kept = np.nonzero(keep)[0]
+    idx, n_primal, n_A = _var_index(nb, ng, ns, n_flow, len(kept))
     th, V = idx["theta"], idx["V"]
     ents = {}
 
@@ -212,6 +232,17 @@ def block_pattern(nb, lines, gen_bus, sto_bus):
     for s, k in enumerate(sto_bus):
         put(idx["lamP"][k], idx["Psd"][s], 3)
         put(idx["lamP"][k], idx["Psc"][s], 3)
+    if line_flow:
+        nl = len(lines)
+        for end in range(2):
+            for l, (f, t) in enumerate(lines):
+                r = idx["lamI"][end * nl + l]
+                for u in (th[f], th[t], V[f], V[t]):
+                    put(r, u, 3)
+                put(r, r, 4)
+        for q, j in enumerate(kept):
+            put(idx["slack"][q], idx["slack"][q], 5)
+            put(idx["lamI"][j], idx["slack"][q], 6)
     keys = sorted(ents.keys(), key=lambda ij: (ij[1], ij[0]))
     rows = np.array([ij[0] for ij in keys], dtype=np.int32)
     cols = np.array([ij[1] for ij in keys], dtype=np.int64)
@@ -251,6 +282,16 @@ def draw_values(n_A, colptr, rowind, kind, N, rng, barrier_range, dual_reg=DUAL_
     return vals
 
 
+def draw_slacks(n_flow, N, rng, ls_range, keep_below):
+    """L_s = S^-1 Y of every line-flow slack and period, log-uniform in
+    ls_range; a slack whose L_s falls below keep_below in any period is kept
+    in the block (the reduction needs L_s away from zero, section 2.1)."""
+    lo, hi = ls_range
+    Ls = np.exp(rng.uniform(math.log(lo), math.log(hi), size=(N, n_flow)))
+    keep = (Ls < keep_below).any(axis=0)
+    return Ls, keep
+
+
 def redraw_barrier(inst: "Instance", rng: np.random.Generator, barrier_range=None) -> np.ndarray:
     """New values with only the barrier diagonal re-drawn (an IPM-like
     iteration that keeps the pattern, the Hessian off-diagonals and Jacobian)."""
@@ -285,14 +326,36 @@ def storage_coupling(nb, ng, ns, rng):
 
 
 def make_instance(nb, lines, ng, ns, N, nrhs, seed, barrier_range=(1e-6, 1e6),
-                  corner="diag", rng=None, gen_bus=None, sto_bus=None) -> Instance:
+                  corner="diag", rng=None, gen_bus=None, sto_bus=None, line_flow=False, ls_range=None,
+                  keep_below=1e-3) -> Instance:
+    """One instance. With line_flow the blocks carry the line-flow rows and
+    their slacks (block_pattern): slacks whose L_s falls below keep_below in
+    some period stay in the block, the others are eliminated and described
+    by inst.slack: lam_row (the flow row of A_n each one is linked to by
+    -1), Ls [N, n_elim] and rs [nrhs, N * n_elim] (their right-hand sides,
+    period-major)."""
     rng = rng if rng is not None else np.random.default_rng(seed)
     if gen_bus is None:
         gen_bus = np.sort(rng.choice(nb, size=ng, replace=False)).astype(np.int64)
     if sto_bus is None:
         sto_bus = np.sort(rng.choice(nb, size=ns, replace=False)).astype(np.int64)
-    n_A, n_primal, colptr, rowind, kind = block_pattern(nb, lines, gen_bus, sto_bus)
+    keep = Ls = None
+    if line_flow:
+        Ls, keep = draw_slacks(2 * len(lines), N, rng, ls_range or barrier_range, keep_below)
+    n_A, n_primal, colptr, rowind, kind = block_pattern(nb, lines, gen_bus, sto_bus, line_flow, keep)
     vals = draw_values(n_A, colptr, rowind, kind, N, rng, barrier_range)
+    slack = None
+    if line_flow:
+        idx, _, _ = _var_index(nb, ng, ns, 2 * len(lines), int(keep.sum()))
+        cols = np.repeat(np.arange(n_A), np.diff(colptr))
+        kept = np.nonzero(keep)[0]
+        for q, j in enumerate(kept):      # kept slack q: diagonal L_s, link -1
+            d = np.nonzero((kind == 5) & (cols == idx["slack"][q]))[0]
+            vals[:, d] = Ls[:, j][:, None]
+        vals[:, kind == 6] = -1.0
+        elim = np.nonzero(~keep)[0]
+        slack = dict(lam_row=idx["lamI"][elim].astype(np.int32), Ls=np.ascontiguousarray(Ls[:, elim]),
+                     keep=keep)
     c0p, c0i, c0v, c1p, c1i, c1v = storage_coupling(nb, ng, ns, rng)
     n_g = N * ns
     if corner == "diag":
@@ -302,12 +365,14 @@ def make_instance(nb, lines, ng, ns, N, nrhs, seed, barrier_range=(1e-6, 1e6),
     else:
         raise ValueError(corner)
     b = rng.standard_normal((nrhs, N * n_A + n_g))
+    if slack is not None:
+        slack["rs"] = rng.standard_normal((nrhs, N * len(slack["lam_row"])))
     return Instance(nb=nb, ng=ng, ns=ns, N=N, lines=lines, gen_bus=gen_bus, sto_bus=sto_bus,
                     n_A=n_A, n_primal=n_primal, colptr=colptr, rowind=rowind, vals=vals,
                     C0_rowptr=c0p, C0_colind=c0i, C0_vals=c0v,
                     C1_rowptr=c1p, C1_colind=c1i, C1_vals=c1v,
                     corner_diag=corner_diag, b=b, barrier_range=barrier_range,
-                    meta=dict(kind=kind, seed=seed))
+                    meta=dict(kind=kind, seed=seed, slack=slack))
 
 
 # ----------------------------------------------------------------------------
@@ -341,7 +406,7 @@ def make_workload(cfg: int, rep: int = 0, N=None, nrhs=None, corner="diag", barr
 
 
 def make_small(nb=12, nextra=6, ng=3, ns=2, N=3, nrhs=1, seed=0, barrier_range=(1e-6, 1e6),
-               corner="diag", topo="tree") -> Instance:
+               corner="diag", topo="tree", line_flow=False, ls_range=None, keep_below=1e-3) -> Instance:
     """A tiny instance for brute-force checks."""
     rng = np.random.default_rng(seed)
     if topo == "ring":
@@ -349,7 +414,7 @@ def make_small(nb=12, nextra=6, ng=3, ns=2, N=3, nrhs=1, seed=0, barrier_range=(
     else:
         lines = tree_with_chords(nb, nb - 1 + nextra, rng)
     return make_instance(nb, lines, ng, ns, N, nrhs, seed, barrier_range=barrier_range,
-                         corner=corner, rng=rng)
+                         corner=corner, rng=rng, line_flow=line_flow, ls_range=ls_range, keep_below=keep_below)
 
 
 def uneven_batch(count=64, seed=None, nb_range=(118, 3000), horizons=(12, 24, 48, 96), nrhs=1,

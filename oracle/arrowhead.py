@@ -135,3 +135,57 @@ def backward_error(inst, x, b, K=None):
     with np.errstate(divide="ignore", invalid="ignore"):
         w = np.where(den > 0, np.abs(r) / den, 0.0)
     return float(np.max(w))
+
+
+# ----------------------------------------------------------------------------
+# line-flow slacks (section 2.1, Eqs. SCOPFslackAtEnd, SCOPFhessianReduced,
+# SCOPFslackReduction)
+# ----------------------------------------------------------------------------
+
+def assemble_unreduced(inst) -> sp.csr_matrix:
+    """K with the eliminated slacks put back: order (u_1..u_N, u_g, s_1..s_N)
+    (slacks last, as in Eq. SCOPFslackAtEnd). Slack j of period n has the
+    diagonal L_s[n, j] and the entry -1 linking it to its flow row
+    lam_row[j] of A_n."""
+    sl = inst.meta["slack"]
+    K = assemble(inst)
+    N, nA, ne = inst.N, inst.n_A, len(sl["lam_row"])
+    rows = (np.arange(N)[:, None] * nA + sl["lam_row"][None, :]).ravel()
+    E = sp.csr_matrix((-np.ones(N * ne), (rows, np.arange(N * ne))), shape=(K.shape[0], N * ne))
+    Ls = sp.diags(sl["Ls"].ravel())
+    return sp.bmat([[K, E], [E.T, Ls]], format="csr")
+
+
+def rhs_unreduced(inst) -> np.ndarray:
+    """[b, r_s]: the right-hand sides of the unreduced system."""
+    return np.concatenate([inst.b, inst.meta["slack"]["rs"]], axis=1)
+
+
+def reduce_slacks(inst):
+    """The reduced system of Eq. SCOPFhessianReduced: eliminating slack j
+    (row  -lambda_I,j + L_s,j s_j = r_j) subtracts 1/L_s,j from the diagonal
+    of its flow row and adds r_j / L_s,j to that row's right-hand side.
+    Returns a copy of inst with those values and right-hand sides."""
+    import copy
+    sl = inst.meta["slack"]
+    out = copy.copy(inst)
+    vals = inst.vals.copy()
+    b = inst.b.copy()
+    N, nA, ne = inst.N, inst.n_A, len(sl["lam_row"])
+    diag_pos = inst.colptr[sl["lam_row"]]           # the diagonal leads its column
+    vals[:, diag_pos] -= 1.0 / sl["Ls"]
+    rs = sl["rs"].reshape(-1, N, ne)
+    for n in range(N):
+        b[:, n * nA + sl["lam_row"]] += rs[:, n, :] / sl["Ls"][n]
+    out.vals, out.b = vals, b
+    return out
+
+
+def recover_slacks(inst, x) -> np.ndarray:
+    """Eq. SCOPFslackReduction: L_s,j s_j = r_j + lambda_I,j, from the solution
+    x of the reduced system. Returns [nrhs, N * n_elim]."""
+    sl = inst.meta["slack"]
+    x = np.atleast_2d(x)
+    N, nA, ne = inst.N, inst.n_A, len(sl["lam_row"])
+    lam = np.stack([x[:, n * nA + sl["lam_row"]] for n in range(N)], axis=1)   # [nrhs, N, ne]
+    return ((sl["rs"].reshape(-1, N, ne) + lam) / sl["Ls"][None]).reshape(x.shape[0], N * ne)

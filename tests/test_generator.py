@@ -90,3 +90,53 @@ def test_seeded_determinism():
     assert np.array_equal(a.vals, b.vals) and np.array_equal(a.b, b.b)
     c = kktgen.make_workload(1, rep=1)
     assert not np.array_equal(a.vals, c.vals)
+
+
+
+def _paper_lines_in_order(s):
+    """Lines in the order of the printed flow rows 61..69 (one per line, its
+    (theta_f, theta_t) columns), from-bus first as printed."""
+    out = []
+    for r in range(61, 70):
+        th = sorted(b for a, b in s if a == r and b <= 9)
+        out.append((th[0] - 1, th[1] - 1))
+    return out
+
+
+def test_line_flow_slacks_reproduce_printed_opf_kkt():
+    """With the line-flow rows and every slack kept in the block, the
+    generator's pattern is the printed 78 x 78 one entry for entry (576
+    nonzeros: x, slacks, lambda_E, lambda_I in the order of Eq.
+    SCOPFhessianSymmetric); with every slack eliminated (Eq.
+    SCOPFhessianReduced) it is the printed one without the slack rows and
+    columns: 522 nonzeros, the count the figure prints for the reduced
+    60 x 60 system. Moving the slacks last (Eq. SCOPFslackAtEnd) keeps 576."""
+    s = _paper_pattern()
+    lines = np.array(_paper_lines_in_order(s))
+    gen_bus = []
+    for g in range(3):
+        gen_bus.append([a for a, b in s if b == 19 + g and 43 <= a <= 51][0] - 43)
+    nb = 9
+
+    def ours(keep):
+        n_A, n_primal, colptr, rowind, kind = kktgen.block_pattern(nb, lines, np.array(gen_bus),
+                                                                    np.array([], dtype=np.int64), True, keep)
+        cols = np.repeat(np.arange(n_A), np.diff(colptr))
+        e = set()
+        for i, j in zip(rowind.tolist(), cols.tolist()):
+            e.add((i + 1, j + 1))
+            e.add((j + 1, i + 1))
+        return n_A, n_primal, e
+
+    n_A, n_primal, full = ours(np.ones(18, bool))
+    assert (n_A, n_primal) == (78, 42)
+    assert full == s and len(full) == 576
+    n_A, n_primal, red = ours(np.zeros(18, bool))
+    assert (n_A, n_primal) == (60, 24)
+    renum = lambda p: p if p <= 24 else p - 18
+    printed_red = {(renum(a), renum(b)) for a, b in s if not (25 <= a <= 42 or 25 <= b <= 42)}
+    assert red == printed_red and len(red) == 522
+    # slacks last: a symmetric permutation keeps the count
+    perm = list(range(1, 25)) + list(range(43, 79)) + list(range(25, 43))
+    pos = {p: q + 1 for q, p in enumerate(perm)}
+    assert len({(pos[a], pos[b]) for a, b in s}) == 576

@@ -386,6 +386,48 @@ def test_residual_ld_matches_exact_rational():
 
 
 # --------------------------------------------------------------------------
+# line-flow slacks: reduction and recovery (Eqs. SCOPFhessianReduced,
+# SCOPFslackReduction) against the unreduced system (Eq. SCOPFslackAtEnd)
+# --------------------------------------------------------------------------
+
+SLACK_CASES = [dict(nb=8, nextra=3, ng=2, ns=2, N=3, nrhs=2, seed=31),
+               dict(nb=12, nextra=6, ng=3, ns=0, N=2, nrhs=1, seed=32),
+               dict(nb=10, nextra=5, ng=2, ns=1, N=4, nrhs=1, seed=33)]
+
+
+def _slack_inst(case):
+    return kktgen.make_small(barrier_range=(1e-2, 1e2), line_flow=True, ls_range=(1e-4, 1e2), keep_below=1e-3,
+                             **case)
+
+
+def pin_slack_reduction(inst):
+    """Reduce (Eq. SCOPFhessianReduced), solve the reduced system by Algorithm
+    1, recover the slacks (Eq. SCOPFslackReduction): the result is the LAPACK
+    solution of the unreduced system (slacks last), entry for entry; the
+    unreduced K has the inertia the IPM expects with the eliminated slacks
+    counted as primal, i.e. the reduced inertia plus N n_elim positive."""
+    red = ah.reduce_slacks(inst)
+    out = sc.algorithm1(red)
+    s_rec = ah.recover_slacks(red, out["x"])
+    Kf = ah.assemble_unreduced(inst).toarray()
+    full = np.linalg.solve(Kf, ah.rhs_unreduced(inst).T).T
+    got = np.concatenate([out["x"], s_rec], axis=1)
+    assert _rel(got, full) < 1e-10, _rel(got, full)
+    ne = len(inst.meta["slack"]["lam_row"])
+    expect_red = (inst.N * inst.n_primal, inst.N * (inst.n_A - inst.n_primal) + inst.n_g, 0)
+    assert out["inertia"] == expect_red
+    assert inertia_eig(Kf) == (expect_red[0] + inst.N * ne, expect_red[1], 0)
+
+
+@pytest.mark.parametrize("case", SLACK_CASES)
+def test_slack_reduction_equals_unreduced_solve(case):
+    inst = _slack_inst(case)
+    sl = inst.meta["slack"]
+    assert sl["keep"].any() and (~sl["keep"]).any()      # both kinds of slack present
+    pin_slack_reduction(inst)
+
+
+# --------------------------------------------------------------------------
 # planted mistakes: each must be caught by at least one pin
 # --------------------------------------------------------------------------
 
@@ -481,7 +523,32 @@ def _mut_residual_ld_fp64(monkeypatch):
     monkeypatch.setattr(ah, "rel_residual_ld", wrong)
 
 
-MUTANTS = [_mut_swap_c0_c1, _mut_border_transposed_periods, _mut_schur_sign, _mut_drop_s00,
+def _mut_slack_recovery_sign(monkeypatch):
+    orig = ah.recover_slacks
+
+    def wrong(inst, x):               # L_s s = r - lambda_I (sign of the multiplier flipped)
+        sl = inst.meta["slack"]
+        N, nA, ne = inst.N, inst.n_A, len(sl["lam_row"])
+        lam = np.stack([np.atleast_2d(x)[:, n * nA + sl["lam_row"]] for n in range(N)], axis=1)
+        return ((sl["rs"].reshape(-1, N, ne) - lam) / sl["Ls"][None]).reshape(-1, N * ne)
+    monkeypatch.setattr(ah, "recover_slacks", wrong)
+
+
+def _mut_slack_reduce_rhs(monkeypatch):
+    orig = ah.reduce_slacks
+
+    def wrong(inst):                  # right-hand side not reduced
+        out = orig(inst)
+        out.b = inst.b.copy()
+        return out
+    monkeypatch.setattr(ah, "reduce_slacks", wrong)
+
+
+def _pin_slack_first_case(inst=None):
+    pin_slack_reduction(_slack_inst(SLACK_CASES[0]))
+
+
+MUTANTS = [_mut_slack_recovery_sign, _mut_slack_reduce_rhs, _mut_swap_c0_c1, _mut_border_transposed_periods, _mut_schur_sign, _mut_drop_s00,
            _mut_local_solve_sign, _mut_ldlt_update, _mut_block_doubled_diagonal, _mut_corner_sign,
            _mut_inertia_sign, _mut_backward_error_no_b, _mut_residual_ld_fp64]
 
@@ -492,7 +559,8 @@ def test_pins_catch_planted_mistakes(mutant, monkeypatch):
     mutant(monkeypatch)
     caught = 0
     for pin in (pin_decomposed_equals_monolithic, pin_plain_equals_structured, pin_local_schur_blocks,
-                pin_inertia_additivity, pin_assembly_raw, pin_backward_error_hand, pin_residual_ld_exact):
+                pin_inertia_additivity, pin_assembly_raw, pin_backward_error_hand, pin_residual_ld_exact,
+                _pin_slack_first_case):
         try:
             pin(inst)
         except (AssertionError, np.linalg.LinAlgError):
