@@ -313,6 +313,39 @@ int kkt_batch_wait(kkt_batch *b);
 int kkt_batch_stream_of(const kkt_batch *b, int64_t i);
 void kkt_batch_destroy(kkt_batch *b);
 
+/* ---- slack elimination (section 2.1) --------------------------------------
+ * A period block with line-flow (inequality) rows has a slack s_j per row,
+ * linked to its multiplier row i by -1 with the diagonal L_s,j = S^-1 Y > 0
+ * (Eq. SCOPFhessianSymmetric, slacks last in Eq. SCOPFslackAtEnd):
+ *     [ A_n   E  ] [u_n]   [b_n]      E: -1 at (lam_row[j], j)
+ *     [ E^T  L_s ] [s_n] = [r_n]
+ * Eliminating the slacks whose L_s is well away from zero leaves
+ * A_n - E L_s^-1 E^T (1/L_s,j subtracted from the diagonal of row lam_row[j])
+ * and b_n - E L_s^-1 r_n (r_j / L_s,j added to that row): Eq.
+ * SCOPFhessianReduced; afterwards L_s,j s_j = r_j + u_n[lam_row[j]] (Eq.
+ * SCOPFslackReduction). Slacks near zero are left in A_n by the caller as
+ * primal rows of the pattern. The reduced K is what kkt_factor / kkt_solve
+ * see: its inertia lacks the N * n_slack positive eigenvalues of the
+ * eliminated slacks.
+ *
+ * kkt_set_slacks: after kkt_analyze, the row of A_n (a multiplier row,
+ * >= n_primal, at most one slack each; host array, copied) of each of the
+ * n_slack eliminated slacks of every period. KKT_ERR_ARG otherwise. Holds
+ * 12 bytes per slack of device memory beyond kkt_footprint.
+ * kkt_slack_reduce: A_out = A_vals reduced, b_out = b reduced (device
+ * pointers; A_out may be A_vals and b_out may be b, in place):
+ *   A_vals, A_out  [N][nnz_A] as kkt_factor; Ls [N][n_slack];
+ *   b, b_out       [nrhs][N*nA + N*Ns] as kkt_solve (nrhs may be 0: values only);
+ *   rs             [nrhs][N*n_slack], period-major (r_n of period n at n*n_slack).
+ * Synchronises; KKT_ERR_NONFINITE when an L_s is not positive and finite.
+ * kkt_slack_recover: s_out [nrhs][N*n_slack] from the solution x of the
+ * reduced system (device pointers, enqueued on the stream). */
+int kkt_set_slacks(kkt_ctx *ctx, int64_t n_slack, const int32_t *lam_row);
+int kkt_slack_reduce(kkt_ctx *ctx, const double *A_vals, const double *Ls, const double *b,
+                     const double *rs, double *A_out, double *b_out, int64_t nrhs);
+int kkt_slack_recover(kkt_ctx *ctx, const double *Ls, const double *rs, const double *x,
+                      double *s_out, int64_t nrhs);
+
 /* kkt_schur: write the assembled Schur complement S of the last kkt_factor
  * (dense n_g x n_g, column-major, both triangles; n_g = N*Ns) into the
  * caller's device buffer S_out. Diagnostic; enqueued on the stream. */

@@ -198,6 +198,25 @@ def kkt_solve_noalloc(ctx, b, x, nrhs, steps):
     return _check(load_library().kkt_solve_noalloc(ctx, _ptr(b), _ptr(x), int(nrhs), int(steps)), "kkt_solve_noalloc")
 
 
+def kkt_set_slacks(ctx, lam_row):
+    """The multiplier row of A_n each eliminated slack is linked to (host)."""
+    lam_row = np.ascontiguousarray(lam_row, dtype=np.int32)
+    return _check(load_library().kkt_set_slacks(ctx, int(lam_row.size), lam_row.ctypes.data if lam_row.size else None),
+                  "kkt_set_slacks")
+
+
+def kkt_slack_reduce(ctx, A_vals, Ls, b, rs, A_out, b_out, nrhs):
+    """Eq. SCOPFhessianReduced on device arrays (see include/kkt.h)."""
+    return _check(load_library().kkt_slack_reduce(ctx, _ptr(A_vals), _ptr(Ls), _ptr(b), _ptr(rs), _ptr(A_out),
+                                                  _ptr(b_out), int(nrhs)), "kkt_slack_reduce")
+
+
+def kkt_slack_recover(ctx, Ls, rs, x, s_out, nrhs):
+    """Eq. SCOPFslackReduction on device arrays (see include/kkt.h)."""
+    return _check(load_library().kkt_slack_recover(ctx, _ptr(Ls), _ptr(rs), _ptr(x), _ptr(s_out), int(nrhs)),
+                  "kkt_slack_recover")
+
+
 def kkt_solve_status(ctx):
     info = _abi.SolveInfo()
     rc = _check(load_library().kkt_solve_status(ctx, C.byref(info)), "kkt_solve_status")

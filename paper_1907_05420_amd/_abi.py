@@ -77,6 +77,10 @@ SIGNATURES = {
     "kkt_factor_status": (C.c_int, [C.c_void_p, C.POINTER(Inertia)]),
     "kkt_solve_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
     "kkt_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
+    "kkt_set_slacks": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "kkt_slack_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int64]),
+    "kkt_slack_recover": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "kkt_solve_status": (C.c_int, [C.c_void_p, C.POINTER(SolveInfo)]),
     "kkt_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     "kkt_batch_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -159,6 +159,12 @@ struct kkt_ctx {
     kkt_ctx *fb = nullptr;
     bool fb_factored = false;
     kkt_inertia fb_inertia{};
+    // eliminated slacks (kkt_set_slacks): their flow rows and the positions
+    // of those rows' diagonal entries in A_vals
+    int64_t n_slack = 0;
+    int32_t *d_slack_row = nullptr;
+    int64_t *d_slack_dpos = nullptr;
+    std::vector<void *> slack_allocs;
 };
 
 namespace {
@@ -1061,10 +1067,15 @@ extern "C" int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s) {
     if (rc) { free_static(ctx); return rc; }
     if (ctx->fb) { kkt_destroy(ctx->fb); ctx->fb = nullptr; }
     ctx->fb_factored = false;
+    for (void *q : ctx->slack_allocs) (void)hipFree(q);
+    ctx->slack_allocs.clear();
+    ctx->n_slack = 0;
+    ctx->d_slack_row = nullptr;
+    ctx->d_slack_dpos = nullptr;
+    ctx->pat_colptr.assign(s->A_colptr, s->A_colptr + s->nA + 1);
     if (ctx->opt.precision == KKT_MIXED) {
         // the pattern, for an FP64 fallback analysis
         const int64_t nnz = s->A_colptr[s->nA];
-        ctx->pat_colptr.assign(s->A_colptr, s->A_colptr + s->nA + 1);
         ctx->pat_rowind.assign(s->A_rowind, s->A_rowind + nnz);
         ctx->pat_n_primal = s->n_primal;
         ctx->pat_Ns = s->Ns;
@@ -1696,6 +1707,77 @@ extern "C" int kkt_schur_blocks(kkt_ctx *ctx, double *out) {
     return KKT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// slack elimination (section 2.1, Eqs. SCOPFslackAtEnd, SCOPFhessianReduced,
+// SCOPFslackReduction)
+// ---------------------------------------------------------------------------
+
+extern "C" int kkt_set_slacks(kkt_ctx *ctx, int64_t n_slack, const int32_t *lam_row) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->analyzed) return KKT_ERR_ORDER;
+    if (n_slack < 0 || (n_slack > 0 && !lam_row)) return KKT_ERR_ARG;
+    const Symbolic &S = ctx->sy;
+    std::vector<char> seen(S.nA, 0);
+    std::vector<int64_t> dpos(n_slack);
+    for (int64_t j = 0; j < n_slack; ++j) {
+        const int32_t r = lam_row[j];
+        // a multiplier row (negative pivot), at most one slack each
+        if (r < S.n_primal || r >= S.nA || seen[r]) return KKT_ERR_ARG;
+        seen[r] = 1;
+        dpos[j] = ctx->pat_colptr[r];  // the diagonal leads its column
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void *q : ctx->slack_allocs) (void)hipFree(q);
+    ctx->slack_allocs.clear();
+    ctx->n_slack = 0;
+    if (n_slack == 0) return KKT_OK;
+    void *pr = nullptr, *pd = nullptr;
+    if (hipMalloc(&pr, 4 * n_slack) != hipSuccess) return KKT_ERR_NOMEM;
+    ctx->slack_allocs.push_back(pr);
+    if (hipMalloc(&pd, 8 * n_slack) != hipSuccess) return KKT_ERR_NOMEM;
+    ctx->slack_allocs.push_back(pd);
+    HIPCHK(hipMemcpy(pr, lam_row, 4 * n_slack, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pd, dpos.data(), 8 * n_slack, hipMemcpyHostToDevice));
+    ctx->d_slack_row = (int32_t *)pr;
+    ctx->d_slack_dpos = (int64_t *)pd;
+    ctx->n_slack = n_slack;
+    return KKT_OK;
+}
+
+extern "C" int kkt_slack_reduce(kkt_ctx *ctx, const double *A_vals, const double *Ls, const double *b,
+                                const double *rs, double *A_out, double *b_out, int64_t nrhs) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->analyzed) return KKT_ERR_ORDER;
+    if (!A_vals || !A_out || nrhs < 0 || (nrhs > 0 && (!b || !b_out)) ||
+        (ctx->n_slack > 0 && (!Ls || (nrhs > 0 && !rs))))
+        return KKT_ERR_ARG;
+    const Symbolic &S = ctx->sy;
+    hipStream_t st = ctx->stream;
+    if (A_out != A_vals)
+        HIPCHK(hipMemcpyAsync(A_out, A_vals, 8 * S.nnzA * ctx->N, hipMemcpyDeviceToDevice, st));
+    if (nrhs > 0 && b_out != b)
+        HIPCHK(hipMemcpyAsync(b_out, b, 8 * ctx->ntot * nrhs, hipMemcpyDeviceToDevice, st));
+    launch_zero<int>(ctx->d_flag + 2, 1, st);
+    launch_slack_reduce(Ls, rs, ctx->n_slack, ctx->N, nrhs, ctx->d_slack_row, ctx->d_slack_dpos, S.nnzA, S.nA,
+                        ctx->ntot, A_out, b_out, ctx->d_flag + 2, st);
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return flag ? KKT_ERR_NONFINITE : KKT_OK;
+}
+
+extern "C" int kkt_slack_recover(kkt_ctx *ctx, const double *Ls, const double *rs, const double *x, double *s_out,
+                                 int64_t nrhs) {
+    if (!ctx) return KKT_ERR_ARG;
+    if (!ctx->analyzed) return KKT_ERR_ORDER;
+    if (nrhs < 1 || !x || (ctx->n_slack > 0 && (!Ls || !rs || !s_out))) return KKT_ERR_ARG;
+    const Symbolic &S = ctx->sy;
+    launch_slack_recover(Ls, rs, ctx->n_slack, ctx->N, nrhs, ctx->d_slack_row, S.nA, ctx->ntot, x, s_out,
+                         ctx->stream);
+    HIPCHK(hipGetLastError());
+    return KKT_OK;
+}
+
 extern "C" int kkt_enable_timing(kkt_ctx *ctx, int on) {
     if (!ctx) return KKT_ERR_ARG;
     ctx->timing = on != 0;
@@ -1718,6 +1800,7 @@ extern "C" void kkt_destroy(kkt_ctx *ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->fb) kkt_destroy(ctx->fb);
+    for (void *q : ctx->slack_allocs) (void)hipFree(q);
     free_ws(ctx);
     free_static(ctx);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);

@@ -176,6 +176,17 @@ void launch_sell_values(const double *A, int64_t nnzA, int64_t N, int64_t nA, in
                         double dw, double dc, double *Asell, hipStream_t st);
 void launch_matvec(const ResidualArgs &ra, const double *x, double *y, double *work, hipStream_t st);
 
+// ---- slack elimination (Eqs. SCOPFhessianReduced, SCOPFslackReduction) ----------
+// A_out[n][dpos[j]] -= 1/Ls[n][j]; b_out rows n nA + lam_row[j] += rs / Ls;
+// flag |= 1 where an L_s is not positive and finite
+void launch_slack_reduce(const double *Ls, const double *rs, int64_t ns, int64_t N, int64_t nrhs,
+                         const int32_t *lam_row, const int64_t *dpos, int64_t nnzA, int64_t nA, int64_t ntot,
+                         double *A_out, double *b_out, int *flag, hipStream_t st);
+// s_out = (rs + x[rows n nA + lam_row[j]]) / Ls
+void launch_slack_recover(const double *Ls, const double *rs, int64_t ns, int64_t N, int64_t nrhs,
+                          const int32_t *lam_row, int64_t nA, int64_t ntot, const double *x, double *s_out,
+                          hipStream_t st);
+
 // ---- Krylov helpers (vectors are [nrhs][n] blocks; coefficient arrays on device)
 // h[k * ldh + i] = <W_k, V_i,k> for i < nv (deterministic two-stage sums;
 // part holds nrhs * nv * 512 doubles)
