@@ -377,6 +377,8 @@ def main():
     ap.add_argument("--serve-refine", default="tolerance", choices=["tolerance", "fixed"],
                     help="serve: refine every solve to 1e-10, or a fixed number of steps (--refine-steps)")
     ap.add_argument("--refine-steps", type=int, default=3, help="fixed refinement steps of a batch")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="mesh2000_N96: skip the other workloads reported beside the headline")
     ap.add_argument("--recompute-periods", type=int, default=0,
                     help="hold the factors of this many periods only and recompute them in every solve pass "
                          "(0 = keep all)")
@@ -488,6 +490,30 @@ def main():
             "phase_ms": {"block_factor": ps[0], "schur_prefix": ps[1], "schur_elimination": ps[2],
                          "solve_refined": ps[3]},
             "device_bytes": ms["stats"]["footprint"], "device_bytes_dense": m["stats"]["footprint"]}
+    if cfg == 2 and not args.no_extra and prec == pk.KKT_FP64 and args.recompute_periods == 0:
+        # the other workloads, each in a process of its own (device memory
+        # released in between), reported beside the headline
+        extra = {"serve": ["--workload", "serve", "--requests", "12", "--iterations", "10"],
+                 "uneven64": ["--workload", "uneven64", "--steps", "2", "--warmup", "1"],
+                 "mesh9241_N24": ["--workload", "mesh9241_N24", "--steps", "3", "--warmup", "1", "--schur", "dense",
+                                  "--no-cpu-baseline"]}
+        res["other_workloads"] = {}
+        for name, argv in extra.items():
+            try:
+                r = subprocess.run([sys.executable, os.path.abspath(__file__)] + argv, capture_output=True,
+                                   text=True, timeout=400)
+                line = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+            except (subprocess.TimeoutExpired, ValueError, IndexError) as e:
+                log(f"{name}: {e}")
+                line = None
+            if line is None:
+                res["other_workloads"][name] = None
+                continue
+            keep = ("value", "unit", "ms_per_step", "p50_ms", "p99_ms", "rel_res", "rel_res_max", "above_1e-10",
+                    "solves_at_tolerance", "refine_iters", "inertia_ok", "speedup_vs_sequential", "device_gb",
+                    "device_bytes", "request_p50_ms", "request_p99_ms", "phase_ms", "config")
+            res["other_workloads"][name] = {k: line[k] for k in keep if k in line}
+            log(f"{name}: {res['other_workloads'][name].get('value')}")
     if not args.no_cpu_baseline and cfg == 2:
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only"],
                            capture_output=True, text=True, timeout=900)
