@@ -349,13 +349,12 @@ __device__ inline float lane_value(float v, int lane) {
 }
 __device__ inline int lane_value(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// the pivot block at column t0 of front d in period n, by the whole
+// 256-thread workgroup; Ls [2][16][NB] and Ds [2][16] in LDS
 template <typename T>
-__global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int t0) {
-    // multipliers and pivots of a 16-column block, double-buffered by block
-    __shared__ T Ls[2][16][NB];
-    __shared__ T Ds[2][16];
-    const FrontDesc d = sd[fl[blockIdx.x]];
-    const int n = blockIdx.y, i = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ inline void diag_core(const FactorArgs<T> &fa, const FrontDesc &d, int n, int t0, T (*Ls)[16][NB],
+                                 T (*Ds)[16]) {
+    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nb = min(NB, d.c - t0), m = d.m;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     T R[16], X[16];
@@ -461,6 +460,14 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
     flush_tally(tl, fa.cnt + 4 * n);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int t0) {
+    // multipliers and pivots of a 16-column block, double-buffered by block
+    __shared__ T Ls[2][16][NB];
+    __shared__ T Ds[2][16];
+    diag_core<T>(fa, sd[fl[blockIdx.x]], blockIdx.y, t0, Ls, Ds);
+}
+
 // Locate the front of a flattened task index through per-step prefix sums.
 __device__ inline int find_front(const int32_t *pre, int nf, int b) {
     int lo = 0, hi = nf - 1;
@@ -504,19 +511,16 @@ __device__ inline void tile_stage(T *sC, typename Acc<T>::type (&acc)[2][2], int
 
 // Rows below the pivot block: L21 = F21 (L11^-1)^T D^-1 as one MFMA product
 // per 64-row tile (L11^-1 is stored in the pivot block).
+// row tile `tile` below the pivot block at t0 of front d in period n, by the
+// whole 256-thread workgroup; sA, sB [NB * LDS_LD] and Ds [NB] in LDS
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
-                                              const int32_t *pre, int nf, int t0, int pe, int win) {
+__device__ inline void trsm_core(const FactorArgs<T> &fa, const FrontDesc &d, int n, int tile, int t0, int pe,
+                                 int win, T *sA, T *sB, T *Ds) {
     typedef typename Acc<T>::type acc_t;
-    __shared__ T sA[NB * LDS_LD];
-    __shared__ T sB[NB * LDS_LD];
-    __shared__ T Ds[NB];
-    const int fi = find_front(pre, nf, blockIdx.x);
-    const FrontDesc d = sd[fl[fi]];
-    const int n = blockIdx.y, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int nb = min(NB, d.c - t0), m = d.m;
     const int mr = win == 3 ? min(pe, d.c) : m;  // rows below mr are left to k_panel_trsm
-    const int R0 = t0 + nb + (blockIdx.x - pre[fi]) * 64;
+    const int R0 = t0 + nb + tile * 64;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     {
         // clamped addresses, all loads issued before the first use
@@ -556,6 +560,16 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
     const int r = R0 + row;
     if (r < mr)
         for (int q = tid >> 6; q < nb; q += 4) P[r + (int64_t)(t0 + q) * m] = sC[row + q * LDT] / Ds[q];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
+                                              const int32_t *pre, int nf, int t0, int pe, int win) {
+    __shared__ T sA[NB * LDS_LD];
+    __shared__ T sB[NB * LDS_LD];
+    __shared__ T Ds[NB];
+    const int fi = find_front(pre, nf, blockIdx.x);
+    trsm_core<T>(fa, sd[fl[fi]], blockIdx.y, blockIdx.x - pre[fi], t0, pe, win, sA, sB, Ds);
 }
 
 // Rows below a factored sub-panel (columns [t0, cend), cend = min(pe, c), at
@@ -739,21 +753,19 @@ __device__ inline void trap_decode(int t, int Tr, int &ti, int &tj) {
 // F(r, q) -= sum_k L(r, k) d_k L(q, k) for r >= q in the region of upd_geom:
 // one 64x64 tile per workgroup, K in chunks of 64, FP64/FP32 MFMA 16x16x4,
 // coalesced read-modify-write of the target through an LDS stage.
+// tile `tile` of an update of front d in period n, by the whole 256-thread
+// workgroup; sA, sB [NB * LDS_LD] in LDS
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
-                                                const int32_t *pre, int nf, int kind, int t0, int pe, int win) {
+__device__ inline void update_core(const FactorArgs<T> &fa, const FrontDesc &d, int n, int tile, int kind, int t0,
+                                   int pe, int win, T *sA, T *sB) {
     typedef typename Acc<T>::type acc_t;
-    __shared__ T sA[NB * LDS_LD];
-    __shared__ T sB[NB * LDS_LD];
-    const int fi = find_front(pre, nf, blockIdx.x);
-    const FrontDesc d = sd[fl[fi]];
-    const int n = blockIdx.y, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int m = d.m, c = d.c;
     const UpdGeom g = upd_geom(kind, t0, pe, c, m, win);
     const int mr = (kind == 2 && win == 3) ? g.qhi : m;  // rows below mr are left to k_panel_trsm
     const int Tr = (mr - g.lo + 63) / 64;
     int ti, tj;
-    trap_decode(blockIdx.x - pre[fi], Tr, ti, tj);
+    trap_decode(tile, Tr, ti, tj);
     const int R0 = g.lo + 64 * ti, Q0 = g.lo + 64 * tj;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
@@ -792,6 +804,15 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
     tile_stage<T>(sC, acc, lane, w);
     __syncthreads();
     rmw_sub_row<T, 16>(P, Ub, m, c, R0 + row, Q0, kk, 4, g.qhi, sC + row, LDT, mr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
+                                                const int32_t *pre, int nf, int kind, int t0, int pe, int win) {
+    __shared__ T sA[NB * LDS_LD];
+    __shared__ T sB[NB * LDS_LD];
+    const int fi = find_front(pre, nf, blockIdx.x);
+    update_core<T>(fa, sd[fl[fi]], blockIdx.y, blockIdx.x - pre[fi], kind, t0, pe, win, sA, sB);
 }
 
 // Trailing update after an outer panel (kind 3) on 128x128 tiles: four waves
@@ -1248,6 +1269,7 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
             hipLaunchKernelGGL(k_panel_trsm<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
                                s.nf, s.t0, s.pe);
             break;
+
         case 4:
             hipLaunchKernelGGL(k_update_big<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
                                s.nf, s.t0, s.pe, s.win);
