@@ -423,6 +423,33 @@ def main():
     k_bytes = sum(k["bytes"] for k in m["kstats"])
     achieved = k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
     traffic = measured_traffic() if cfg == 2 else None  # the committed counters are of mesh2000_N96
+    # the other phases against their own rooflines (algorithmic work only):
+    # block factor: N x the period's factorisation flops, N x (entries of A's
+    # stored triangle + factor entries) x 8 bytes read/written once;
+    # solve: every pass reads each period's factor twice (forward, backward)
+    # and the dense Schur factor's two triangles once each; every FGMRES
+    # iteration adds one product with K (values 8 B + column index 4 B per
+    # stored entry, both triangles)
+    st = m["stats"]
+    N = w["N"]
+    nnz_a = int(inst.colptr[-1])
+    bf_flops = N * st["flops_factor"]
+    bf_bytes = 8.0 * N * (nnz_a + st["nnz_L"])
+    t_bf = max(bf_flops / (MI355X_FP64_TFLOPS * 1e12), bf_bytes / (MI355X_HBM_GBS * 1e9))
+    iters = float(np.mean([i["refine_iters"] for i in m["infos"]]))
+    pass_bytes = 16.0 * N * st["nnz_L"] + 8.0 * ng * ng
+    matvec_bytes = 12.0 * N * (2 * nnz_a - inst.n_A)
+    sv_bytes = (iters + 1) * pass_bytes + iters * matvec_bytes
+    phase_roofline = {
+        "block_factor": {"flops": bf_flops, "bytes": bf_bytes, "ms": ph[0],
+                         "tflops": bf_flops / (ph[0] * 1e-3) / 1e12 if ph[0] > 0 else 0.0,
+                         "gbs": bf_bytes / (ph[0] * 1e-3) / 1e9 if ph[0] > 0 else 0.0,
+                         "attainable_ms": t_bf * 1e3, "frac_attainable": t_bf * 1e3 / ph[0] if ph[0] > 0 else 0.0},
+        "solve_refined": {"passes": iters + 1, "pass_bytes": pass_bytes, "matvec_bytes": matvec_bytes,
+                          "bytes": sv_bytes, "ms": ph[3],
+                          "gbs": sv_bytes / (ph[3] * 1e-3) / 1e9 if ph[3] > 0 else 0.0,
+                          "frac_hbm": sv_bytes / (ph[3] * 1e-3) / 1e9 / MI355X_HBM_GBS if ph[3] > 0 else 0.0},
+    }
     res = {
         "metric": METRIC,
         "value": m["value"],
@@ -455,6 +482,7 @@ def main():
                      "schur_update_kernel": ph[4]},
         "schur_ldlt_tflops": ng ** 3 / 3.0 / (ph[2] * 1e-3) / 1e12 if ph[2] > 0 else 0.0,
         "analyze_ms": m["analyze_ms"],
+        "phase_roofline": phase_roofline,
         "roofline": {"bound": "mfma", "kernel": "k_update_big (dense Schur trailing update, FP64 MFMA)",
                      "achieved": achieved, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_TFLOPS,

@@ -35,15 +35,14 @@ using namespace kkt;
 
 namespace {
 
-// kind 0-6: launches (see StepDev); SYNC_TO_SIDE: the side stream waits for
+// kind 0-7: launches (see StepDev); SYNC_TO_SIDE: the side stream waits for
 // the main stream's work so far; SYNC_TO_MAIN: the main stream waits for the
-// side stream's work so far; SYNC_TO_INV / SYNC_INV_TO_MAIN: the same between
-// the main stream and the stream of the diagonal-block inverses.
-constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101, SYNC_TO_INV = 102, SYNC_INV_TO_MAIN = 103;
+// side stream's work so far.
+constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101;
 constexpr int PANEL_ROWS = 1024;  // rows below a sub-panel from which its rows below take one launch
 struct StepHost {
     int kind, win, t0, pe, nf, ntasks;
-    int side;                 // 0: main stream, 1: side stream, 2: inverse stream
+    int side;                 // 0: main stream, 1: side stream
     int64_t fl_off, pre_off;  // offsets (int32 elements) into the task buffer
 };
 
@@ -131,8 +130,6 @@ struct kkt_ctx {
     // side stream and events of the lookahead
     hipStream_t side = nullptr;
     hipEvent_t ev_main = nullptr, ev_side = nullptr;
-    hipStream_t inv = nullptr;  // inverses of the dense factor's diagonal blocks
-    hipEvent_t ev_inv_main = nullptr, ev_inv = nullptr;
     // timing
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -291,23 +288,15 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
             continue;
         }
         // the panel is factored: the side stream may update the columns
-        // beyond the next panel with it (after its own previous update), and
-        // the inverse stream may invert its diagonal blocks, which only the
-        // dense solves use and no later step of the factorisation reads
+        // beyond the next panel with it (after its own previous update)
         sync(SYNC_TO_SIDE);
-        sync(SYNC_TO_INV);
-        for (int j0 = k; j0 < std::min(pe, cmax); j0 += INV_W) add(5, j0, pe, 0, 2);
-        if (outer_w == 2 * INV_W) add(6, k, pe, 0, 2);  // and of the whole panel's diagonal block
         // the next panel's columns: the side stream's update from the
         // previous panel must be done before this panel's update of them
         if (k > 0) sync(SYNC_TO_MAIN);
         add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
         add(big ? 4 : 3, k, pe, 2, 1);  // the rest, side stream
     }
-    if (lookahead) {
-        sync(SYNC_TO_MAIN);
-        sync(SYNC_INV_TO_MAIN);
-    }
+    if (lookahead) sync(SYNC_TO_MAIN);
 }
 
 StepDev step_dev(const StepHost &s, const int32_t *base) {
@@ -600,7 +589,8 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = dalloc(ctx, (void **)&ctx->d_tauS, 8 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_amaxS, 256))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_cntS, 256))) return rc;
-        if ((rc = dalloc(ctx, (void **)&ctx->d_invtmp, 8 * INV_W * INV_W))) return rc;
+        const int64_t pairs = (ctx->ng + 2 * INV_W - 1) / (2 * INV_W);
+        if ((rc = dalloc(ctx, (void **)&ctx->d_invtmp, 8 * INV_W * INV_W * pairs))) return rc;
     }
     return KKT_OK;
 }
@@ -814,14 +804,8 @@ int factor_schur(kkt_ctx *ctx) {
         } else if (s.kind == SYNC_TO_MAIN) {
             HIPCHK(hipEventRecord(ctx->ev_side, ctx->side));
             HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
-        } else if (s.kind == SYNC_TO_INV) {
-            HIPCHK(hipEventRecord(ctx->ev_inv_main, st));
-            HIPCHK(hipStreamWaitEvent(ctx->inv, ctx->ev_inv_main, 0));
-        } else if (s.kind == SYNC_INV_TO_MAIN) {
-            HIPCHK(hipEventRecord(ctx->ev_inv, ctx->inv));
-            HIPCHK(hipStreamWaitEvent(st, ctx->ev_inv, 0));
         } else {
-            hipStream_t ss = s.side == 2 ? ctx->inv : s.side ? ctx->side : st;
+            hipStream_t ss = s.side ? ctx->side : st;
             const bool timed = ctx->timing && s.kind == 4;
             if (timed) {
                 if ((size_t)(2 * ctx->kcount + 2) > ctx->kev.size()) {
@@ -833,10 +817,7 @@ int factor_schur(kkt_ctx *ctx) {
                 }
                 HIPCHK(hipEventRecord(ctx->kev[2 * ctx->kcount], ss));
             }
-            if (s.kind == 6)
-                launch_inv_combine(fa, ctx->d_sdS, ctx->d_stasks + s.fl_off, s.t0, (int)ctx->ng, ctx->d_invtmp, ss);
-            else
-                launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, ss);
+            launch_step<double>(fa, ctx->d_sdS, step_dev(s, ctx->d_stasks), 1, ss);
             if (timed) {
                 HIPCHK(hipEventRecord(ctx->kev[2 * ctx->kcount + 1], ss));
                 double f = 0.0, b = 0.0;
@@ -847,6 +828,9 @@ int factor_schur(kkt_ctx *ctx) {
             }
         }
     }
+    // the inverses of the diagonal blocks, which only the dense solves use,
+    // for all blocks at once
+    launch_inverses_all(fa, ctx->d_sdS, ctx->d_stasks + ctx->ssteps.front().fl_off, (int)ctx->ng, ctx->d_invtmp, st);
     launch_mirror_lower(ctx->d_S, ctx->ng, st);
     return KKT_OK;
 }
@@ -1009,10 +993,7 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return KKT_ERR_HIP; }
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&ctx->inv, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_inv_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_inv, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming) != hipSuccess) {
         kkt_destroy(ctx);
         return KKT_ERR_HIP;
     }
@@ -1807,12 +1788,8 @@ extern "C" void kkt_destroy(kkt_ctx *ctx) {
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->kev) (void)hipEventDestroy(e);
-    if (ctx->inv) (void)hipStreamSynchronize(ctx->inv);
     if (ctx->ev_main) (void)hipEventDestroy(ctx->ev_main);
     if (ctx->ev_side) (void)hipEventDestroy(ctx->ev_side);
-    if (ctx->ev_inv_main) (void)hipEventDestroy(ctx->ev_inv_main);
-    if (ctx->ev_inv) (void)hipEventDestroy(ctx->ev_inv);
-    if (ctx->inv) (void)hipStreamDestroy(ctx->inv);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }

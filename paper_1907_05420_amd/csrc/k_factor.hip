@@ -934,6 +934,8 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
     const FrontDesc d = sd[fl[blockIdx.x]];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m = d.m;
+    j0 += INV_W * blockIdx.y;  // one diagonal block per blockIdx.y
+    if (j0 >= d.c) return;
     const int nbw = min(INV_W, d.c - j0);
     const int nsb = (nbw + 63) / 64;
     double *P = fa.L + d.Loff;
@@ -1047,9 +1049,12 @@ __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, cons
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int row = tid & 63, kk = tid >> 6;
     const int m = d.m;
-    const int ja = j0, jb = j0 + INV_W;
-    const int nbw_b = min(INV_W, d.c - jb);  // > 0: the launch exists only then
+    // one 2*INV_W block per blockIdx.y, each with its own INV_W x INV_W staging
+    const int ja = j0 + 2 * INV_W * blockIdx.y, jb = ja + INV_W;
+    tmp += (int64_t)INV_W * INV_W * blockIdx.y;
+    const int nbw_b = min(INV_W, d.c - jb);
     const int ti = blockIdx.x / (INV_W / 64), tj = blockIdx.x % (INV_W / 64);
+    if (nbw_b <= 64 * ti) return;  // no second block, or a tile row past its end
     double *P = fa.L + d.Loff;
     acc_t acc[2][2];
 #pragma unroll
@@ -1098,6 +1103,17 @@ void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_
     const int tiles = ((nbw_b + 63) / 64) * (INV_W / 64);
     for (int mode = 0; mode < 2; ++mode)
         hipLaunchKernelGGL(k_inv_combine, dim3(tiles), dim3(256), 0, st, fa, sd, fl, j0, mode, tmp);
+}
+
+void launch_inverses_all(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int c, double *tmp,
+                         hipStream_t st) {
+    if (c <= 0) return;
+    hipLaunchKernelGGL(k_inv256, dim3(1, (unsigned)((c + INV_W - 1) / INV_W)), dim3(256), 0, st, fa, sd, fl, 0);
+    const int pairs = (c + 2 * INV_W - 1) / (2 * INV_W);
+    if (c <= INV_W) return;
+    for (int mode = 0; mode < 2; ++mode)
+        hipLaunchKernelGGL(k_inv_combine, dim3((INV_W / 64) * (INV_W / 64), (unsigned)pairs), dim3(256), 0, st, fa, sd,
+                           fl, 0, mode, tmp);
 }
 
 // Structured Schur elimination (section 4.3): G = W Linv for one front, W the
@@ -1274,10 +1290,6 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
             hipLaunchKernelGGL(k_update_big<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
                                s.nf, s.t0, s.pe, s.win);
             break;
-        case 5:
-            if constexpr (std::is_same<T, double>::value)
-                hipLaunchKernelGGL(k_inv256, dim3(s.nf, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.t0);
-            break;
         default:
             hipLaunchKernelGGL(k_update<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
                                s.nf, s.kind, s.t0, s.pe, s.win);
@@ -1287,8 +1299,6 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
 // host mirror of the per-front task counts of a step
 int step_tasks(int kind, int t0, int pe, int c, int m, int win) {
     if (kind == 4) return step_tasks_big(t0, pe, c, m, win);
-    if (kind == 5) return c > t0 ? 1 : 0;
-    if (kind == 6) return c > t0 + INV_W ? 1 : 0;
     if (kind == 0) return c > t0 ? 1 : 0;
     if (kind == 1) {
         const int nb = std::min(NB, c - t0);

@@ -41,9 +41,9 @@ struct TreeArgs {
 // per block the pivot block (kind 0), the rows below it (kind 1) and the rest
 // of the outer panel (kind 2); after each outer panel one trailing update of
 // rank <= the panel width (kind 3 on 64x64 tiles, kind 4 on 128x128 tiles for
-// large trailing matrices); for the dense Schur factor also the inverse of
-// each INV_W-wide diagonal block (kind 5) and, from two of them, of each
-// 2*INV_W-wide one (kind 6), which the dense solves use.
+// large trailing matrices). The dense Schur factor's diagonal-block
+// inverses, which only the dense solves use, follow its last panel
+// (launch_inverses_all).
 constexpr int OUTER_W = 256;
 constexpr int SCHUR_OUTER_W = 512;
 constexpr int MAX_OUTER_W = 512;
@@ -118,6 +118,11 @@ void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, i
 void launch_mirror_lower(double *S, int64_t ng, hipStream_t st);
 // inverse of the INV_W diagonal block at j0 of the (single) front fl[0]
 void launch_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, hipStream_t st);
+// every INV_W and 2*INV_W diagonal-block inverse of the dense factor of one
+// front with c pivots, after its factorisation (tmp: INV_W^2 doubles per
+// 2*INV_W block)
+void launch_inverses_all(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int c, double *tmp,
+                         hipStream_t st);
 // structured Schur (section 4.3): thresholds from S's diagonal, front j
 // [S_d[j] - U; S_o[j] - U], U accumulation, G_j = W_j Linv_j, and the solve
 void launch_struct_tau(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
