@@ -105,7 +105,7 @@ struct kkt_ctx {
     bool has_corner = false;
     double dw = 0.0, dc = 0.0;
     double *d_S = nullptr, *d_prefix = nullptr, *d_tauS = nullptr, *d_amaxS = nullptr;
-    double *d_invtmp = nullptr;  // INV_W x INV_W staging of the block-inverse combination
+    double *d_invtmp = nullptr;  // staging of the block-inverse combinations
     // structured Schur (section 4.3): the N fronts [A_j; B_j] (2 Ns x Ns, ld
     // 2 Ns; Ns x Ns for the last), G_j = W_j Linv_j and its transpose, the
     // running U_j and the update block of the current front, and the solve's
@@ -589,8 +589,10 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = dalloc(ctx, (void **)&ctx->d_tauS, 8 * ctx->ng))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_amaxS, 256))) return rc;
         if ((rc = dalloc(ctx, (void **)&ctx->d_cntS, 256))) return rc;
-        const int64_t pairs = (ctx->ng + 2 * INV_W - 1) / (2 * INV_W);
-        if ((rc = dalloc(ctx, (void **)&ctx->d_invtmp, 8 * INV_W * INV_W * pairs))) return rc;
+        int64_t tmp = 0;
+        for (int64_t W = INV_W; 2 * W <= DENSE_INV_W; W *= 2)
+            tmp = std::max(tmp, W * W * ((ctx->ng + 2 * W - 1) / (2 * W)));
+        if ((rc = dalloc(ctx, (void **)&ctx->d_invtmp, 8 * tmp))) return rc;
     }
     return KKT_OK;
 }

@@ -1011,12 +1011,13 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
     }
 }
 
-// Inverse of the unit lower 2*INV_W block [j0, j0 + 2*INV_W) of the dense
-// factor from the inverses Xa, Xb of its two INV_W diagonal blocks (stored by
-// k_inv256): X = [Xa 0; Xba Xb] with Xba = -Xb Lba Xa, in two launches of
-// 64x64 tiles: mode 0 forms T = Lba Xa into `tmp` (ld INV_W), mode 1 writes
-// -Xb T in place of Lba. Lba is no longer needed by the factorisation once
-// the panel's own updates are done.
+// Inverse of the unit lower 2W block [ja, ja + 2W) of a dense factor from
+// the inverses Xa, Xb of its two W-wide diagonal blocks (stored below their
+// diagonals): X = [Xa 0; Xba Xb] with Xba = -Xb Lba Xa, in two launches of
+// 64x64 tiles: mode 0 forms T = Lba Xa into `tmp` (ld W), mode 1 writes -Xb T
+// in place of Lba. Lba is no longer needed by the factorisation once the
+// panel's own updates are done. W is INV_W or 2 INV_W; blockIdx.y picks the
+// 2W block (ja = j0 + 2W blockIdx.y, its own W x W staging in tmp).
 __device__ inline void load_tile64(double *sX, const double *base, int64_t ld, int r0, int c0, int rlim, int clim,
                                    bool asA, bool diag, int row, int kk) {
     // sX[k][r] = M[r0 + r][c0 + k] ("A" operand, transposed) or
@@ -1041,7 +1042,7 @@ __device__ inline void load_tile64(double *sX, const double *base, int64_t ld, i
 }
 
 __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl,
-                                                     int j0, int mode, double *tmp) {
+                                                     int j0, int mode, double *tmp, int W) {
     typedef Acc<double>::type acc_t;
     __shared__ double sA[NB * LDS_LD];
     __shared__ double sB[NB * LDS_LD];
@@ -1049,11 +1050,10 @@ __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, cons
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int row = tid & 63, kk = tid >> 6;
     const int m = d.m;
-    // one 2*INV_W block per blockIdx.y, each with its own INV_W x INV_W staging
-    const int ja = j0 + 2 * INV_W * blockIdx.y, jb = ja + INV_W;
-    tmp += (int64_t)INV_W * INV_W * blockIdx.y;
-    const int nbw_b = min(INV_W, d.c - jb);
-    const int ti = blockIdx.x / (INV_W / 64), tj = blockIdx.x % (INV_W / 64);
+    const int ja = j0 + 2 * W * blockIdx.y, jb = ja + W;
+    tmp += (int64_t)W * W * blockIdx.y;
+    const int nbw_b = min(W, d.c - jb);
+    const int ti = blockIdx.x / (W / 64), tj = blockIdx.x % (W / 64);
     if (nbw_b <= 64 * ti) return;  // no second block, or a tile row past its end
     double *P = fa.L + d.Loff;
     acc_t acc[2][2];
@@ -1063,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, cons
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
     if (mode == 0) {
         // T_ij = sum_{k >= j} Lba_ik Xa_kj
-        for (int k = tj; k < INV_W / 64; ++k) {
+        for (int k = tj; k < W / 64; ++k) {
             __syncthreads();
             load_tile64(sA, P, m, jb + 64 * ti, ja + 64 * k, jb + nbw_b, jb, true, false, row, kk);
             load_tile64(sB, P, m, ja + 64 * k, ja + 64 * tj, jb, jb, false, k == tj, row, kk);
@@ -1075,7 +1075,7 @@ __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, cons
         for (int k = 0; k <= ti; ++k) {
             __syncthreads();
             load_tile64(sA, P, m, jb + 64 * ti, jb + 64 * k, jb + nbw_b, jb + nbw_b, true, k == ti, row, kk);
-            load_tile64(sB, tmp, INV_W, 64 * k, 64 * tj, nbw_b, INV_W, false, false, row, kk);
+            load_tile64(sB, tmp, W, 64 * k, 64 * tj, nbw_b, W, false, false, row, kk);
             __syncthreads();
             tile_mma<double>(sA, sB, acc, lane, w);
         }
@@ -1087,7 +1087,7 @@ __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, cons
     if (r < nbw_b)
         for (int q = kk; q < 64; q += 4) {
             const double v = sA[row + q * LDT];
-            if (mode == 0) tmp[r + (int64_t)(64 * tj + q) * INV_W] = v;
+            if (mode == 0) tmp[r + (int64_t)(64 * tj + q) * W] = v;
             else P[(int64_t)(jb + r) + (int64_t)(ja + 64 * tj + q) * m] = -v;
         }
 }
@@ -1102,18 +1102,20 @@ void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_
     if (nbw_b <= 0) return;
     const int tiles = ((nbw_b + 63) / 64) * (INV_W / 64);
     for (int mode = 0; mode < 2; ++mode)
-        hipLaunchKernelGGL(k_inv_combine, dim3(tiles), dim3(256), 0, st, fa, sd, fl, j0, mode, tmp);
+        hipLaunchKernelGGL(k_inv_combine, dim3(tiles), dim3(256), 0, st, fa, sd, fl, j0, mode, tmp, INV_W);
 }
 
 void launch_inverses_all(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int c, double *tmp,
                          hipStream_t st) {
     if (c <= 0) return;
     hipLaunchKernelGGL(k_inv256, dim3(1, (unsigned)((c + INV_W - 1) / INV_W)), dim3(256), 0, st, fa, sd, fl, 0);
-    const int pairs = (c + 2 * INV_W - 1) / (2 * INV_W);
-    if (c <= INV_W) return;
-    for (int mode = 0; mode < 2; ++mode)
-        hipLaunchKernelGGL(k_inv_combine, dim3((INV_W / 64) * (INV_W / 64), (unsigned)pairs), dim3(256), 0, st, fa, sd,
-                           fl, 0, mode, tmp);
+    // 2 INV_W blocks from pairs of INV_W ones, then DENSE_INV_W blocks
+    for (int W = INV_W; 2 * W <= DENSE_INV_W && c > W; W *= 2) {
+        const int pairs = (c + 2 * W - 1) / (2 * W);
+        for (int mode = 0; mode < 2; ++mode)
+            hipLaunchKernelGGL(k_inv_combine, dim3((W / 64) * (W / 64), (unsigned)pairs), dim3(256), 0, st, fa, sd,
+                               fl, 0, mode, tmp, W);
+    }
 }
 
 // Structured Schur elimination (section 4.3): G = W Linv for one front, W the

@@ -581,20 +581,21 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
 // one, so that both L (forward) and L^T (backward) are read down columns.
 // Steps go over DBW-wide blocks: forward y_J = X_J v_J then v_below -=
 // L[below, J] y_J; backward x_J = X_J^T z_J then z_above -= L[J, above]^T x_J.
-constexpr int DBW = 2 * INV_W;  // the factor holds the inverses of its 2*INV_W-wide diagonal blocks
+constexpr int DBW = DENSE_INV_W;  // the factor holds the inverses of its DBW-wide diagonal blocks
 
 // out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow
-// (ncol <= DBW): 64 rows per workgroup, DBW/64 groups of 64 columns, reduced
+// (ncol <= DBW): GV_R rows per workgroup, GV_G groups of 64 columns, reduced
 // at the end. All global loads of a workgroup are issued before the first use.
 constexpr int GV_G = DBW / 64;
-__global__ __launch_bounds__(64 * GV_G) void k_dense_gemv(const double *S, int64_t ng, int64_t row0, int64_t nrow,
-                                                          int64_t col0, int ncol, const double *w, double *out,
-                                                          int nrhs) {
+constexpr int GV_R = 512 / GV_G;
+__global__ __launch_bounds__(512) void k_dense_gemv(const double *S, int64_t ng, int64_t row0, int64_t nrow,
+                                                    int64_t col0, int ncol, const double *w, double *out,
+                                                    int nrhs) {
     __shared__ double wb[DBW * RB];
-    __shared__ double red[GV_G * 64 * RB];
+    __shared__ double red[GV_G * GV_R * RB];
     const int tid = threadIdx.x;
-    const int a = tid & 63, g = tid >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 64 + a;
+    const int a = tid % GV_R, g = tid / GV_R;
+    const int64_t i = (int64_t)blockIdx.x * GV_R + a;
     const int qa = 64 * g;
     const int ncq = max(1, min(64, ncol - qa));
     // groups past the last column (a ragged last block) read, and then
@@ -610,7 +611,7 @@ __global__ __launch_bounds__(64 * GV_G) void k_dense_gemv(const double *S, int64
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr)
                 if (rr < nr) o[rr] = out[(int64_t)(k0r + rr) * ng + row0 + i];
-        for (int idx = tid; idx < DBW * RB; idx += 64 * GV_G) {
+        for (int idx = tid; idx < DBW * RB; idx += 512) {
             const int q = idx / RB, r = idx % RB;
             wb[idx] = (q < ncol && r < nr) ? w[(int64_t)(k0r + r) * ng + q] : 0.0;
         }
@@ -625,13 +626,13 @@ __global__ __launch_bounds__(64 * GV_G) void k_dense_gemv(const double *S, int64
             }
         }
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) red[(g * 64 + a) * RB + rr] = acc[rr];
+        for (int rr = 0; rr < RB; ++rr) red[(g * GV_R + a) * RB + rr] = acc[rr];
         __syncthreads();
         if (g == 0 && i < nrow)
             for (int rr = 0; rr < nr; ++rr) {
                 double t = 0.0;
 #pragma unroll
-                for (int gg = 0; gg < GV_G; ++gg) t += red[(gg * 64 + a) * RB + rr];
+                for (int gg = 0; gg < GV_G; ++gg) t += red[(gg * GV_R + a) * RB + rr];
                 out[(int64_t)(k0r + rr) * ng + row0 + i] = o[rr] - t;
             }
         __syncthreads();
@@ -807,7 +808,7 @@ void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t
                            (const double *)v, y, (int)nrhs, 0);
         const int64_t below = ng - j0 - nbw;
         if (below > 0)
-            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((below + 63) / 64)), dim3(64 * GV_G), 0, st, S, ng, j0 + nbw,
+            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((below + GV_R - 1) / GV_R)), dim3(512), 0, st, S, ng, j0 + nbw,
                                below, j0, (int)nbw, (const double *)(y + j0), v, (int)nrhs);
     }
 }
@@ -819,7 +820,7 @@ void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t
         hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, j0,
                            (const double *)z, x, (int)nrhs, 1);
         if (j0 > 0)
-            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((j0 + 63) / 64)), dim3(64 * GV_G), 0, st, S, ng, (int64_t)0,
+            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((j0 + GV_R - 1) / GV_R)), dim3(512), 0, st, S, ng, (int64_t)0,
                                j0, j0, (int)nbw, (const double *)(x + j0), z, (int)nrhs);
     }
 }

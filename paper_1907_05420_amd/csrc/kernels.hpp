@@ -48,6 +48,9 @@ constexpr int OUTER_W = 256;
 constexpr int SCHUR_OUTER_W = 512;
 constexpr int MAX_OUTER_W = 512;
 constexpr int INV_W = 256;
+// width of the inverted diagonal blocks of the dense Schur factor that its
+// solves use (built from INV_W ones by doubling)
+constexpr int DENSE_INV_W = 4 * INV_W;
 struct StepDev {
     int kind;
     int win;                // trailing updates: 0 all, 1 next panel's columns, 2 the rest
@@ -118,9 +121,9 @@ void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, i
 void launch_mirror_lower(double *S, int64_t ng, hipStream_t st);
 // inverse of the INV_W diagonal block at j0 of the (single) front fl[0]
 void launch_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, hipStream_t st);
-// every INV_W and 2*INV_W diagonal-block inverse of the dense factor of one
-// front with c pivots, after its factorisation (tmp: INV_W^2 doubles per
-// 2*INV_W block)
+// the DENSE_INV_W diagonal-block inverses of the dense factor of one front
+// with c pivots, after its factorisation (through INV_W and 2 INV_W ones;
+// tmp: W^2 doubles per 2W block at each doubling, W < DENSE_INV_W)
 void launch_inverses_all(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int c, double *tmp,
                          hipStream_t st);
 // structured Schur (section 4.3): thresholds from S's diagonal, front j
