@@ -833,7 +833,6 @@ int factor_schur(kkt_ctx *ctx) {
     // the inverses of the diagonal blocks, which only the dense solves use,
     // for all blocks at once
     launch_inverses_all(fa, ctx->d_sdS, ctx->d_stasks + ctx->ssteps.front().fl_off, (int)ctx->ng, ctx->d_invtmp, st);
-    launch_mirror_lower(ctx->d_S, ctx->ng, st);
     return KKT_OK;
 }
 

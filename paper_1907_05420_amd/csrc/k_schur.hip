@@ -68,32 +68,6 @@ __global__ void k_copy_sbar(const T *U, int64_t Ustride, int64_t uoff, int64_t n
     out[n * nb * nb + idx] = sbar_at(U + n * Ustride + uoff, nb, i, j);
 }
 
-// Copy the strict lower triangle of the factor of S into the strict upper
-// triangle (U[q][i] = L[i][q]), one 64x64 tile per workgroup through LDS.
-__global__ __launch_bounds__(256) void k_mirror_lower(double *S, int64_t ng, int nt) {
-    __shared__ double T[64 * 65];
-    // blockIdx.x enumerates the lower tiles (I >= J) row by row
-    const int64_t t = blockIdx.x;
-    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    while (I * (I + 1) / 2 > t) --I;
-    const int64_t J = t - I * (I + 1) / 2;
-    if (I >= nt) return;
-    const int64_t r0 = I * 64, c0 = J * 64;
-    const int nr = (int)min((int64_t)64, ng - r0), nc = (int)min((int64_t)64, ng - c0);
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-        const int a = idx & 63, q = idx >> 6;
-        if (a < nr && q < nc) T[a + q * 65] = S[(r0 + a) + (c0 + q) * ng];
-    }
-    __syncthreads();
-    // U[c0 + q][r0 + a] = L[r0 + a][c0 + q]: write down the columns of U
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-        const int q = idx & 63, a = idx >> 6;
-        if (a < nr && q < nc && (I > J || q < a)) S[(c0 + q) + (r0 + a) * ng] = T[a + q * 65];
-    }
-}
-
 // ---- structured Schur (section 4.3, Eq. GlobalSchur) ------------------------
 // Block column j (0-based) of S has the diagonal block S_d[j] = C_jj + S_11,j +
 // P_j and, in every row block below it, S_o[j] = S_10,j + P_j (P_j = sum of
@@ -546,12 +520,6 @@ void launch_struct_solve(const double *F, const double *G, const double *GT, con
         hipLaunchKernelGGL(k_struct_bwd_chain, dim3(1), dim3(SC_T), lds_b, st, GT, N, (int)Ns, (const double *)aa,
                            xg + k0 * ng, ng, nr);
     }
-}
-
-void launch_mirror_lower(double *S, int64_t ng, hipStream_t st) {
-    const int nt = (int)((ng + 63) / 64);
-    const int64_t ntiles = (int64_t)nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)ntiles), dim3(256), 0, st, S, ng, nt);
 }
 
 void launch_schur_prefix(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,

@@ -576,11 +576,10 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
 // ---- dense Schur factor solves ----------------------------------------------
 // The factor of S (column-major, ld ng) keeps D on its diagonal, the inverse
 // X_J of every unit lower DBW x DBW diagonal block J strictly below that
-// block's diagonal, and L elsewhere strictly below the diagonal; after the
-// factorisation the strict lower triangle is mirrored into the strict upper
-// one, so that both L (forward) and L^T (backward) are read down columns.
-// Steps go over DBW-wide blocks: forward y_J = X_J v_J then v_below -=
-// L[below, J] y_J; backward x_J = X_J^T z_J then z_above -= L[J, above]^T x_J.
+// block's diagonal, and L elsewhere strictly below the diagonal (the upper
+// triangle is not read). Steps go over DBW-wide blocks: forward y_J = X_J v_J
+// then v_below -= L[below, J] y_J (rows of a column block); backward x_J =
+// X_J^T z_J then z_above -= L[J, above]^T x_J (dot products down columns).
 constexpr int DBW = DENSE_INV_W;  // the factor holds the inverses of its DBW-wide diagonal blocks
 
 // out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow
@@ -639,13 +638,12 @@ __global__ __launch_bounds__(512) void k_dense_gemv(const double *S, int64_t ng,
     }
 }
 
-// In-block product with the stored inverse of diagonal block [j0, j0 + nbw):
-// out[j0 + i] = in[j0 + i] + sum_q M[i][q] in[j0 + q] with M = X_J (lower,
-// q < i) or X_J^T read from the mirrored upper triangle (upper, q > i).
+// Forward in-block product with the stored inverse of diagonal block
+// [j0, j0 + nbw): out[j0 + i] = in[j0 + i] + sum_{q < i} X_J[i][q] in[j0 + q].
 // 16 rows per workgroup, 16 groups of DBW/16 columns.
 constexpr int BK_C = DBW / 16;
 __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, int64_t j0, const double *in,
-                                                   double *out, int nrhs, int upper) {
+                                                   double *out, int nrhs) {
     __shared__ double vb[DBW * RB];
     __shared__ double red[16 * 16 * RB];
     const int tid = threadIdx.x;
@@ -654,9 +652,9 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
     const int i = blockIdx.x * 16 + rl;
     const int q0 = min(BK_C * g, nbw - 1);
     const double *rowp = S + j0 + min(i, nbw - 1) + (j0 + q0) * ng;
-    // only the groups with a column on the used side of the diagonal read
-    // the factor (the strict lower or upper triangle: half of the block)
-    const bool used = upper ? BK_C * g + BK_C - 1 > i : BK_C * g < i;
+    // only the groups with a column left of the diagonal read the factor
+    // (the strict lower triangle: half of the block)
+    const bool used = BK_C * g < i;
     double l[BK_C];
     if (used) {
 #pragma unroll
@@ -676,7 +674,7 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
 #pragma unroll
         for (int u = 0; u < BK_C; ++u) {
             const int q = BK_C * g + u;
-            const bool ok = q < nbw && (upper ? q > i : q < i);
+            const bool ok = q < nbw && q < i;
             const double x = ok ? l[u] : 0.0;
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) acc[rr] += x * vb[min(q, DBW - 1) * RB + rr];
@@ -691,6 +689,73 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
                 for (int gg = 0; gg < 16; ++gg) t += red[(gg * 16 + rl) * RB + rr];
                 out[(int64_t)(k0r + rr) * ng + j0 + i] = t;
             }
+        __syncthreads();
+    }
+}
+
+// Products with the transpose of the stored lower triangle, for the
+// backward solves: output i is the dot product of the contiguous column
+// segment S[row0 .. row0 + nq, col0 + i] with a vector, so every read runs
+// down a column. Four waves per workgroup, TD_CPW outputs per wave, the nq <=
+// DBW terms of a dot product split over the 64 lanes (16 each) and summed
+// across the wave at the end.
+//   BLK false: out[col0 + i] -= sum_{q < nq} S[row0 + q, col0 + i] w[q]
+//   BLK true (row0 = col0 = j0, the in-block product with X_J^T):
+//              out[j0 + i] = in[j0 + i] + sum_{i < q < nq} S[j0 + q, j0 + i] in[j0 + q]
+constexpr int TD_CPW = 2;
+template <bool BLK>
+__global__ __launch_bounds__(256) void k_dense_tdot(const double *S, int64_t ng, int64_t row0, int nq, int64_t col0,
+                                                    int ncols, const double *w, const double *in, double *out,
+                                                    int nrhs) {
+    __shared__ double wb[DBW * RB];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int i0 = ((int)blockIdx.x * 4 + wv) * TD_CPW;
+    // the column segments of this wave's outputs (clamped, always-valid
+    // addresses; terms past nq, and for BLK those with q <= i, are masked)
+    double v[TD_CPW][DBW / 64];
+#pragma unroll
+    for (int c = 0; c < TD_CPW; ++c) {
+        const double *colp = S + row0 + (col0 + min(i0 + c, ncols - 1)) * ng;
+#pragma unroll
+        for (int k = 0; k < DBW / 64; ++k) v[c][k] = colp[min(lane + 64 * k, nq - 1)];
+    }
+    for (int k0r = 0; k0r < nrhs; k0r += RB) {
+        const int nr = min(RB, nrhs - k0r);
+        const double *src = BLK ? in + row0 : w;
+        for (int idx = tid; idx < DBW * RB; idx += 256) {
+            const int q = idx / RB, r = idx % RB;
+            wb[idx] = (q < nq && r < nr) ? src[(int64_t)(k0r + r) * ng + q] : 0.0;
+        }
+        __syncthreads();
+        double acc[TD_CPW][RB];
+#pragma unroll
+        for (int c = 0; c < TD_CPW; ++c) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[c][r] = 0.0;
+#pragma unroll
+            for (int k = 0; k < DBW / 64; ++k) {
+                const int q = lane + 64 * k;
+                const bool ok = q < nq && (!BLK || q > i0 + c);
+                const double x = ok ? v[c][k] : 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) acc[c][r] += x * wb[min(q, DBW - 1) * RB + r];
+            }
+        }
+        // sums across the wave, in a fixed order
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+            for (int c = 0; c < TD_CPW; ++c)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) acc[c][r] += __shfl_xor(acc[c][r], off);
+        if (lane == 0)
+#pragma unroll
+            for (int c = 0; c < TD_CPW; ++c)
+                if (i0 + c < ncols)
+                    for (int r = 0; r < nr; ++r) {
+                        const int64_t o = (int64_t)(k0r + r) * ng + col0 + i0 + c;
+                        out[o] = BLK ? in[o] + acc[c][r] : out[o] - acc[c][r];
+                    }
         __syncthreads();
     }
 }
@@ -805,7 +870,7 @@ void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t
     for (int64_t j0 = 0; j0 < ng; j0 += DBW) {
         const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
         hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, j0,
-                           (const double *)v, y, (int)nrhs, 0);
+                           (const double *)v, y, (int)nrhs);
         const int64_t below = ng - j0 - nbw;
         if (below > 0)
             hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((below + GV_R - 1) / GV_R)), dim3(512), 0, st, S, ng, j0 + nbw,
@@ -815,13 +880,17 @@ void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t
 
 void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st) {
     hipLaunchKernelGGL(k_div_diag, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, S, ng, z, z, (int)nrhs);
+    constexpr int per_wg = 4 * TD_CPW;
     for (int64_t j0 = ((ng - 1) / DBW) * DBW; j0 >= 0; j0 -= DBW) {
-        const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
-        hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, j0,
-                           (const double *)z, x, (int)nrhs, 1);
+        const int nbw = (int)std::min<int64_t>(DBW, ng - j0);
+        // x_J = X_J^T z_J, then z_above -= L[J, above]^T x_J, both read down
+        // the columns of the stored lower triangle
+        hipLaunchKernelGGL(k_dense_tdot<true>, dim3((unsigned)((nbw + per_wg - 1) / per_wg)), dim3(256), 0, st, S,
+                           ng, j0, nbw, j0, nbw, (const double *)nullptr, (const double *)z, x, (int)nrhs);
         if (j0 > 0)
-            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((j0 + GV_R - 1) / GV_R)), dim3(512), 0, st, S, ng, (int64_t)0,
-                               j0, j0, (int)nbw, (const double *)(x + j0), z, (int)nrhs);
+            hipLaunchKernelGGL(k_dense_tdot<false>, dim3((unsigned)((j0 + per_wg - 1) / per_wg)), dim3(256), 0, st, S,
+                               ng, j0, nbw, (int64_t)0, (int)j0, (const double *)(x + j0), (const double *)nullptr, z,
+                               (int)nrhs);
     }
 }
 

@@ -118,7 +118,6 @@ void launch_schur_assemble(const void *U, int64_t Ustride, int64_t uoff, int64_t
                            double *amax_s, int mirror, hipStream_t st);
 void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t nb, int precision,
                       double *out, hipStream_t st);
-void launch_mirror_lower(double *S, int64_t ng, hipStream_t st);
 // inverse of the INV_W diagonal block at j0 of the (single) front fl[0]
 void launch_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, hipStream_t st);
 // the DENSE_INV_W diagonal-block inverses of the dense factor of one front
