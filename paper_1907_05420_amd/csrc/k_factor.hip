@@ -820,7 +820,7 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
 // double-buffered LDS (one barrier per chunk), epilogue through LDS in two
 // 64-column halves for a coalesced read-modify-write of the target.
 constexpr int BT = 128;      // tile edge
-constexpr int KC = 16;       // K chunk
+constexpr int KC = 8;        // K chunk
 constexpr int LD2 = BT + 16; // LDS leading dimension (bank spread)
 
 template <typename T>
@@ -828,6 +828,7 @@ __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const F
                                                        const int32_t *pre, int nf, int t0, int pe, int win) {
     typedef typename Acc<T>::type acc_t;
     __shared__ T smem[2 * 2 * KC * LD2];
+    static_assert(2 * 2 * KC * LD2 >= 32 * (BT + 1), "epilogue stage");
     const int fi = find_front(pre, nf, blockIdx.x);
     const FrontDesc d = sd[fl[fi]];
     const int n = blockIdx.y, tid = threadIdx.x;
@@ -901,21 +902,22 @@ __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const F
         if (ch + 1 < nch) sstore((ch + 1) & 1, (ch + 1) * KC);
         __syncthreads();
     }
-    // epilogue: two 64-column halves through LDS (128 x 64 stage, ld 129)
+    // epilogue: four 32-column quarters through LDS (128 x 32 stage, ld 129)
     T *sC = smem;
-    for (int half = 0; half < 2; ++half) {
-        if ((w & 1) == half) {
+#pragma unroll
+    for (int qt = 0; qt < 4; ++qt) {
+        if ((w & 1) == (qt >> 1)) {
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
+                for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr)
-                        sC[(wr + 16 * bi + mfma_row(T(0), lk, rr)) + (16 * bj + li) * (BT + 1)] = acc[bi][bj][rr];
+                        sC[(wr + 16 * bi + mfma_row(T(0), lk, rr)) + (16 * bb + li) * (BT + 1)] =
+                            acc[bi][2 * (qt & 1) + bb][rr];
         }
         __syncthreads();
-        rmw_sub_row<T, 16>(P, Ub, m, c, R0 + lrow, Q0 + 64 * half, lkk, 2, g.qhi, sC + lrow, BT + 1);
-        rmw_sub_row<T, 16>(P, Ub, m, c, R0 + lrow, Q0 + 64 * half, lkk + 32, 2, g.qhi, sC + lrow, BT + 1);
+        rmw_sub_row<T, 16>(P, Ub, m, c, R0 + lrow, Q0 + 32 * qt, lkk, 2, g.qhi, sC + lrow, BT + 1);
         __syncthreads();
     }
 }
