@@ -9,6 +9,7 @@
 // (du_g[n], sum_{m>n} du_g[m]) yields du_n = A_n^-1 (b_n - B_n^T du_g), i.e.
 // Eq. SCsolve1 with B_n^T du_g = C_1^T du_g[n] + C_0^T sum_{m>n} du_g[m] (Eq. B12N).
 // Vectors are FP64; factors are read in their stored precision.
+#include "dense_index.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -581,12 +582,12 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
 // then v_below -= L[below, J] y_J (rows of a column block); backward x_J =
 // X_J^T z_J then z_above -= L[J, above]^T x_J (dot products down columns).
 constexpr int DBW = DENSE_INV_W;  // the factor holds the inverses of its DBW-wide diagonal blocks
+static_assert(DBW == DENSE_BLOCK && RB == DS_RB, "dense solve geometry");
 
 // out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow
 // (ncol <= DBW): GV_R rows per workgroup, GV_G groups of 64 columns, reduced
-// at the end. All global loads of a workgroup are issued before the first use.
-constexpr int GV_G = DBW / 64;
-constexpr int GV_R = 512 / GV_G;
+// at the end (geometry and addresses in dense_index.hpp). All global loads of
+// a workgroup are issued before the first use.
 __global__ __launch_bounds__(512) void k_dense_gemv(const double *S, int64_t ng, int64_t row0, int64_t nrow,
                                                     int64_t col0, int ncol, const double *w, double *out,
                                                     int nrhs) {
@@ -599,10 +600,9 @@ __global__ __launch_bounds__(512) void k_dense_gemv(const double *S, int64_t ng,
     const int ncq = max(1, min(64, ncol - qa));
     // groups past the last column (a ragged last block) read, and then
     // ignore, that column: every address stays inside the factor
-    const double *rowp = S + row0 + min(i, nrow - 1) + (col0 + min(qa, ncol - 1)) * ng;
     double l[64];
 #pragma unroll
-    for (int u = 0; u < 64; ++u) l[u] = rowp[(int64_t)min(u, ncq - 1) * ng];
+    for (int u = 0; u < 64; ++u) l[u] = S[gemv_s_addr(ng, row0, nrow, col0, ncol, blockIdx.x, tid, u)];
     for (int k0r = 0; k0r < nrhs; k0r += RB) {
         const int nr = min(RB, nrhs - k0r);
         double o[RB] = {0.0, 0.0, 0.0, 0.0};
@@ -640,8 +640,7 @@ __global__ __launch_bounds__(512) void k_dense_gemv(const double *S, int64_t ng,
 
 // Forward in-block product with the stored inverse of diagonal block
 // [j0, j0 + nbw): out[j0 + i] = in[j0 + i] + sum_{q < i} X_J[i][q] in[j0 + q].
-// 16 rows per workgroup, 16 groups of DBW/16 columns.
-constexpr int BK_C = DBW / 16;
+// 16 rows per workgroup, 16 groups of BK_C columns.
 __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, int64_t j0, const double *in,
                                                    double *out, int nrhs) {
     __shared__ double vb[DBW * RB];
@@ -650,15 +649,13 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
     const int nbw = (int)min((int64_t)DBW, ng - j0);
     const int rl = tid & 15, g = tid >> 4;
     const int i = blockIdx.x * 16 + rl;
-    const int q0 = min(BK_C * g, nbw - 1);
-    const double *rowp = S + j0 + min(i, nbw - 1) + (j0 + q0) * ng;
     // only the groups with a column left of the diagonal read the factor
     // (the strict lower triangle: half of the block)
     const bool used = BK_C * g < i;
     double l[BK_C];
     if (used) {
 #pragma unroll
-        for (int u = 0; u < BK_C; ++u) l[u] = rowp[(int64_t)min(u, nbw - 1 - q0) * ng];
+        for (int u = 0; u < BK_C; ++u) l[u] = S[blk_s_addr(ng, j0, nbw, blockIdx.x, tid, u)];
     } else {
 #pragma unroll
         for (int u = 0; u < BK_C; ++u) l[u] = 0.0;
@@ -702,7 +699,6 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
 //   BLK false: out[col0 + i] -= sum_{q < nq} S[row0 + q, col0 + i] w[q]
 //   BLK true (row0 = col0 = j0, the in-block product with X_J^T):
 //              out[j0 + i] = in[j0 + i] + sum_{i < q < nq} S[j0 + q, j0 + i] in[j0 + q]
-constexpr int TD_CPW = 2;
 template <bool BLK>
 __global__ __launch_bounds__(256) void k_dense_tdot(const double *S, int64_t ng, int64_t row0, int nq, int64_t col0,
                                                     int ncols, const double *w, const double *in, double *out,
@@ -714,11 +710,9 @@ __global__ __launch_bounds__(256) void k_dense_tdot(const double *S, int64_t ng,
     // addresses; terms past nq, and for BLK those with q <= i, are masked)
     double v[TD_CPW][DBW / 64];
 #pragma unroll
-    for (int c = 0; c < TD_CPW; ++c) {
-        const double *colp = S + row0 + (col0 + min(i0 + c, ncols - 1)) * ng;
+    for (int c = 0; c < TD_CPW; ++c)
 #pragma unroll
-        for (int k = 0; k < DBW / 64; ++k) v[c][k] = colp[min(lane + 64 * k, nq - 1)];
-    }
+        for (int k = 0; k < DBW / 64; ++k) v[c][k] = S[tdot_s_addr(ng, row0, nq, col0, ncols, blockIdx.x, wv, c, lane, k)];
     for (int k0r = 0; k0r < nrhs; k0r += RB) {
         const int nr = min(RB, nrhs - k0r);
         const double *src = BLK ? in + row0 : w;
@@ -869,26 +863,25 @@ void launch_border_values(const double *xg, SolveArgs sa, int64_t nA, int64_t Ns
 void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st) {
     for (int64_t j0 = 0; j0 < ng; j0 += DBW) {
         const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
-        hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)((nbw + 15) / 16)), dim3(256), 0, st, S, ng, j0,
+        hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)blk_grid((int)nbw)), dim3(256), 0, st, S, ng, j0,
                            (const double *)v, y, (int)nrhs);
         const int64_t below = ng - j0 - nbw;
         if (below > 0)
-            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)((below + GV_R - 1) / GV_R)), dim3(512), 0, st, S, ng, j0 + nbw,
+            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)gemv_grid(below)), dim3(512), 0, st, S, ng, j0 + nbw,
                                below, j0, (int)nbw, (const double *)(y + j0), v, (int)nrhs);
     }
 }
 
 void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st) {
     hipLaunchKernelGGL(k_div_diag, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, S, ng, z, z, (int)nrhs);
-    constexpr int per_wg = 4 * TD_CPW;
     for (int64_t j0 = ((ng - 1) / DBW) * DBW; j0 >= 0; j0 -= DBW) {
         const int nbw = (int)std::min<int64_t>(DBW, ng - j0);
         // x_J = X_J^T z_J, then z_above -= L[J, above]^T x_J, both read down
         // the columns of the stored lower triangle
-        hipLaunchKernelGGL(k_dense_tdot<true>, dim3((unsigned)((nbw + per_wg - 1) / per_wg)), dim3(256), 0, st, S,
+        hipLaunchKernelGGL(k_dense_tdot<true>, dim3((unsigned)tdot_grid(nbw)), dim3(256), 0, st, S,
                            ng, j0, nbw, j0, nbw, (const double *)nullptr, (const double *)z, x, (int)nrhs);
         if (j0 > 0)
-            hipLaunchKernelGGL(k_dense_tdot<false>, dim3((unsigned)((j0 + per_wg - 1) / per_wg)), dim3(256), 0, st, S,
+            hipLaunchKernelGGL(k_dense_tdot<false>, dim3((unsigned)tdot_grid(j0)), dim3(256), 0, st, S,
                                ng, j0, nbw, (int64_t)0, (int)j0, (const double *)(x + j0), (const double *)nullptr, z,
                                (int)nrhs);
     }
