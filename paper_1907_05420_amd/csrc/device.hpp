@@ -54,6 +54,20 @@ __device__ inline v4f mfma16x16x4(float a, float b, v4f c) {
 __device__ inline int mfma_row(double, int lk, int rr) { return lk + 4 * rr; }
 __device__ inline int mfma_row(float, int lk, int rr) { return 4 * lk + rr; }
 
+// Raw buffer access (stride 0): loads at byte offsets past `bytes` return
+// zero. Word 3 of the descriptor selects 32-bit data without swizzling.
+typedef __amdgpu_buffer_rsrc_t BufRes;
+__device__ inline BufRes make_bufres(const void *base, int64_t bytes) {
+    const int nr = bytes < 0x7fffffff ? (int)bytes : 0x7fffffff;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, nr, 0x00020000);
+}
+__device__ inline double buf_load(BufRes r, int off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline float buf_load(BufRes r, int off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 template <typename T> struct Acc;
 template <> struct Acc<double> { typedef v4d type; };
 template <> struct Acc<float> { typedef v4f type; };

@@ -816,19 +816,24 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
 }
 
 // Trailing update after an outer panel (kind 3) on 128x128 tiles: four waves
-// of 64x64 (4x4 MFMA 16x16x4 blocks each), K in chunks of 16 staged through
-// double-buffered LDS (one barrier per chunk), epilogue through LDS in two
-// 64-column halves for a coalesced read-modify-write of the target.
+// of 64x64 (4x4 MFMA 16x16x4 blocks each). No LDS and no barrier in the main
+// loop: every lane loads its own MFMA operands (rows of the panel, one K step
+// of 4 per slot) with buffer loads into a ring of UPF register slots, so each
+// wave runs on its own and the loads of later steps are in flight while the
+// current one is multiplied. Buffer loads (intrinsic calls) keep the ring: a
+// plain load feeding a loop-carried value is folded into the next iteration.
+// Columns past the panel's K read as zero through the buffer's range check.
+// The epilogue goes through LDS in four 32-column quarters for a coalesced
+// read-modify-write of the target.
 constexpr int BT = 128;      // tile edge
-constexpr int KC = 8;        // K chunk
-constexpr int LD2 = BT + 16; // LDS leading dimension (bank spread)
+constexpr int UPF = 3;       // K steps in flight per lane
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl,
                                                        const int32_t *pre, int nf, int t0, int pe, int win) {
     typedef typename Acc<T>::type acc_t;
-    __shared__ T smem[2 * 2 * KC * LD2];
-    static_assert(2 * 2 * KC * LD2 >= 32 * (BT + 1), "epilogue stage");
+    __shared__ T sC[32 * (BT + 1)];
+    __shared__ T sD[MAX_OUTER_W + 4 * UPF];
     const int fi = find_front(pre, nf, blockIdx.x);
     const FrontDesc d = sd[fl[fi]];
     const int n = blockIdx.y, tid = threadIdx.x;
@@ -849,61 +854,49 @@ __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const F
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
-    // pivots D of the K range, staged once (K <= MAX_OUTER_W)
-    __shared__ T sD[MAX_OUTER_W];
-    for (int k = tid; k < g.K; k += 256) sD[k] = P[(t0 + k) + (int64_t)(t0 + k) * m];
-    // loader: row = tid % 128, k = tid / 128 + 2 j (j < 8); clamped addresses,
-    // no arithmetic on the loaded values until they are stored to LDS, so the
-    // loads of the next chunk stay in flight during the MFMA loop
-    const int lrow = tid & (BT - 1), lkk = tid >> 7;
-    const bool arow = R0 + lrow < m, brow = Q0 + lrow < m;
-    const T *Pa = P + min(R0 + lrow, m - 1), *Pb = P + min(Q0 + lrow, m - 1);
-    T ra[KC / 2], rb[KC / 2];
-    auto gload = [&](int kc) {
-#pragma unroll
-        for (int j = 0; j < KC / 2; ++j) {
-            const int k = min(kc + lkk + 2 * j, g.K - 1);
-            const int64_t col = (int64_t)(t0 + k) * m;
-            ra[j] = Pa[col];
-            rb[j] = Pb[col];
-        }
-    };
-    auto sstore = [&](int buf, int kc) {
-        T *sA = smem + buf * 2 * KC * LD2, *sB = sA + KC * LD2;
-#pragma unroll
-        for (int j = 0; j < KC / 2; ++j) {
-            const int k = kc + lkk + 2 * j;
-            const bool ok = k < g.K;
-            sA[(lkk + 2 * j) * LD2 + lrow] = (ok && arow) ? ra[j] * sD[ok ? k : 0] : T(0);
-            sB[(lkk + 2 * j) * LD2 + lrow] = (ok && brow) ? rb[j] : T(0);
-        }
-    };
-    const int nch = (g.K + KC - 1) / KC;
-    gload(0);
-    __syncthreads();  // sD
-    sstore(0, 0);
+    // pivots D of the K range (K <= MAX_OUTER_W), zero past K
+    const int nks = (g.K + 3) / 4;                     // K steps of 4
+    const int nkp = ((nks + UPF - 1) / UPF) * UPF;     // padded to the ring
+    for (int k = tid; k < 4 * nkp; k += 256) sD[k] = k < g.K ? P[(t0 + k) + (int64_t)(t0 + k) * m] : T(0);
     __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) gload((ch + 1) * KC);
-        const T *sA = smem + (ch & 1) * 2 * KC * LD2, *sB = sA + KC * LD2;
+    // the panel's K columns as one buffer; lane offsets of its four A rows
+    // and four B rows (rows past the front clamped) in column lk
+    const BufRes rs = make_bufres(P + (int64_t)t0 * m, (int64_t)g.K * m * (int64_t)sizeof(T));
+    int oa[4], ob[4];
 #pragma unroll
-        for (int k = 0; k < KC; k += 4) {
-            T a[4], b[4];
+    for (int x = 0; x < 4; ++x) {
+        oa[x] = (int)sizeof(T) * (min(R0 + wr + 16 * x + li, m - 1) + lk * m);
+        ob[x] = (int)sizeof(T) * (min(Q0 + wc + 16 * x + li, m - 1) + lk * m);
+    }
+    const int step = (int)sizeof(T) * 4 * m;
+    T ra[UPF][4], rb[UPF][4];
+    auto load = [&](int slot, int ks) {
+        const int co = step * ks;
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                a[x] = sA[(k + lk) * LD2 + wr + 16 * x + li];
-                b[x] = sB[(k + lk) * LD2 + wc + 16 * x + li];
-            }
+        for (int x = 0; x < 4; ++x) {
+            ra[slot][x] = buf_load(rs, oa[x] + co, T(0));
+            rb[slot][x] = buf_load(rs, ob[x] + co, T(0));
+        }
+    };
+#pragma unroll
+    for (int sl = 0; sl < UPF - 1; ++sl) load(sl, sl);
+    for (int ks0 = 0; ks0 < nkp; ks0 += UPF) {
+#pragma unroll
+        for (int sl = 0; sl < UPF; ++sl) {
+            const int ks = ks0 + sl;
+            load((sl + UPF - 1) % UPF, ks + UPF - 1);
+            const T dk = sD[4 * ks + lk];
+            T a[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[x] = ra[sl][x] * dk;
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16x16x4(a[bi], b[bj], acc[bi][bj]);
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16x16x4(a[bi], rb[sl][bj], acc[bi][bj]);
         }
-        if (ch + 1 < nch) sstore((ch + 1) & 1, (ch + 1) * KC);
-        __syncthreads();
     }
+    const int lrow = tid & (BT - 1), lkk = tid >> 7;
     // epilogue: four 32-column quarters through LDS (128 x 32 stage, ld 129)
-    T *sC = smem;
 #pragma unroll
     for (int qt = 0; qt < 4; ++qt) {
         if ((w & 1) == (qt >> 1)) {
