@@ -287,13 +287,15 @@ void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl
             add(big ? 4 : 3, k, pe);
             continue;
         }
-        // the panel is factored: the side stream may update the columns
-        // beyond the next panel with it (after its own previous update)
-        sync(SYNC_TO_SIDE);
         // the next panel's columns: the side stream's update from the
         // previous panel must be done before this panel's update of them
         if (k > 0) sync(SYNC_TO_MAIN);
         add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
+        // the side stream updates the columns beyond the next panel once the
+        // main stream's update of the next panel's columns is done: started
+        // together, the large update takes the compute units first and the
+        // next panel (the critical path) waits behind it
+        sync(SYNC_TO_SIDE);
         add(big ? 4 : 3, k, pe, 2, 1);  // the rest, side stream
     }
     if (lookahead) sync(SYNC_TO_MAIN);
