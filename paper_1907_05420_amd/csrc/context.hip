@@ -106,6 +106,7 @@ struct kkt_ctx {
     double dw = 0.0, dc = 0.0;
     double *d_S = nullptr, *d_prefix = nullptr, *d_tauS = nullptr, *d_amaxS = nullptr;
     double *d_invtmp = nullptr;  // staging of the block-inverse combinations
+    int *d_dsync = nullptr;      // dense Schur solves: [0] failure flag, then the step counters
     // structured Schur (section 4.3): the N fronts [A_j; B_j] (2 Ns x Ns, ld
     // 2 Ns; Ns x Ns for the last), G_j = W_j Linv_j and its transpose, the
     // running U_j and the update block of the current front, and the solve's
@@ -595,6 +596,8 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         for (int64_t W = INV_W; 2 * W <= DENSE_INV_W; W *= 2)
             tmp = std::max(tmp, W * W * ((ctx->ng + 2 * W - 1) / (2 * W)));
         if ((rc = dalloc(ctx, (void **)&ctx->d_invtmp, 8 * tmp))) return rc;
+        const int64_t nblk = (ctx->ng + DENSE_INV_W - 1) / DENSE_INV_W;
+        if ((rc = dalloc(ctx, (void **)&ctx->d_dsync, 4 * (1 + 2 * nblk)))) return rc;
     }
     return KKT_OK;
 }
@@ -908,8 +911,8 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
             launch_struct_solve(ctx->d_sfront, ctx->d_sG, ctx->d_sGT, ctx->d_sM, ctx->d_sMT, ctx->N, S.Ns, ctx->d_bh,
                                 ctx->d_xg, ctx->d_ssa, ctx->d_saa, ctx->d_sce, nrhs, st);
         } else {
-            launch_dense_fwd(ctx->d_S, ctx->ng, ctx->d_bh, ctx->d_y, nrhs, st);
-            launch_dense_bwd(ctx->d_S, ctx->ng, ctx->d_y, ctx->d_xg, nrhs, st);
+            launch_dense_fwd(ctx->d_S, ctx->ng, ctx->d_bh, ctx->d_y, nrhs, ctx->d_dsync, st);
+            launch_dense_bwd(ctx->d_S, ctx->ng, ctx->d_y, ctx->d_xg, nrhs, ctx->d_dsync, st);
         }
         launch_border_values(ctx->d_xg, sa, S.nA, S.Ns, st);
     }
@@ -1446,6 +1449,19 @@ int refine_fgmres(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, Refine
 
 }  // namespace
 
+namespace {
+// a dense Schur solve step whose in-block product waited past its bound
+// (the wait between the workgroups of one launch); synchronises
+bool dense_wait_failed(kkt_ctx *ctx) {
+    if (!ctx->d_dsync) return false;
+    int f = 0;
+    if (hipMemcpyAsync(&f, ctx->d_dsync, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return true;
+    return f != 0;
+}
+}  // namespace
+
 extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, kkt_solve_info *info) {
     if (!ctx) return KKT_ERR_ARG;
     if (!ctx->analyzed || !ctx->factored) return KKT_ERR_ORDER;
@@ -1471,6 +1487,7 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
         if (flag) return KKT_ERR_NONFINITE;
     }
     mark(ctx, 4);
+    if (ctx->d_dsync) launch_zero<int>(ctx->d_dsync, 1, st);
     rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
     if (rc) return rc;
     RefineState rs;
@@ -1485,6 +1502,7 @@ extern "C" int kkt_solve(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs,
         HIPCHK(hipStreamSynchronize(st));
         ctx->times[3] = elapsed(ctx, 4, 5);
     }
+    if (dense_wait_failed(ctx)) return KKT_ERR_HIP;
     if (mixed && rs.status == KKT_WARN_REFINE) {
         // refinement around the FP32 factor stopped above the target:
         // factor the same values in FP64 and solve again with that factor
@@ -1521,6 +1539,7 @@ int solve_fixed_steps(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs, in
     // a non-finite right-hand side is recorded for kkt_solve_status
     launch_zero<int>(ctx->d_flag + 1, 1, st);
     launch_check_finite(b, ctx->ntot * nrhs, ctx->d_flag + 1, st);
+    if (ctx->d_dsync) launch_zero<int>(ctx->d_dsync, 1, st);
     int rc = mixed ? solve_once<float>(ctx, b, x, nrhs) : solve_once<double>(ctx, b, x, nrhs);
     if (rc) return rc;
     ResidualArgs ra = residual_args(ctx, nrhs);
@@ -1649,6 +1668,7 @@ extern "C" int kkt_solve_status(kkt_ctx *ctx, kkt_solve_info *info) {
     HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (flag) return KKT_ERR_NONFINITE;
+    if (dense_wait_failed(ctx)) return KKT_ERR_HIP;
     double rel = 0.0, omega = 0.0, fl = 0.0;
     for (int64_t k = 0; k < nrhs; ++k) {
         const double bn = nh[4 * k + 1] > 0 ? nh[4 * k + 1] : 1.0;

@@ -38,13 +38,12 @@ __host__ __device__ inline int64_t gemv_s_addr(int64_t ng, int64_t row0, int64_t
     return row0 + ds_min(i, nrow - 1) + (col0 + ds_min(qa, ncol - 1) + ds_min(u, ncq - 1)) * ng;
 }
 
-// Forward in-block product out[j0 + i] = in[j0 + i] + sum_{q < i} X[i][q]
-// in[j0 + q] (i < nbw): 256 threads, 16 rows by 16 groups of BK_C columns.
-constexpr int BK_C = DENSE_BLOCK / 16;
-__host__ __device__ inline int64_t blk_s_addr(int64_t ng, int64_t j0, int nbw, int64_t blk, int tid, int u) {
-    const int64_t i = blk * 16 + (tid & 15);
-    const int64_t q0 = ds_min((int64_t)BK_C * (tid >> 4), nbw - 1);
-    return j0 + ds_min(i, nbw - 1) + (j0 + q0 + ds_min(u, nbw - 1 - q0)) * ng;
+// The forward in-block product out[j0 + i] = in[j0 + i] + sum_{q < i}
+// X[i][q] in[j0 + q] (i < nbw) takes the same geometry and addresses with
+// row0 = col0 = j0, nrow = ncol = nbw; a column group loads only if it has a
+// column left of the row's diagonal (64 g < i).
+__host__ __device__ inline bool gemv_tri_used(int64_t blk, int tid) {
+    return 64 * (tid / GV_R) < blk * GV_R + tid % GV_R;
 }
 
 // Backward products with the transpose, as dot products down the columns:
@@ -59,7 +58,22 @@ __host__ __device__ inline int64_t tdot_s_addr(int64_t ng, int64_t row0, int nq,
 
 // workgroups of each launch
 __host__ __device__ inline int64_t gemv_grid(int64_t nrow) { return (nrow + GV_R - 1) / GV_R; }
-__host__ __device__ inline int64_t blk_grid(int nbw) { return (nbw + 15) / 16; }
 __host__ __device__ inline int64_t tdot_grid(int64_t ncols) { return (ncols + 4 * TD_CPW - 1) / (4 * TD_CPW); }
+
+// One launch per block step joins a product below or above a block with the
+// next block's in-block product. Forward step after block [j0, j1): row
+// workgroups 0 .. gemv_grid(ng - j1) - 1 (the first gemv_grid(nbw1) of them
+// cover the next block [j1, j1 + nbw1)), then gemv_grid(nbw1) workgroups of
+// the next block's in-block product. Backward step before block [j0 - DB,
+// j0): the product with block [j0, ..) over the columns [0, j0) in reverse
+// order of workgroups (workgroup b takes tdot block tdot_grid(j0) - 1 - b, so
+// the first tdot_grid(DB) of them cover the columns of block [j0 - DB, j0)),
+// then tdot_grid(DB) workgroups of that block's in-block product.
+__host__ __device__ inline int64_t fwd_step_grid(int64_t ng, int64_t j1) {
+    return gemv_grid(ng - j1) + gemv_grid(ds_min(DENSE_BLOCK, ng - j1));
+}
+__host__ __device__ inline int64_t bwd_step_grid(int64_t j0) {
+    return tdot_grid(j0) + tdot_grid(DENSE_BLOCK);
+}
 
 }  // namespace kkt

@@ -584,42 +584,79 @@ __global__ void k_border_values(const double *xg, SolveArgs sa, int64_t nA, int6
 constexpr int DBW = DENSE_INV_W;  // the factor holds the inverses of its DBW-wide diagonal blocks
 static_assert(DBW == DENSE_BLOCK && RB == DS_RB, "dense solve geometry");
 
-// out[i] -= sum_{q < ncol} S[(row0 + i) + (col0 + q) ng] w[q] for i < nrow
-// (ncol <= DBW): GV_R rows per workgroup, GV_G groups of 64 columns, reduced
-// at the end (geometry and addresses in dense_index.hpp). All global loads of
-// a workgroup are issued before the first use.
-__global__ __launch_bounds__(512) void k_dense_gemv(const double *S, int64_t ng, int64_t row0, int64_t nrow,
-                                                    int64_t col0, int ncol, const double *w, double *out,
-                                                    int nrhs) {
-    __shared__ double wb[DBW * RB];
-    __shared__ double red[GV_G * GV_R * RB];
+// Signals between the workgroups of one launch. A producer workgroup, once
+// its outputs are stored, adds one to a counter with an agent-scope release
+// (its stores become visible to every XCD before the add); a consumer
+// workgroup waits with agent-scope acquires until the counter reaches the
+// number of producers. Producers never wait and come first in the
+// launch's workgroup order, so they are all dispatched before any consumer
+// and every wait ends; the wait is still bounded (about a second), after
+// which the consumer sets the launch's failure flag and leaves its outputs
+// unwritten.
+constexpr int WAIT_LIMIT = 1 << 22;
+__device__ __forceinline__ void signal_done(int *cnt) {
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool wait_done(int *cnt, int need, int *flag) {
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        // relaxed polling (no cache invalidation per poll, which would
+        // evict the producers' operands), one acquire once the count is in
+        int it = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need && it < WAIT_LIMIT) {
+            __builtin_amdgcn_s_sleep(4);
+            ++it;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok = it < WAIT_LIMIT;
+        if (!ok) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// Row product of workgroup `blk` (GV_R rows, GV_G groups of 64 columns,
+// reduced at the end; geometry and addresses in dense_index.hpp; all global
+// loads of a workgroup are issued before the first use):
+//   TRI false: out[row0 + i] -= sum_{q < ncol} S[row0 + i, col0 + q] w[q],
+//   TRI true (row0 = col0, nrow = ncol, w = in + col0, the in-block product
+//   with the stored inverse): out[row0 + i] = in[row0 + i] + sum_{q < i}
+//   S[row0 + i, row0 + q] in[row0 + q], loading only the groups left of the
+//   diagonal.
+__device__ __forceinline__ void gemv_body(bool TRI, const double *S, int64_t ng, int64_t row0, int64_t nrow,
+                                          int64_t col0, int ncol, const double *w, const double *in, double *out,
+                                          int nrhs, int64_t blk, double *wb, double *red) {
     const int tid = threadIdx.x;
     const int a = tid % GV_R, g = tid / GV_R;
-    const int64_t i = (int64_t)blockIdx.x * GV_R + a;
+    const int64_t i = blk * GV_R + a;
     const int qa = 64 * g;
     const int ncq = max(1, min(64, ncol - qa));
+    const bool used = TRI ? gemv_tri_used(blk, tid) : true;
+    // terms u < nu of this thread's group are used (for TRI: left of the diagonal)
+    const int nu = TRI ? (int)max((int64_t)0, min((int64_t)ncq, i - qa)) : ncq;
     // groups past the last column (a ragged last block) read, and then
     // ignore, that column: every address stays inside the factor
     double l[64];
+    if (used) {
 #pragma unroll
-    for (int u = 0; u < 64; ++u) l[u] = S[gemv_s_addr(ng, row0, nrow, col0, ncol, blockIdx.x, tid, u)];
+        for (int u = 0; u < 64; ++u) l[u] = S[gemv_s_addr(ng, row0, nrow, col0, ncol, blk, tid, u)];
+    } else {
+#pragma unroll
+        for (int u = 0; u < 64; ++u) l[u] = 0.0;
+    }
     for (int k0r = 0; k0r < nrhs; k0r += RB) {
         const int nr = min(RB, nrhs - k0r);
-        double o[RB] = {0.0, 0.0, 0.0, 0.0};
-        if (g == 0 && i < nrow)
-#pragma unroll
-            for (int rr = 0; rr < RB; ++rr)
-                if (rr < nr) o[rr] = out[(int64_t)(k0r + rr) * ng + row0 + i];
         for (int idx = tid; idx < DBW * RB; idx += 512) {
             const int q = idx / RB, r = idx % RB;
             wb[idx] = (q < ncol && r < nr) ? w[(int64_t)(k0r + r) * ng + q] : 0.0;
         }
         __syncthreads();
         double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-        if (qa < ncol) {
+        if (qa < ncol && used) {
 #pragma unroll
             for (int u = 0; u < 64; ++u) {
-                const double x = u < ncq ? l[u] : 0.0;
+                const double x = u < nu ? l[u] : 0.0;
 #pragma unroll
                 for (int rr = 0; rr < RB; ++rr) acc[rr] += x * wb[(qa + min(u, ncq - 1)) * RB + rr];
             }
@@ -632,62 +669,38 @@ __global__ __launch_bounds__(512) void k_dense_gemv(const double *S, int64_t ng,
                 double t = 0.0;
 #pragma unroll
                 for (int gg = 0; gg < GV_G; ++gg) t += red[(gg * GV_R + a) * RB + rr];
-                out[(int64_t)(k0r + rr) * ng + row0 + i] = o[rr] - t;
+                const int64_t o = (int64_t)(k0r + rr) * ng + row0 + i;
+                out[o] = TRI ? in[o] + t : out[o] - t;
             }
         __syncthreads();
     }
 }
 
-// Forward in-block product with the stored inverse of diagonal block
-// [j0, j0 + nbw): out[j0 + i] = in[j0 + i] + sum_{q < i} X_J[i][q] in[j0 + q].
-// 16 rows per workgroup, 16 groups of BK_C columns.
-__global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, int64_t j0, const double *in,
+// In-block product of the first block (the other blocks' in-block products
+// run inside the forward step launches)
+__global__ __launch_bounds__(512) void k_dense_tri(const double *S, int64_t ng, int64_t j0, int nbw, const double *in,
                                                    double *out, int nrhs) {
-    __shared__ double vb[DBW * RB];
-    __shared__ double red[16 * 16 * RB];
-    const int tid = threadIdx.x;
-    const int nbw = (int)min((int64_t)DBW, ng - j0);
-    const int rl = tid & 15, g = tid >> 4;
-    const int i = blockIdx.x * 16 + rl;
-    // only the groups with a column left of the diagonal read the factor
-    // (the strict lower triangle: half of the block)
-    const bool used = BK_C * g < i;
-    double l[BK_C];
-    if (used) {
-#pragma unroll
-        for (int u = 0; u < BK_C; ++u) l[u] = S[blk_s_addr(ng, j0, nbw, blockIdx.x, tid, u)];
-    } else {
-#pragma unroll
-        for (int u = 0; u < BK_C; ++u) l[u] = 0.0;
-    }
-    for (int k0r = 0; k0r < nrhs; k0r += RB) {
-        const int nr = min(RB, nrhs - k0r);
-        for (int idx = tid; idx < DBW * RB; idx += 256) {
-            const int q = idx / RB, r = idx % RB;
-            vb[idx] = (q < nbw && r < nr) ? in[(int64_t)(k0r + r) * ng + j0 + q] : 0.0;
-        }
-        __syncthreads();
-        double acc[RB] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int u = 0; u < BK_C; ++u) {
-            const int q = BK_C * g + u;
-            const bool ok = q < nbw && q < i;
-            const double x = ok ? l[u] : 0.0;
-#pragma unroll
-            for (int rr = 0; rr < RB; ++rr) acc[rr] += x * vb[min(q, DBW - 1) * RB + rr];
-        }
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) red[(g * 16 + rl) * RB + rr] = acc[rr];
-        __syncthreads();
-        if (g == 0 && i < nbw)
-            for (int rr = 0; rr < nr; ++rr) {
-                double t = vb[i * RB + rr];
-#pragma unroll
-                for (int gg = 0; gg < 16; ++gg) t += red[(gg * 16 + rl) * RB + rr];
-                out[(int64_t)(k0r + rr) * ng + j0 + i] = t;
-            }
-        __syncthreads();
-    }
+    __shared__ double wb[DBW * RB];
+    __shared__ double red[GV_G * GV_R * RB];
+    gemv_body(true, S, ng, j0, nbw, j0, nbw, in + j0, in, out, nrhs, blockIdx.x, wb, red);
+}
+
+// Forward step after block [j0, j0 + nbw), whose y_J is final: v_below -=
+// L[below, J] y_J, then the next block's in-block product y = X v on it by
+// the last workgroups, once the workgroups of its rows have stored them.
+__global__ __launch_bounds__(512) void k_dense_fwd_step(const double *S, int64_t ng, int64_t j0, int nbw, double *v,
+                                                        double *y, int nrhs, int *cnt, int *flag) {
+    __shared__ double wb[DBW * RB];
+    __shared__ double red[GV_G * GV_R * RB];
+    const int64_t j1 = j0 + nbw, below = ng - j1;
+    const int nbw1 = (int)min((int64_t)DBW, below);
+    const int64_t G = gemv_grid(below), P = gemv_grid(nbw1);
+    const int64_t b = blockIdx.x;
+    const bool tri = b >= G;
+    if (tri && !wait_done(cnt, (int)P, flag)) return;
+    gemv_body(tri, S, ng, j1, tri ? nbw1 : below, tri ? j1 : j0, tri ? nbw1 : nbw, tri ? v + j1 : y + j0, v,
+              tri ? y : v, nrhs, tri ? b - G : b, wb, red);
+    if (b < P) signal_done(cnt);
 }
 
 // Products with the transpose of the stored lower triangle, for the
@@ -700,19 +713,17 @@ __global__ __launch_bounds__(256) void k_dense_blk(const double *S, int64_t ng, 
 //   BLK true (row0 = col0 = j0, the in-block product with X_J^T):
 //              out[j0 + i] = in[j0 + i] + sum_{i < q < nq} S[j0 + q, j0 + i] in[j0 + q]
 template <bool BLK>
-__global__ __launch_bounds__(256) void k_dense_tdot(const double *S, int64_t ng, int64_t row0, int nq, int64_t col0,
-                                                    int ncols, const double *w, const double *in, double *out,
-                                                    int nrhs) {
-    __shared__ double wb[DBW * RB];
+__device__ __forceinline__ void tdot_body(const double *S, int64_t ng, int64_t row0, int nq, int64_t col0, int ncols,
+                                 const double *w, const double *in, double *out, int nrhs, int64_t blk, double *wb) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int i0 = ((int)blockIdx.x * 4 + wv) * TD_CPW;
+    const int i0 = ((int)blk * 4 + wv) * TD_CPW;
     // the column segments of this wave's outputs (clamped, always-valid
     // addresses; terms past nq, and for BLK those with q <= i, are masked)
     double v[TD_CPW][DBW / 64];
 #pragma unroll
     for (int c = 0; c < TD_CPW; ++c)
 #pragma unroll
-        for (int k = 0; k < DBW / 64; ++k) v[c][k] = S[tdot_s_addr(ng, row0, nq, col0, ncols, blockIdx.x, wv, c, lane, k)];
+        for (int k = 0; k < DBW / 64; ++k) v[c][k] = S[tdot_s_addr(ng, row0, nq, col0, ncols, blk, wv, c, lane, k)];
     for (int k0r = 0; k0r < nrhs; k0r += RB) {
         const int nr = min(RB, nrhs - k0r);
         const double *src = BLK ? in + row0 : w;
@@ -751,6 +762,33 @@ __global__ __launch_bounds__(256) void k_dense_tdot(const double *S, int64_t ng,
                         out[o] = BLK ? in[o] + acc[c][r] : out[o] - acc[c][r];
                     }
         __syncthreads();
+    }
+}
+
+template <bool BLK>
+__global__ __launch_bounds__(256) void k_dense_tdot(const double *S, int64_t ng, int64_t row0, int nq, int64_t col0,
+                                                    int ncols, const double *w, const double *in, double *out,
+                                                    int nrhs) {
+    __shared__ double wb[DBW * RB];
+    tdot_body<BLK>(S, ng, row0, nq, col0, ncols, w, in, out, nrhs, blockIdx.x, wb);
+}
+
+// Backward step with block [j0, j0 + nbw), whose x_J is final: z_above -=
+// L[J, above]^T x_J over the columns [0, j0) (last columns first), then the
+// in-block product x = X^T z of block [j0 - DBW, j0) by the last
+// workgroups, once the workgroups of its columns have stored them.
+__global__ __launch_bounds__(256) void k_dense_bwd_step(const double *S, int64_t ng, int64_t j0, int nbw, double *z,
+                                                        double *x, int nrhs, int *cnt, int *flag) {
+    __shared__ double wb[DBW * RB];
+    const int64_t G = tdot_grid(j0), P = tdot_grid(DBW);
+    const int64_t b = blockIdx.x;
+    if (b < G) {
+        tdot_body<false>(S, ng, j0, nbw, 0, (int)j0, x + j0, nullptr, z, nrhs, G - 1 - b, wb);
+        if (b < P) signal_done(cnt);
+    } else {
+        if (!wait_done(cnt, (int)P, flag)) return;
+        const int64_t jp = j0 - DBW;
+        tdot_body<true>(S, ng, jp, DBW, jp, DBW, nullptr, z, x, nrhs, b - G, wb);
     }
 }
 
@@ -860,30 +898,35 @@ void launch_border_values(const double *xg, SolveArgs sa, int64_t nA, int64_t Ns
                        xg, sa, nA, Ns);
 }
 
-void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st) {
-    for (int64_t j0 = 0; j0 < ng; j0 += DBW) {
-        const int64_t nbw = std::min<int64_t>(DBW, ng - j0);
-        hipLaunchKernelGGL(k_dense_blk, dim3((unsigned)blk_grid((int)nbw)), dim3(256), 0, st, S, ng, j0,
-                           (const double *)v, y, (int)nrhs);
-        const int64_t below = ng - j0 - nbw;
-        if (below > 0)
-            hipLaunchKernelGGL(k_dense_gemv, dim3((unsigned)gemv_grid(below)), dim3(512), 0, st, S, ng, j0 + nbw,
-                               below, j0, (int)nbw, (const double *)(y + j0), v, (int)nrhs);
+void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, int *sync, hipStream_t st) {
+    const int64_t nblk = (ng + DBW - 1) / DBW;
+    if (nblk > 1) launch_zero<int>(sync + 1, 2 * (nblk - 1), st);
+    const int nbw0 = (int)std::min<int64_t>(DBW, ng);
+    hipLaunchKernelGGL(k_dense_tri, dim3((unsigned)gemv_grid(nbw0)), dim3(512), 0, st, S, ng, (int64_t)0, nbw0,
+                       (const double *)v, y, (int)nrhs);
+    for (int64_t k = 0; k + 1 < nblk; ++k) {
+        const int64_t j0 = k * DBW;
+        hipLaunchKernelGGL(k_dense_fwd_step, dim3((unsigned)fwd_step_grid(ng, j0 + DBW)), dim3(512), 0, st, S, ng, j0,
+                           (int)DBW, v, y, (int)nrhs, sync + 1 + k, sync);
     }
 }
 
-void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st) {
+void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, int *sync, hipStream_t st) {
+    const int64_t nblk = (ng + DBW - 1) / DBW;
+    int *cnt = sync + 1 + (nblk > 1 ? nblk - 1 : 0);
     hipLaunchKernelGGL(k_div_diag, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, S, ng, z, z, (int)nrhs);
-    for (int64_t j0 = ((ng - 1) / DBW) * DBW; j0 >= 0; j0 -= DBW) {
+    const int64_t jl = (nblk - 1) * DBW;
+    const int nbwl = (int)(ng - jl);
+    // x_J = X_J^T z_J for the last block, then one step per block: z_above
+    // -= L[J, above]^T x_J and the in-block product of the block before it,
+    // both read down the columns of the stored lower triangle
+    hipLaunchKernelGGL(k_dense_tdot<true>, dim3((unsigned)tdot_grid(nbwl)), dim3(256), 0, st, S, ng, jl, nbwl, jl,
+                       nbwl, (const double *)nullptr, (const double *)z, x, (int)nrhs);
+    for (int64_t k = nblk - 1; k >= 1; --k) {
+        const int64_t j0 = k * DBW;
         const int nbw = (int)std::min<int64_t>(DBW, ng - j0);
-        // x_J = X_J^T z_J, then z_above -= L[J, above]^T x_J, both read down
-        // the columns of the stored lower triangle
-        hipLaunchKernelGGL(k_dense_tdot<true>, dim3((unsigned)tdot_grid(nbw)), dim3(256), 0, st, S,
-                           ng, j0, nbw, j0, nbw, (const double *)nullptr, (const double *)z, x, (int)nrhs);
-        if (j0 > 0)
-            hipLaunchKernelGGL(k_dense_tdot<false>, dim3((unsigned)tdot_grid(j0)), dim3(256), 0, st, S,
-                               ng, j0, nbw, (int64_t)0, (int)j0, (const double *)(x + j0), (const double *)nullptr, z,
-                               (int)nrhs);
+        hipLaunchKernelGGL(k_dense_bwd_step, dim3((unsigned)bwd_step_grid(j0)), dim3(256), 0, st, S, ng, j0, nbw, z, x,
+                           (int)nrhs, cnt + (k - 1), sync);
     }
 }
 

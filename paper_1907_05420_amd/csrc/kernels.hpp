@@ -146,8 +146,11 @@ void launch_struct_solve(const double *F, const double *G, const double *GT, con
 // (tmp: INV_W x INV_W doubles)
 void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, int c, double *tmp,
                         hipStream_t st);
-void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, hipStream_t st);
-void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, hipStream_t st);
+// sync: [0] failure flag (set if an in-block product's wait passed its
+// bound), then 2 (ceil(ng / DENSE_INV_W) - 1) step counters, zeroed by the
+// forward launcher
+void launch_dense_fwd(const double *S, int64_t ng, double *v, double *y, int64_t nrhs, int *sync, hipStream_t st);
+void launch_dense_bwd(const double *S, int64_t ng, double *z, double *x, int64_t nrhs, int *sync, hipStream_t st);
 
 // ---- residual ------------------------------------------------------------------
 struct ResidualArgs {

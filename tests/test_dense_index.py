@@ -36,42 +36,55 @@ struct Cov {
 static void pass(int64_t ng, bool cover) {
     Cov cv(ng, cover);
     const int64_t NS = ng * ng;
-    // forward: in-block product, then the rows below
-    for (int64_t j0 = 0; j0 < ng; j0 += DENSE_BLOCK) {
-        const int nbw = (int)ds_min(DENSE_BLOCK, ng - j0);
-        for (int64_t b = 0; b < blk_grid(nbw); ++b)
-            for (int tid = 0; tid < 256; ++tid) {
-                const int64_t i = b * 16 + (tid & 15);
-                const int g = tid >> 4;
-                if (!(BK_C * g < i)) continue;  // groups right of the diagonal load nothing
-                for (int u = 0; u < BK_C; ++u) {
-                    const int64_t a = blk_s_addr(ng, j0, nbw, b, tid, u);
-                    CHECK(a >= 0 && a < NS, "blk ng %lld j0 %lld b %lld tid %d u %d addr %lld\n", (long long)ng,
+    // forward: the first block's in-block product, then one launch per step:
+    // the rows below block [j0, j1) (their first row workgroups, the
+    // producers, cover the next block exactly), then the next block's
+    // in-block product (the product's geometry with row0 = col0)
+    auto tri = [&](int64_t j0, int nbw) {
+        for (int64_t b = 0; b < gemv_grid(nbw); ++b)
+            for (int tid = 0; tid < 512; ++tid) {
+                if (!gemv_tri_used(b, tid)) continue;  // groups right of the diagonal load nothing
+                const int64_t i = b * GV_R + tid % GV_R;
+                const int qa = 64 * (tid / GV_R);
+                const int ncq = (int)ds_max(1, ds_min(64, nbw - qa));
+                for (int u = 0; u < 64; ++u) {
+                    const int64_t a = gemv_s_addr(ng, j0, nbw, j0, nbw, b, tid, u);
+                    CHECK(a >= 0 && a < NS, "tri ng %lld j0 %lld b %lld tid %d u %d addr %lld\n", (long long)ng,
                           (long long)j0, (long long)b, tid, u, (long long)a);
-                    const int64_t q = (int64_t)BK_C * g + u;
-                    if (q < nbw && q < i && i < nbw) {  // unmasked
-                        CHECK(a == (j0 + i) + (j0 + q) * ng, "blk addr ng %lld\n", (long long)ng);
+                    const int64_t q = qa + u;
+                    if (qa < nbw && u < ncq && q < i && i < nbw) {  // unmasked
+                        CHECK(a == (j0 + i) + (j0 + q) * ng, "tri addr ng %lld\n", (long long)ng);
                         cv.hit(a);
                     }
                 }
             }
+    };
+    tri(0, (int)ds_min(DENSE_BLOCK, ng));
+    for (int64_t j0 = 0; j0 + DENSE_BLOCK < ng; j0 += DENSE_BLOCK) {
+        const int nbw = DENSE_BLOCK;
         const int64_t row0 = j0 + nbw, nrow = ng - row0;
-        if (nrow > 0)
-            for (int64_t b = 0; b < gemv_grid(nrow); ++b)
-                for (int tid = 0; tid < 512; ++tid) {
-                    const int64_t i = b * GV_R + tid % GV_R;
-                    const int qa = 64 * (tid / GV_R);
-                    const int ncq = (int)ds_max(1, ds_min(64, nbw - qa));
-                    for (int u = 0; u < 64; ++u) {
-                        const int64_t a = gemv_s_addr(ng, row0, nrow, j0, nbw, b, tid, u);
-                        CHECK(a >= 0 && a < NS, "gemv ng %lld j0 %lld b %lld tid %d u %d\n", (long long)ng,
-                              (long long)j0, (long long)b, tid, u);
-                        if (qa < nbw && u < ncq && i < nrow) {
-                            CHECK(a == (row0 + i) + (j0 + qa + u) * ng, "gemv addr ng %lld\n", (long long)ng);
-                            cv.hit(a);
-                        }
+        const int nbw1 = (int)ds_min(DENSE_BLOCK, nrow);
+        const int64_t G = gemv_grid(nrow), P = gemv_grid(nbw1);
+        CHECK(fwd_step_grid(ng, row0) == G + P, "fwd grid ng %lld\n", (long long)ng);
+        // the producers' rows are the next block's rows, and no other workgroup writes them
+        CHECK(ds_min(P * GV_R, nrow) >= nbw1 && (P - 1) * GV_R < nbw1, "producers ng %lld j0 %lld\n", (long long)ng,
+              (long long)j0);
+        for (int64_t b = 0; b < G; ++b)
+            for (int tid = 0; tid < 512; ++tid) {
+                const int64_t i = b * GV_R + tid % GV_R;
+                const int qa = 64 * (tid / GV_R);
+                const int ncq = (int)ds_max(1, ds_min(64, nbw - qa));
+                for (int u = 0; u < 64; ++u) {
+                    const int64_t a = gemv_s_addr(ng, row0, nrow, j0, nbw, b, tid, u);
+                    CHECK(a >= 0 && a < NS, "gemv ng %lld j0 %lld b %lld tid %d u %d\n", (long long)ng,
+                          (long long)j0, (long long)b, tid, u);
+                    if (qa < nbw && u < ncq && i < nrow) {
+                        CHECK(a == (row0 + i) + (j0 + qa + u) * ng, "gemv addr ng %lld\n", (long long)ng);
+                        cv.hit(a);
                     }
                 }
+            }
+        tri(row0, nbw1);
     }
     if (cover) {  // every strictly lower entry once (diagonal D is read by the division)
         for (int64_t q = 0; q < ng; ++q)
@@ -82,28 +95,37 @@ static void pass(int64_t ng, bool cover) {
             }
         cv.n.assign((size_t)(ng * ng), 0);
     }
-    // backward: in-block product with X^T, then the rows above
-    for (int64_t j0 = ((ng - 1) / DENSE_BLOCK) * DENSE_BLOCK; j0 >= 0; j0 -= DENSE_BLOCK) {
-        const int nbw = (int)ds_min(DENSE_BLOCK, ng - j0);
-        for (int pass2 = 0; pass2 < 2; ++pass2) {
-            const bool blk = pass2 == 0;
-            const int64_t row0 = j0, col0 = blk ? j0 : 0;
-            const int nq = nbw, ncols = blk ? nbw : (int)j0;
-            if (ncols <= 0) continue;
-            for (int64_t b = 0; b < tdot_grid(ncols); ++b)
-                for (int wv = 0; wv < 4; ++wv)
-                    for (int c = 0; c < TD_CPW; ++c)
-                        for (int lane = 0; lane < 64; ++lane)
-                            for (int k = 0; k < DENSE_BLOCK / 64; ++k) {
-                                const int64_t a = tdot_s_addr(ng, row0, nq, col0, ncols, b, wv, c, lane, k);
-                                CHECK(a >= 0 && a < NS, "tdot ng %lld j0 %lld\n", (long long)ng, (long long)j0);
-                                const int64_t i = (b * 4 + wv) * TD_CPW + c, q = lane + 64 * k;
-                                if (i < ncols && q < nq && (!blk || q > i)) {
-                                    CHECK(a == (row0 + q) + (col0 + i) * ng, "tdot addr ng %lld\n", (long long)ng);
-                                    cv.hit(a);
-                                }
+    // backward: the last block's in-block product with X^T, then one launch
+    // per step: the columns [0, j0) above block [j0, ..) in reverse order of
+    // workgroups (the first tdot_grid(DENSE_BLOCK), the producers, cover the
+    // block before it exactly), then that block's in-block product
+    auto tdot = [&](int64_t row0, int nq, int64_t col0, int ncols, bool blk, bool rev) {
+        const int64_t G = tdot_grid(ncols);
+        for (int64_t bb = 0; bb < G; ++bb) {
+            const int64_t b = rev ? G - 1 - bb : bb;
+            for (int wv = 0; wv < 4; ++wv)
+                for (int c = 0; c < TD_CPW; ++c)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int k = 0; k < DENSE_BLOCK / 64; ++k) {
+                            const int64_t a = tdot_s_addr(ng, row0, nq, col0, ncols, b, wv, c, lane, k);
+                            CHECK(a >= 0 && a < NS, "tdot ng %lld row0 %lld\n", (long long)ng, (long long)row0);
+                            const int64_t i = (b * 4 + wv) * TD_CPW + c, q = lane + 64 * k;
+                            if (rev && bb < tdot_grid(DENSE_BLOCK))  // producers: the last DENSE_BLOCK columns
+                                CHECK(i >= ncols - DENSE_BLOCK, "bwd producers ng %lld\n", (long long)ng);
+                            if (i < ncols && q < nq && (!blk || q > i)) {
+                                CHECK(a == (row0 + q) + (col0 + i) * ng, "tdot addr ng %lld\n", (long long)ng);
+                                cv.hit(a);
                             }
+                        }
         }
+    };
+    const int64_t jl = ((ng - 1) / DENSE_BLOCK) * DENSE_BLOCK;
+    tdot(jl, (int)(ng - jl), jl, (int)(ng - jl), true, false);
+    for (int64_t j0 = jl; j0 >= DENSE_BLOCK; j0 -= DENSE_BLOCK) {
+        const int nbw = (int)ds_min(DENSE_BLOCK, ng - j0);
+        CHECK(bwd_step_grid(j0) == tdot_grid(j0) + tdot_grid(DENSE_BLOCK), "bwd grid ng %lld\n", (long long)ng);
+        tdot(j0, nbw, 0, (int)j0, false, true);
+        tdot(j0 - DENSE_BLOCK, DENSE_BLOCK, j0 - DENSE_BLOCK, DENSE_BLOCK, true, false);
     }
     if (cover)
         for (int64_t q = 0; q < ng; ++q)
