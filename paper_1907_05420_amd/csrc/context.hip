@@ -421,7 +421,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             if (S.nrow[t] > S.ncol[t])
                 for (int q0 = 0; q0 < S.ncol[t]; q0 += 64) { buf.push_back(t); buf.push_back(q0); ++lp.nrcol; }
         lp.step_begin = (int)ctx->steps.size();
-        plan_steps(fd, large, buf, ctx->steps, false, ctx->big_rows, OUTER_W, OUTER_W);
+        plan_steps(fd, large, buf, ctx->steps, false, ctx->big_rows, OUTER_W, INNER_W);
         lp.step_end = (int)ctx->steps.size();
     }
     if ((rc = upload(ctx, &ctx->d_tasks, buf))) return rc;
@@ -441,7 +441,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         std::vector<int32_t> sbuf;
         for (int k = 0; k < 2; ++k) {
             ctx->sf_steps[k].clear();
-            plan_steps(sf, std::vector<int32_t>{k}, sbuf, ctx->sf_steps[k], false, ctx->big_rows, OUTER_W, OUTER_W);
+            plan_steps(sf, std::vector<int32_t>{k}, sbuf, ctx->sf_steps[k], false, ctx->big_rows, INNER_W, INNER_W);
         }
         if ((rc = upload(ctx, &ctx->d_sftasks, sbuf))) return rc;
     } else if (ctx->ng > 0) {
@@ -455,7 +455,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = upload(ctx, &ctx->d_sdS, sdS))) return rc;
         std::vector<int32_t> sbuf;
         ctx->ssteps.clear();
-        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true, ctx->big_rows, SCHUR_OUTER_W, INV_W);
+        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true, ctx->big_rows, SCHUR_OUTER_W, INNER_W);
         if ((rc = upload(ctx, &ctx->d_stasks, sbuf))) return rc;
     }
     // residual: full symmetric CSR of the pattern (caller order) and C^T by column

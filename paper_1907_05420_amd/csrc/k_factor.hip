@@ -722,9 +722,11 @@ __host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int
         g.K = cend - t0;
         g.lo = cend;
         g.qhi = m;
-        // the next outer panel has the width of this one (pe - t0)
+        // the next outer panel has the width of this one (pe - t0); its
+        // columns end at the front's last pivot (the update block's columns
+        // take the whole outer panel's update after it)
         const int nxt = pe + (pe - t0) < m ? pe + (pe - t0) : m;
-        if (win == 1) g.qhi = nxt;
+        if (win == 1) g.qhi = nxt < c ? nxt : c;
         else if (win == 2) g.lo = nxt;
     }
     return g;

@@ -37,14 +37,16 @@ struct TreeArgs {
 
 // One launch of the blocked right-looking factorisation over a group of large
 // fronts. Pivot columns go in 64-wide blocks inside outer panels (OUTER_W
-// columns for the period fronts, SCHUR_OUTER_W for the dense Schur factor):
-// per block the pivot block (kind 0), the rows below it (kind 1) and the rest
-// of the outer panel (kind 2); after each outer panel one trailing update of
-// rank <= the panel width (kind 3 on 64x64 tiles, kind 4 on 128x128 tiles for
-// large trailing matrices). The dense Schur factor's diagonal-block
-// inverses, which only the dense solves use, follow its last panel
-// (launch_inverses_all).
-constexpr int OUTER_W = 256;
+// columns for the period fronts, SCHUR_OUTER_W for the dense Schur factor)
+// of sub-panels of INNER_W columns: per block the pivot block (kind 0), the
+// rows below it (kind 1) and the rest of the sub-panel (kind 2); after a
+// sub-panel the next sub-panel's columns, after each outer panel one
+// trailing update of rank <= the panel width (kind 3 on 64x64 tiles, kind 4
+// on 128x128 tiles for large trailing matrices). The dense Schur factor's
+// diagonal-block inverses, which only the dense solves use, follow its last
+// panel (launch_inverses_all).
+constexpr int OUTER_W = 512;
+constexpr int INNER_W = 256;  // at most four pivot blocks (k_panel_trsm)
 constexpr int SCHUR_OUTER_W = 512;
 constexpr int MAX_OUTER_W = 512;
 constexpr int INV_W = 256;
