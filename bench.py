@@ -111,7 +111,7 @@ def cpu_baseline():
 
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "k_update_big_mesh2000_N96_counters.txt")
 # the dominant kernel's source: the kernel file and its tile-order header
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1907_05420_amd", "csrc", f) for f in ("k_factor.hip", "tile_order.hpp", "device.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1907_05420_amd", "csrc", f) for f in ("k_factor.hip", "tile_order.hpp", "device.hpp", "step_plan.hpp")]
 
 
 def git_blob_sha1(path):

@@ -13,6 +13,7 @@
 
 #include "../../include/kkt.h"
 #include "device.hpp"
+#include "step_plan.hpp"
 #include "footprint.hpp"
 #include "kernels.hpp"
 #include "symbolic.hpp"
@@ -34,17 +35,6 @@ using namespace kkt;
     } while (0)
 
 namespace {
-
-// kind 0-7: launches (see StepDev); SYNC_TO_SIDE: the side stream waits for
-// the main stream's work so far; SYNC_TO_MAIN: the main stream waits for the
-// side stream's work so far.
-constexpr int SYNC_TO_SIDE = 100, SYNC_TO_MAIN = 101;
-constexpr int PANEL_ROWS = 1024;  // rows below a sub-panel from which its rows below take one launch
-struct StepHost {
-    int kind, win, t0, pe, nf, ntasks;
-    int side;                 // 0: main stream, 1: side stream
-    int64_t fl_off, pre_off;  // offsets (int32 elements) into the task buffer
-};
 
 struct LevelPlan {
     int64_t small_off = 0, all_off = 0, ea_off = 0, large_off = 0;  // int32 offsets into the task buffer
@@ -205,101 +195,6 @@ void free_ws(kkt_ctx *ctx) {
     ctx->d_V = ctx->d_Z = ctx->d_h = ctx->d_kpart = nullptr;
     ctx->bytes_ws = 0;
     ctx->ws_nrhs = 0;
-}
-
-// launch sequence of the blocked factorisation of a set of fronts
-// With lookahead (dense Schur), each trailing update is split: the next
-// panel's columns on the main stream, the rest on the side stream, so that the
-// latency-bound factorisation of the next panel overlaps the large update.
-void plan_steps(const std::vector<FrontDesc> &fd, const std::vector<int32_t> &fl, std::vector<int32_t> &buf,
-                std::vector<StepHost> &steps, bool lookahead, int big_rows, int outer_w, int inner_w) {
-    int cmax = 0;
-    for (int32_t f : fl) cmax = std::max(cmax, fd[f].c);
-    auto sync = [&](int kind) {
-        StepHost s{};
-        s.kind = kind;
-        steps.push_back(s);
-    };
-    auto add = [&](int kind, int t0, int pe, int win = 0, int side = 0) {
-        std::vector<int32_t> act;
-        std::vector<int> cnt;
-        for (int32_t f : fl) {
-            if (fd[f].c <= t0) continue;
-            int k = step_tasks(kind, t0, pe, fd[f].c, fd[f].m, win);
-            if (k <= 0) continue;
-            act.push_back(f);
-            cnt.push_back(k);
-        }
-        if (act.empty()) return;
-        StepHost s{};
-        s.kind = kind;
-        s.win = win;
-        s.side = side;
-        s.t0 = t0;
-        s.pe = pe;
-        s.nf = (int)act.size();
-        s.fl_off = (int64_t)buf.size();
-        buf.insert(buf.end(), act.begin(), act.end());
-        s.pre_off = (int64_t)buf.size();
-        int acc = 0;
-        for (int k : cnt) { buf.push_back(acc); acc += k; }
-        buf.push_back(acc);
-        s.ntasks = acc;
-        steps.push_back(s);
-    };
-    // large trailing matrices (rows below column `col`) take the 128x128 tile kernel
-    auto big_from = [&](int t0, int col) {
-        for (int32_t f : fl)
-            if (fd[f].c > t0 && fd[f].m - std::min(col, fd[f].c) >= big_rows) return 1;
-        return 0;
-    };
-    for (int k = 0; k < cmax; k += outer_w) {
-        const int pe = k + outer_w;
-        // the panel's columns were brought up to date by the main stream's
-        // update from the previous panel, after the side stream had finished
-        // the updates of the panels before it; the side stream's update from
-        // the previous panel (columns beyond this panel) runs meanwhile.
-        // Inside the panel, sub-panels of inner_w columns: 64-column steps
-        // update only their own sub-panel, and each finished sub-panel updates
-        // the next sub-panel's columns in one rank-inner_w product.
-        for (int s0 = k; s0 < std::min(pe, cmax); s0 += inner_w) {
-            const int se = std::min(s0 + inner_w, pe);
-            // where the fronts have many rows below the sub-panel (the dense
-            // Schur factor, the largest period fronts) the 64-column steps
-            // stay inside the sub-panel's diagonal block, and the rows below
-            // it take all of the sub-panel's columns in one launch. Fronts
-            // with few rows below (most period fronts, the structured Schur's
-            // 2 N_s x N_s fronts) keep the per-block steps: there the
-            // one-launch form's per-tile chain of products is the slower one.
-            int below = 0;
-            for (int32_t f : fl)
-                if (fd[f].c > s0) below = std::max(below, fd[f].m - std::min(se, fd[f].c));
-            const bool one_launch = lookahead || below >= PANEL_ROWS;
-            for (int j0 = s0; j0 < std::min(se, cmax); j0 += 64) {
-                add(0, j0, se);
-                add(1, j0, se, one_launch ? 3 : 0);
-                add(2, j0, se, one_launch ? 3 : 0);
-            }
-            if (one_launch) add(7, s0, se);
-            if (se < std::min(pe, cmax)) add(big_from(s0, se) ? 4 : 3, s0, se, 1, 0);
-        }
-        const int big = big_from(k, pe);
-        if (!lookahead) {
-            add(big ? 4 : 3, k, pe);
-            continue;
-        }
-        // the next panel's columns: the side stream's update from the
-        // previous panel must be done before this panel's update of them
-        if (k > 0) sync(SYNC_TO_MAIN);
-        add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
-        // the side stream updates the columns beyond the next panel once the
-        // main stream's update of the next panel's columns is done: started
-        // together, the large update takes the compute units first and the
-        // next panel (the critical path) waits behind it
-        sync(SYNC_TO_SIDE);
-        add(big ? 4 : 3, k, pe, 2, 1);  // the rest, side stream
-    }
-    if (lookahead) sync(SYNC_TO_MAIN);
 }
 
 StepDev step_dev(const StepHost &s, const int32_t *base) {

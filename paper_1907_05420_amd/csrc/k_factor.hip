@@ -12,12 +12,13 @@
 
 #include "device.hpp"
 #include "kernels.hpp"
+#include "step_plan.hpp"
 #include "tile_order.hpp"
 
 namespace kkt {
 
 constexpr int SMALL_M = 64;
-constexpr int NB = 64;      // pivot block width
+constexpr int NB = PIVOT_NB;  // pivot block width
 constexpr int LDT = 65;     // LDS leading dimension of a 64x64 tile
 
 // --------------------------------------------------------------------------
@@ -702,36 +703,6 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<T> fa, const Fron
     }
 }
 
-// Geometry of an update after the pivot columns [t0, t0+K): target rows and
-// columns start at lo; columns end at qhi. kind 2: inside the outer panel
-// ending at pe; kind 3: the trailing matrix after that panel.
-struct UpdGeom {
-    int lo, qhi, K;
-};
-// win (trailing updates only): 0 the whole trailing matrix; 1 the columns of
-// the next outer panel; 2 everything right of the next outer panel.
-__host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int m, int win = 0) {
-    const int cend = pe < c ? pe : c;
-    UpdGeom g;
-    if (kind == 2) {
-        g.K = (c - t0) < NB ? (c - t0) : NB;
-        g.lo = t0 + g.K;
-        g.qhi = cend;
-        (void)win;  // win 3 (rows below the panel left out) is applied by the caller's row limit
-    } else {
-        g.K = cend - t0;
-        g.lo = cend;
-        g.qhi = m;
-        // the next outer panel has the width of this one (pe - t0); its
-        // columns end at the front's last pivot (the update block's columns
-        // take the whole outer panel's update after it)
-        const int nxt = pe + (pe - t0) < m ? pe + (pe - t0) : m;
-        if (win == 1) g.qhi = nxt < c ? nxt : c;
-        else if (win == 2) g.lo = nxt;
-    }
-    return g;
-}
-
 // algorithmic work of one trailing-update launch on a front (see kkt.h)
 void update_work(int t0, int pe, int c, int m, int win, double *flops, double *bytes) {
     const UpdGeom g = upd_geom(3, t0, pe, c, m, win);
@@ -827,7 +798,7 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
 // Columns past the panel's K read as zero through the buffer's range check.
 // The epilogue goes through LDS in four 32-column quarters for a coalesced
 // read-modify-write of the target.
-constexpr int BT = 128;      // tile edge
+constexpr int BT = BIG_TILE;  // tile edge
 constexpr int UPF = 3;       // K steps in flight per lane
 
 template <typename T>
@@ -1211,12 +1182,6 @@ void launch_struct_pair(const double *G, int ns, int N, double *M, double *MT, h
     hipLaunchKernelGGL(k_struct_pair, dim3((unsigned)(nt * nt), (unsigned)(N / 2)), dim3(256), 0, st, G, ns, N, M, MT);
 }
 
-int step_tasks_big(int t0, int pe, int c, int m, int win) {
-    const UpdGeom g = upd_geom(3, t0, pe, c, m, win);
-    if (g.K <= 0 || g.qhi <= g.lo) return 0;
-    const int Tr = (m - g.lo + BT - 1) / BT, Tc = (g.qhi - g.lo + BT - 1) / BT;
-    return Tc * Tr - Tc * (Tc - 1) / 2;
-}
 
 // --------------------------------------------------------------------------
 // host launchers
@@ -1293,26 +1258,6 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
             hipLaunchKernelGGL(k_update<T>, dim3(s.ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, s.fl, s.pre,
                                s.nf, s.kind, s.t0, s.pe, s.win);
     }
-}
-
-// host mirror of the per-front task counts of a step
-int step_tasks(int kind, int t0, int pe, int c, int m, int win) {
-    if (kind == 4) return step_tasks_big(t0, pe, c, m, win);
-    if (kind == 0) return c > t0 ? 1 : 0;
-    if (kind == 1) {
-        const int nb = std::min(NB, c - t0);
-        const int rows = (win == 3 ? std::min(pe, c) : m) - t0 - nb;
-        return rows > 0 ? (rows + 63) / 64 : 0;
-    }
-    if (kind == 7) {
-        const int rows = m - std::min(pe, c);
-        return c > t0 && rows > 0 ? (rows + 63) / 64 : 0;
-    }
-    const UpdGeom g = upd_geom(kind, t0, pe, c, m, win);
-    if (g.K <= 0 || g.qhi <= g.lo) return 0;
-    const int mr = (kind == 2 && win == 3) ? g.qhi : m;
-    const int Tr = (mr - g.lo + 63) / 64, Tc = (g.qhi - g.lo + 63) / 64;
-    return Tc * Tr - Tc * (Tc - 1) / 2;
 }
 
 #define KKT_INST(T)                                                                                        \

@@ -62,7 +62,6 @@ struct StepDev {
     const int32_t *pre;     // prefix sums of the per-front task counts (kinds 1-4)
     int ntasks;
 };
-int step_tasks(int kind, int t0, int pe, int c, int m, int win = 0);
 // algorithmic flops and HBM bytes of one trailing-update launch on a front
 void update_work(int t0, int pe, int c, int m, int win, double *flops, double *bytes);
 
