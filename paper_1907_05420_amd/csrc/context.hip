@@ -43,6 +43,13 @@ struct LevelPlan {
     int nsmall_cls[3] = {0, 0, 0};  // small fronts of <= 16, <= 32, <= 64 rows (listed in that order)
     int maxm = 0, maxm_large = 0, maxc_large = 0;
     int step_begin = 0, step_end = 0;
+    int win_begin = 0, win_end = 0;  // pivot windows of the wide fronts (solve)
+};
+
+// a pivot window of the solve's wide fronts as offsets into the task buffer
+struct WindowPlan {
+    int p0 = 0, nfront = 0, nrows = 0, ncols = 0;
+    int64_t f_off = 0, r_off = 0, c_off = 0;
 };
 
 }  // namespace
@@ -71,9 +78,12 @@ struct kkt_ctx {
     int64_t *d_amap = nullptr, *d_c0map = nullptr, *d_c1map = nullptr, *d_rowptr = nullptr, *d_relptr = nullptr;
     int8_t *d_adiag = nullptr, *d_pivsign = nullptr;
     int32_t *d_adpiv = nullptr, *d_rows = nullptr, *d_cptr = nullptr, *d_clist = nullptr, *d_rel = nullptr;
+    int32_t *d_vea = nullptr;  // children's update rows of every front in groups (TreeArgs::vea)
     int32_t *d_perm = nullptr, *d_tasks = nullptr;
     FrontDesc *d_sd = nullptr;
     std::vector<LevelPlan> levels;
+    std::vector<WindowPlan> win_plan;
+    std::vector<TriWindow> win;            // win_plan with device pointers
     std::vector<StepHost> steps, ssteps;   // sparse levels, Schur
     int32_t *d_stasks = nullptr;           // Schur step tasks
     FrontDesc *d_sdS = nullptr;
@@ -230,6 +240,7 @@ TreeArgs tree_args(const kkt_ctx *ctx) {
     t.clist = ctx->d_clist;
     t.relptr = ctx->d_relptr;
     t.rel = ctx->d_rel;
+    t.vea = ctx->d_vea;
     t.rows = ctx->d_rows;
     t.rowptr = ctx->d_rowptr;
     return t;
@@ -253,6 +264,36 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
     if ((rc = upload(ctx, &ctx->d_clist, S.child_list))) return rc;
     if ((rc = upload(ctx, &ctx->d_relptr, S.relptr))) return rc;
     if ((rc = upload(ctx, &ctx->d_rel, S.rel))) return rc;
+    {
+        // the children's update rows of every front, in groups of children
+        // whose rows are disjoint: a child goes into the group after the last
+        // one holding an earlier child that shares a row with it, so every
+        // row receives its children's entries in the children's order
+        std::vector<int32_t> vea(S.nsup), last_group(S.max_front + 1);
+        for (int32_t t = 0; t < S.nsup; ++t) {
+            vea[t] = (int32_t)vea.size();
+            std::vector<std::vector<int32_t>> groups;  // (src, dst) pairs per group
+            std::fill(last_group.begin(), last_group.begin() + S.nrow[t], 0);
+            for (int32_t k = S.child_ptr[t]; k < S.child_ptr[t + 1]; ++k) {
+                const int32_t ch = S.child_list[k];
+                const int32_t *rl = S.rel.data() + S.relptr[ch];
+                const int uc = S.nrow[ch] - S.ncol[ch];
+                int32_t g = 0;
+                for (int i = 0; i < uc; ++i) g = std::max(g, last_group[rl[i]]);
+                if (g == (int32_t)groups.size()) groups.emplace_back();
+                for (int i = 0; i < uc; ++i) {
+                    groups[g].push_back((int32_t)(S.relptr[ch] + i));
+                    groups[g].push_back(rl[i]);
+                    last_group[rl[i]] = g + 1;
+                }
+            }
+            vea.push_back((int32_t)groups.size());
+            int32_t e = 0;
+            for (const auto &gr : groups) vea.push_back(e += (int32_t)(gr.size() / 2));
+            for (const auto &gr : groups) vea.insert(vea.end(), gr.begin(), gr.end());
+        }
+        if ((rc = upload(ctx, &ctx->d_vea, vea))) return rc;
+    }
     if ((rc = upload(ctx, &ctx->d_perm, S.perm))) return rc;
     if ((rc = upload(ctx, &ctx->d_pivsign, S.pivsign))) return rc;
     std::vector<FrontDesc> fd(S.nsup);
@@ -269,6 +310,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
     std::vector<int32_t> buf;
     ctx->levels.assign(S.nlevels, LevelPlan());
     ctx->steps.clear();
+    ctx->win_plan.clear();
     for (int32_t l = 0; l < S.nlevels; ++l) {
         LevelPlan &lp = ctx->levels[l];
         std::vector<int32_t> small, large, all;
@@ -296,16 +338,39 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         lp.all_off = (int64_t)buf.size();
         lp.nall = (int)all.size();
         buf.insert(buf.end(), all.begin(), all.end());
+        // the solve's pivot part: wide fronts window by window, the others whole
+        std::vector<int32_t> plain, wide;
+        for (int32_t t : large) (S.ncol[t] > TRI_W && S.nrow[t] > S.ncol[t] ? wide : plain).push_back(t);
         lp.large_off = (int64_t)buf.size();
-        lp.nlarge = (int)large.size();
-        buf.insert(buf.end(), large.begin(), large.end());
+        lp.nlarge = (int)plain.size();
+        buf.insert(buf.end(), plain.begin(), plain.end());
+        // extend-add tiles of 64 rows, each with the (child, first row, end
+        // row) segments of the children's update rows that land in it
+        while (buf.size() % 4) buf.push_back(0);  // EaTask alignment
         lp.ea_off = (int64_t)buf.size();
+        {
+            std::vector<int32_t> tiles, segs;
+            for (int32_t t : large)
+                for (int r0 = 0; r0 < S.nrow[t]; r0 += 64) {
+                    const int r1 = std::min(r0 + 64, S.nrow[t]);
+                    const int32_t s0 = (int32_t)segs.size();
+                    for (int32_t k = S.child_ptr[t]; k < S.child_ptr[t + 1]; ++k) {
+                        const int32_t ch = S.child_list[k];
+                        const int32_t *rl = S.rel.data() + S.relptr[ch];
+                        const int uc = S.nrow[ch] - S.ncol[ch];
+                        const int lo = (int)(std::lower_bound(rl, rl + uc, r0) - rl);
+                        const int hi = (int)(std::lower_bound(rl + lo, rl + uc, r1) - rl);
+                        if (lo < hi) segs.insert(segs.end(), {ch, lo, hi});
+                    }
+                    tiles.insert(tiles.end(), {t, r0, s0, ((int32_t)segs.size() - s0) / 3});
+                }
+            lp.nea = (int)(tiles.size() / 4);
+            // segment offsets count from the first task
+            for (size_t q = 0; q < tiles.size(); q += 4) tiles[q + 2] += (int32_t)tiles.size();
+            buf.insert(buf.end(), tiles.begin(), tiles.end());
+            buf.insert(buf.end(), segs.begin(), segs.end());
+        }
         if (buf.size() % 2) buf.push_back(0);  // RowTask alignment (pairs of int32)
-        lp.ea_off = (int64_t)buf.size();
-        int nea = 0;
-        for (int32_t t : large)
-            for (int r0 = 0; r0 < S.nrow[t]; r0 += 64) { buf.push_back(t); buf.push_back(r0); ++nea; }
-        lp.nea = nea;
         // solve: 64 update rows / 64 pivot columns of each large front
         lp.rrow_off = (int64_t)buf.size();
         for (int32_t t : large)
@@ -315,11 +380,43 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         for (int32_t t : large)
             if (S.nrow[t] > S.ncol[t])
                 for (int q0 = 0; q0 < S.ncol[t]; q0 += 64) { buf.push_back(t); buf.push_back(q0); ++lp.nrcol; }
+        lp.win_begin = (int)ctx->win_plan.size();
+        int maxc_wide = 0;
+        for (int32_t t : wide) maxc_wide = std::max(maxc_wide, S.ncol[t]);
+        for (int p0 = 0; p0 < maxc_wide; p0 += TRI_W) {
+            WindowPlan w;
+            w.p0 = p0;
+            w.f_off = (int64_t)buf.size();
+            for (int32_t t : wide)
+                if (S.ncol[t] > p0) { buf.push_back(t); ++w.nfront; }
+            if (buf.size() % 2) buf.push_back(0);  // RowTask alignment
+            w.r_off = (int64_t)buf.size();
+            for (int32_t t : wide)
+                for (int r0 = p0 + TRI_W; r0 < S.ncol[t]; r0 += 64) { buf.push_back(t); buf.push_back(r0); ++w.nrows; }
+            w.c_off = (int64_t)buf.size();
+            for (int32_t t : wide)
+                if (S.ncol[t] > p0)
+                    for (int q0 = 0; q0 < p0; q0 += 64) { buf.push_back(t); buf.push_back(q0); ++w.ncols; }
+            ctx->win_plan.push_back(w);
+        }
+        lp.win_end = (int)ctx->win_plan.size();
         lp.step_begin = (int)ctx->steps.size();
         plan_steps(fd, large, buf, ctx->steps, false, ctx->big_rows, OUTER_W, INNER_W);
         lp.step_end = (int)ctx->steps.size();
     }
     if ((rc = upload(ctx, &ctx->d_tasks, buf))) return rc;
+    ctx->win.clear();
+    for (const WindowPlan &w : ctx->win_plan) {
+        TriWindow tw;
+        tw.p0 = w.p0;
+        tw.fronts = ctx->d_tasks + w.f_off;
+        tw.rows = (const RowTask *)(ctx->d_tasks + w.r_off);
+        tw.cols = (const RowTask *)(ctx->d_tasks + w.c_off);
+        tw.nfront = w.nfront;
+        tw.nrows = w.nrows;
+        tw.ncols = w.ncols;
+        ctx->win.push_back(tw);
+    }
     // Schur front and its steps
     if (ctx->ng > 0 && ctx->structured) {
         const int32_t ns = (int32_t)S.Ns;
@@ -605,7 +702,7 @@ int factor_range(kkt_ctx *ctx, int64_t p0, int64_t np, int64_t *cnt) {
     TreeArgs tr = tree_args(ctx);
     for (const LevelPlan &lp : ctx->levels) {
         launch_small_fronts<T>(fa, ctx->d_sd, ctx->d_tasks + lp.small_off, lp.nsmall_cls, np, tr, st);
-        launch_extend_add<T>(fa, ctx->d_sd, (const RowTask *)(ctx->d_tasks + lp.ea_off), lp.nea, np, tr, st);
+        launch_extend_add<T>(fa, ctx->d_sd, (const EaTask *)(ctx->d_tasks + lp.ea_off), lp.nea, np, tr, st);
         for (int q = lp.step_begin; q < lp.step_end; ++q)
             launch_step<T>(fa, ctx->d_sd, step_dev(ctx->steps[q], ctx->d_tasks), np, st);
     }
@@ -766,6 +863,8 @@ int solve_once(kkt_ctx *ctx, const double *b, double *x, int64_t nrhs) {
         lt.nlarge = lp.nlarge;
         lt.nrect_rows = lp.nrrow;
         lt.nrect_cols = lp.nrcol;
+        lt.win = ctx->win.data() + lp.win_begin;
+        lt.nwin = lp.win_end - lp.win_begin;
         lt.maxm = lp.maxm_large;
         lt.maxc = lp.maxc_large;
         return lt;

@@ -25,6 +25,14 @@ struct RowTask {    // up to 256 consecutive rows [r0, ...) of front `f`
     int32_t f, r0;
 };
 
+// Extend-add into rows [r0, r0 + 64) of front f: nseg segments of three
+// int32 at seg int32 past the first task of the list, each (child, first,
+// end) for the child's update rows [first, end) that land in those rows,
+// children in increasing order.
+struct EaTask {
+    int32_t f, r0, seg, nseg;
+};
+
 // Factor-wide pointers handed to every factor kernel.
 template <typename T>
 struct FactorArgs {
@@ -66,6 +74,25 @@ __device__ inline double buf_load(BufRes r, int off, double) {
 }
 __device__ inline float buf_load(BufRes r, int off, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Task and period of a workgroup of a (tasks, periods) grid, dealt so that
+// every workgroup of one period runs on the same XCD: the dispatcher hands
+// workgroups to the 8 XCDs round-robin in launch order (x fastest), so the
+// launch index L goes to XCD L % 8, and period n takes the indices with
+// L % 8 == n % 8. A period's vectors are then cached in one XCD's L2. Plain
+// order when the period count is not a multiple of 8.
+__device__ inline void period_task(int &task, int &n) {
+    const int gx = (int)gridDim.x, np = (int)gridDim.y;
+    if (np % 8 == 0) {
+        const int L = (int)blockIdx.x + gx * (int)blockIdx.y;
+        const int s = L >> 3;
+        n = 8 * (s / gx) + (L & 7);
+        task = s % gx;
+    } else {
+        task = (int)blockIdx.x;
+        n = (int)blockIdx.y;
+    }
 }
 
 template <typename T> struct Acc;

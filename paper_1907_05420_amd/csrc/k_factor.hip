@@ -270,34 +270,27 @@ __device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q) {
 }
 
 // Extend-add of the children's update blocks into 64-row tiles of a large
-// front.  The child rows landing in a tile form one contiguous range (the
-// relative indices increase), so every tile owns its target rows; children
-// are added one after another in a fixed order.
+// front. The child rows landing in a tile form one contiguous range (the
+// relative indices increase), so every tile owns its target rows; the task
+// lists the children with rows in the tile and those ranges, and they are
+// added one after another in increasing order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const RowTask *tasks,
-                                                    const int32_t *cptr, const int32_t *clist,
-                                                    const int64_t *relptr, const int32_t *rel) {
+__global__ __launch_bounds__(256) void k_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const EaTask *tasks,
+                                                    const int32_t *segs, const int64_t *relptr, const int32_t *rel) {
     __shared__ int32_t rls[EA_RL];
-    const RowTask tk = tasks[blockIdx.x];
+    const EaTask tk = tasks[blockIdx.x];
     const int n = blockIdx.y;
     const FrontDesc d = sd[tk.f];
-    const int r0 = tk.r0, r1 = min(r0 + 64, d.m);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
-    for (int k = cptr[d.sn]; k < cptr[d.sn + 1]; ++k) {
-        const int ch = clist[k];
+    for (int k = 0; k < tk.nseg; ++k) {
+        const int32_t *sg = segs + tk.seg + 3 * k;
+        const int ch = sg[0], i_lo = sg[1], i_hi = sg[2];
         const FrontDesc dc = sd[ch];
         const int uc = dc.m - dc.c;
         const T *Uc = fa.U + (int64_t)n * fa.Ustride + dc.Uoff;
         const int32_t *rl = rel + relptr[ch];
-        // the child rows landing in [r0, r1) (binary search; rl increases)
-        int lo = 0, hi = uc;
-        while (lo < hi) { int mid = (lo + hi) >> 1; if (rl[mid] < r0) lo = mid + 1; else hi = mid; }
-        const int i_lo = lo;
-        hi = min(uc, i_lo + 64);
-        while (lo < hi) { int mid = (lo + hi) >> 1; if (rl[mid] < r1) lo = mid + 1; else hi = mid; }
-        const int i_hi = lo;
         // the columns j <= i_hi - 1 of those rows, target column indices staged
         for (int j0 = 0; j0 < i_hi; j0 += EA_RL) {
             const int jn = min(EA_RL, i_hi - j0);
@@ -1227,11 +1220,11 @@ void launch_small_fronts(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *t
 }
 
 template <typename T>
-void launch_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const RowTask *tasks, int ntasks, int64_t N,
+void launch_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const EaTask *tasks, int ntasks, int64_t N,
                        const TreeArgs &tr, hipStream_t st) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(k_extend_add<T>, dim3(ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, tasks, tr.cptr,
-                       tr.clist, tr.relptr, tr.rel);
+    hipLaunchKernelGGL(k_extend_add<T>, dim3(ntasks, (unsigned)N), dim3(256), 0, st, fa, sd, tasks,
+                       (const int32_t *)tasks, tr.relptr, tr.rel);
 }
 
 template <typename T>
@@ -1265,7 +1258,7 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
     template void launch_scatter<T>(const ScatterArgs &, FactorArgs<T>, int64_t, hipStream_t);            \
     template void launch_small_fronts<T>(FactorArgs<T>, const FrontDesc *, const int32_t *, const int *, int64_t, \
                                          const TreeArgs &, hipStream_t);                                  \
-    template void launch_extend_add<T>(FactorArgs<T>, const FrontDesc *, const RowTask *, int, int64_t,   \
+    template void launch_extend_add<T>(FactorArgs<T>, const FrontDesc *, const EaTask *, int, int64_t,    \
                                        const TreeArgs &, hipStream_t);                                    \
     template void launch_step<T>(FactorArgs<T>, const FrontDesc *, const StepDev &, int64_t, hipStream_t);
 KKT_INST(double)

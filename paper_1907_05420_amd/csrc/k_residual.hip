@@ -209,12 +209,13 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
     __shared__ double wred[4 * RBT], ared[4 * RBT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t nsl = (ra.nA + 63) / 64;
-    const int64_t sl = min((int64_t)blockIdx.x * 4 + (tid >> 6), nsl - 1);
-    const bool slice_on = (int64_t)blockIdx.x * 4 + (tid >> 6) < nsl;
+    int bx, n;
+    period_task(bx, n);
+    const int64_t sl = min((int64_t)bx * 4 + (tid >> 6), nsl - 1);
+    const bool slice_on = (int64_t)bx * 4 + (tid >> 6) < nsl;
     const int64_t i = 64 * sl + lane;
     const bool on = slice_on && i < ra.nA;
     const int64_t ic = on ? i : ra.nA - 1;
-    const int n = blockIdx.y;
     const int64_t ng = ra.N * ra.Ns;
     const int64_t p0 = ra.sl_off[sl];
     const int w = (int)((ra.sl_off[sl + 1] - p0) / 64);
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(256) void k_res_periods(ResidualArgs ra, const doub
             }
             __syncthreads();
             if (tid < nr) {
-                const int64_t o = (int64_t)(k0 + tid) * nw + blockIdx.y * gridDim.x + blockIdx.x;
+                const int64_t o = (int64_t)(k0 + tid) * nw + (int64_t)n * gridDim.x + bx;
                 wpart[o] = fmax(fmax(wred[tid * 4 + 0], wred[tid * 4 + 1]), fmax(wred[tid * 4 + 2], wred[tid * 4 + 3]));
                 apart[o] = (ared[tid * 4 + 0] + ared[tid * 4 + 1]) + (ared[tid * 4 + 2] + ared[tid * 4 + 3]);
             }

@@ -130,80 +130,99 @@ __device__ inline void add_child(double *v, int uc, const int32_t *rel, const do
 // children's update vectors, then y = L11^-1 v over 64-column blocks with the
 // stored inverses of the pivot blocks. Rows below the pivots leave with the
 // children's contributions only; k_fwd_rect subtracts L21 y from them.
+// Only the pivot window [p0, p0 + pw) is solved, and only its own rows take
+// its products: the window starting at 0 also does the extend-add and stores
+// every row of the front, a later one reads and stores its own rows (a wide
+// front's windows alternate with k_fwd_rect's products below each window).
 template <typename T, int RBT>
 __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
-                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
+                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa, int p0, int pw) {
     extern __shared__ double smem[];
     double *Lt = smem;             // 64 x 65 staging tile
-    double *v = smem + 64 * 65;    // m x RBT
-    const int s = tasks[blockIdx.x];
-    const int n = blockIdx.y, tid = threadIdx.x;
+    double *vw = smem + 64 * 65;   // rows [vb, ve) x RBT
+    int tx, n;
+    period_task(tx, n);
+    const int s = tasks[tx];
+    const int tid = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
     const int32_t *R = tr.rows + tr.rowptr[s];
     const int64_t ro = tr.relptr[s];
+    const int p1 = min(c, p0 + pw);
+    const bool first = p0 == 0;
+    const int vb = first ? 0 : p0, ve = first ? m : p1;
+    const int vo = vb * RBT;  // vw[i * RBT + r - vo] holds row i
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
         double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
-        for (int idx = tid; idx < m * RBT; idx += SNT) {
-            const int i = idx / RBT, r = idx % RBT;
-            v[idx] = (r < nr && i < c) ? x0[(int64_t)r * sa.nv + R[i]] : 0.0;
+        for (int idx = tid; idx < (ve - vb) * RBT; idx += SNT) {
+            const int i = vb + idx / RBT, r = idx % RBT;
+            vw[idx] = (r < nr && i < c) ? x0[(int64_t)r * sa.nv + R[i]] : 0.0;
         }
         __syncthreads();
-        for (int qc = tr.cptr[s]; qc < tr.cptr[s + 1]; ++qc) {
-            const int ch = tr.clist[qc];
-            const int uc = sd[ch].m - sd[ch].c;
-            const int32_t *rl = tr.rel + tr.relptr[ch];
-            for (int idx = tid; idx < uc * nr; idx += SNT) {
-                const int i = idx / nr, r = idx % nr;
-                v[rl[i] * RBT + r] += U0[(int64_t)r * sa.usz + tr.relptr[ch] + i];
+        if (first) {
+            // children's update vectors, one group of row-disjoint children at a time
+            const int32_t *rec = tr.vea + tr.vea[s];
+            const int ng = rec[0];
+            const int32_t *pr = rec + 1 + ng;
+            for (int g = 0, e0 = 0; g < ng; ++g) {
+                const int e1 = rec[1 + g];
+                for (int idx = tid; idx < (e1 - e0) * nr; idx += SNT) {
+                    const int e = e0 + idx / nr, r = idx % nr;
+                    vw[pr[2 * e + 1] * RBT + r] += U0[(int64_t)r * sa.usz + pr[2 * e]];
+                }
+                __syncthreads();
+                e0 = e1;
             }
-            __syncthreads();
         }
-        for (int k0 = 0; k0 < c; k0 += 64) {
-            const int nb = min(64, c - k0);
+        for (int k0 = p0; k0 < p1; k0 += 64) {
+            const int nb = min(64, p1 - k0);
             stage_tile<T, SNT>(Lt, P, m, k0, k0, nb, nb, true, tid);
             __syncthreads();
             const int i = tid & 63, r = tid >> 6;
             double yv = 0.0;
             if (i < nb && r < nr) {
-                yv = v[(k0 + i) * RBT + r];
-                for (int q = 0; q < i; ++q) yv += Lt[i + q * 65] * v[(k0 + q) * RBT + r];
+                yv = vw[-vo + (k0 + i) * RBT + r];
+                for (int q = 0; q < i; ++q) yv += Lt[i + q * 65] * vw[-vo + (k0 + q) * RBT + r];
             }
             __syncthreads();
-            if (i < nb && r < nr) v[(k0 + i) * RBT + r] = yv;
+            if (i < nb && r < nr) vw[-vo + (k0 + i) * RBT + r] = yv;
             __syncthreads();
-            for (int i2 = k0 + nb + tid; i2 < c; i2 += SNT) {
+            for (int i2 = k0 + nb + tid; i2 < p1; i2 += SNT) {
                 double acc[RBT];
 #pragma unroll
                 for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
-                row_dot<T, RBT>(P + i2 + (int64_t)k0 * m, m, nb, v + k0 * RBT, acc);
+                row_dot<T, RBT>(P + i2 + (int64_t)k0 * m, m, nb, vw + (k0 * RBT - vo), acc);
 #pragma unroll
-                for (int rr = 0; rr < RBT; ++rr) v[i2 * RBT + rr] -= acc[rr];
+                for (int rr = 0; rr < RBT; ++rr) vw[-vo + i2 * RBT + rr] -= acc[rr];
             }
             __syncthreads();
         }
-        for (int idx = tid; idx < m * nr; idx += SNT) {
-            const int i = idx / nr, r = idx % nr;
-            if (i < c) x0[(int64_t)r * sa.nv + R[i]] = v[i * RBT + r];
-            else U0[(int64_t)r * sa.usz + ro + (i - c)] = v[i * RBT + r];
+        for (int idx = tid; idx < (ve - vb) * nr; idx += SNT) {
+            const int i = vb + idx / nr, r = idx % nr;
+            if (i < c) x0[(int64_t)r * sa.nv + R[i]] = vw[-vo + i * RBT + r];
+            else U0[(int64_t)r * sa.usz + ro + (i - c)] = vw[-vo + i * RBT + r];
         }
         __syncthreads();
     }
 }
 
 // Forward pass, rows below the pivots: u -= L21 y for 64 update rows of a
-// front per workgroup (four column groups, reduced at the end).
+// front per workgroup (four column groups, reduced at the end). With qw > 0
+// the rows are pivot rows of a wide front below its window [q0w, q0w + qw):
+// v -= L[rows, window] y_window on those pivot rows.
 template <typename T, int RBT>
 __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd,
-                                                  const RowTask *tasks, TreeArgs tr, SolveArgs sa) {
+                                                  const RowTask *tasks, TreeArgs tr, SolveArgs sa, int q0w, int qw) {
     __shared__ double yb[256 * RBT];
     __shared__ double red[4 * 64 * RBT];
-    const RowTask tk = tasks[blockIdx.x];
+    int tx, n;
+    period_task(tx, n);
+    const RowTask tk = tasks[tx];
     const int s = tk.f, i0 = tk.r0;
-    const int n = blockIdx.y, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
@@ -212,15 +231,17 @@ __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, c
     const int a = tid & 63, g = tid >> 6;
     const int i = i0 + a;
     const T *rowp = P + min(i, m - 1);
+    const int qb = qw > 0 ? q0w : 0, qe = qw > 0 ? min(c, q0w + qw) : c;
+    const int iend = qw > 0 ? c : m;
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
-        const double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
         double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
         double acc[RBT];
 #pragma unroll
         for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
-        for (int q0 = 0; q0 < c; q0 += 256) {
-            const int nq = min(256, c - q0);
+        for (int q0 = qb; q0 < qe; q0 += 256) {
+            const int nq = min(256, qe - q0);
             gather_rows<RBT, 256>(yb, 256, nq, R + q0, x0, sa.nv, nr, tid);
             __syncthreads();
             const int qa = 64 * g;
@@ -230,11 +251,12 @@ __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, c
 #pragma unroll
         for (int rr = 0; rr < RBT; ++rr) red[(g * 64 + a) * RBT + rr] = acc[rr];
         __syncthreads();
-        if (g == 0 && i < m) {
+        if (g == 0 && i < iend) {
             for (int rr = 0; rr < nr; ++rr) {
                 const double t = red[(0 * 64 + a) * RBT + rr] + red[(1 * 64 + a) * RBT + rr] +
                                  red[(2 * 64 + a) * RBT + rr] + red[(3 * 64 + a) * RBT + rr];
-                U0[(int64_t)rr * sa.usz + ro + (i - c)] -= t;
+                if (qw > 0) x0[(int64_t)rr * sa.nv + R[i]] -= t;
+                else U0[(int64_t)rr * sa.usz + ro + (i - c)] -= t;
             }
         }
         __syncthreads();
@@ -244,31 +266,36 @@ __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, c
 // Backward pass, rows below the pivots: for 64 pivot columns per workgroup,
 // z = D^-1 v - L21^T x_below with x_below the ancestors' final values (L
 // tiles staged through LDS so that global reads run down the columns). z
-// replaces v in place; k_bwd_tri finishes with L11^T.
+// replaces v in place; k_bwd_tri finishes with L11^T. With qw > 0 the rows
+// are a solved pivot window [q0w, q0w + qw) of a wide front and the columns
+// lie before it: z -= L[window, columns]^T x_window, without the division.
 template <typename T, int RBT>
 __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd,
-                                                  const RowTask *tasks, TreeArgs tr, SolveArgs sa) {
+                                                  const RowTask *tasks, TreeArgs tr, SolveArgs sa, int q0w, int qw) {
     __shared__ double Lt[64 * 65];
     __shared__ double xb[64 * RBT];
     __shared__ double red[4 * 64 * RBT];
-    const RowTask tk = tasks[blockIdx.x];
+    int tx, n;
+    period_task(tx, n);
+    const RowTask tk = tasks[tx];
     const int s = tk.f, q0 = tk.r0;
-    const int n = blockIdx.y, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
-    if (m == c) return;
+    if (qw == 0 && m == c) return;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
     const int32_t *R = tr.rows + tr.rowptr[s];
     const int q = tid & 63, g = tid >> 6;
-    const int ncol = min(64, c - q0);
+    const int ncol = min(64, (qw > 0 ? q0w : c) - q0);
+    const int ib0 = qw > 0 ? q0w : c, ib1 = qw > 0 ? min(c, q0w + qw) : m;
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
         double acc[RBT];
 #pragma unroll
         for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
-        for (int ib = c; ib < m; ib += 64) {
-            const int nrow = min(64, m - ib);
+        for (int ib = ib0; ib < ib1; ib += 64) {
+            const int nrow = min(64, ib1 - ib);
             stage_tile<T, 256>(Lt, P, m, ib, q0, nrow, ncol, false, tid);
             gather_rows<RBT, 256>(xb, 64, nrow, R + ib, x0, sa.nv, nr, tid);
             __syncthreads();
@@ -284,12 +311,12 @@ __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, c
         for (int rr = 0; rr < RBT; ++rr) red[(g * 64 + q) * RBT + rr] = acc[rr];
         __syncthreads();
         if (g == 0 && q < ncol) {
-            const double dq = (double)P[(q0 + q) + (int64_t)(q0 + q) * m];
+            const double dq = qw > 0 ? 1.0 : (double)P[(q0 + q) + (int64_t)(q0 + q) * m];
             for (int rr = 0; rr < nr; ++rr) {
                 const double t = red[(0 * 64 + q) * RBT + rr] + red[(1 * 64 + q) * RBT + rr] +
                                  red[(2 * 64 + q) * RBT + rr] + red[(3 * 64 + q) * RBT + rr];
                 double *xp = x0 + (int64_t)rr * sa.nv + R[q0 + q];
-                *xp = *xp / dq - t;
+                *xp = (qw > 0 ? *xp : *xp / dq) - t;
             }
         }
         __syncthreads();
@@ -300,16 +327,20 @@ __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, c
 // 64-column blocks from the last, z_b -= L[below b, b]^T x (rows < c only),
 // then x_b = X_b^T z_b with X_b the stored inverse of the pivot block. The
 // division by D and the rows below the pivots were applied by k_bwd_rect,
-// except for fronts without such rows.
+// except for fronts without such rows. Only the pivot window [p0, p0 + pw)
+// is solved, with the rows of the window: the later windows of a wide front
+// were applied to it by k_bwd_rect's window products.
 template <typename T, int RBT>
 __global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
-                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
+                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa, int p0, int pw) {
     extern __shared__ double smem[];
     double *Lt = smem;                 // 128 x 64 staging tile (ld 129)
     double *red = smem + 129 * 64;     // 8 groups x 64 columns x RBT partial sums
-    double *v = red + 8 * 64 * RBT;    // c x RBT
-    const int s = tasks[blockIdx.x];
-    const int n = blockIdx.y, tid = threadIdx.x;
+    double *vw = red + 8 * 64 * RBT;   // rows [p0, p1) x RBT
+    int tx, n;
+    period_task(tx, n);
+    const int s = tasks[tx];
+    const int tid = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
     if (c == 0) return;
@@ -317,33 +348,35 @@ __global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, co
     const int32_t *R = tr.rows + tr.rowptr[s];
     const int q = tid & 63, g = tid >> 6;
     const bool divide = m == c;
+    const int p1 = min(c, p0 + pw);
+    const int vo = p0 * RBT;  // vw[i * RBT + r - vo] holds row i
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
-        gather_rows<RBT, SNT>(v, c, c, R, x0, sa.nv, nr, tid);
+        gather_rows<RBT, SNT>(vw, p1 - p0, p1 - p0, R + p0, x0, sa.nv, nr, tid);
         if (divide) {
             __syncthreads();
-            for (int i = tid; i < c; i += SNT) {
+            for (int i = p0 + tid; i < p1; i += SNT) {
                 const double dd = (double)P[i + (int64_t)i * m];
 #pragma unroll
-                for (int r = 0; r < RBT; ++r) v[i * RBT + r] /= dd;
+                for (int r = 0; r < RBT; ++r) vw[-vo + i * RBT + r] /= dd;
             }
         }
         __syncthreads();
-        for (int kb = ((c - 1) / 64) * 64; kb >= 0; kb -= 64) {
-            const int nb = min(64, c - kb);
+        for (int kb = p0 + ((p1 - p0 - 1) / 64) * 64; kb >= p0; kb -= 64) {
+            const int nb = min(64, p1 - kb);
             double acc[RBT];
 #pragma unroll
             for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
-            for (int ib = kb + nb; ib < c; ib += 128) {
-                const int nrow = min(128, c - ib);
+            for (int ib = kb + nb; ib < p1; ib += 128) {
+                const int nrow = min(128, p1 - ib);
                 stage_tile<T, SNT, 128>(Lt, P, m, ib, kb, nrow, nb, false, tid);
                 __syncthreads();
                 const int a1 = min(16 * g + 16, nrow);
                 for (int a = 16 * g; a < a1; ++a) {
                     const double l = Lt[a + q * 129];
 #pragma unroll
-                    for (int rr = 0; rr < RBT; ++rr) acc[rr] += l * v[(ib + a) * RBT + rr];
+                    for (int rr = 0; rr < RBT; ++rr) acc[rr] += l * vw[-vo + (ib + a) * RBT + rr];
                 }
                 __syncthreads();
             }
@@ -355,21 +388,21 @@ __global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, co
                 double t = 0.0;
 #pragma unroll
                 for (int gg = 0; gg < 8; ++gg) t += red[(gg * 64 + q) * RBT + g];
-                v[(kb + q) * RBT + g] -= t;
+                vw[-vo + (kb + q) * RBT + g] -= t;
             }
             __syncthreads();
             double xv = 0.0;
             if (g < nr && q < nb) {
-                xv = v[(kb + q) * RBT + g];
-                for (int i = q + 1; i < nb; ++i) xv += Lt[i + q * 65] * v[(kb + i) * RBT + g];
+                xv = vw[-vo + (kb + q) * RBT + g];
+                for (int i = q + 1; i < nb; ++i) xv += Lt[i + q * 65] * vw[-vo + (kb + i) * RBT + g];
             }
             __syncthreads();
-            if (g < nr && q < nb) v[(kb + q) * RBT + g] = xv;
+            if (g < nr && q < nb) vw[-vo + (kb + q) * RBT + g] = xv;
             __syncthreads();
         }
-        for (int idx = tid; idx < c * nr; idx += SNT) {
-            const int i = idx / nr, r = idx % nr;
-            x0[(int64_t)r * sa.nv + R[i]] = v[i * RBT + r];
+        for (int idx = tid; idx < (p1 - p0) * nr; idx += SNT) {
+            const int i = p0 + idx / nr, r = idx % nr;
+            x0[(int64_t)r * sa.nv + R[i]] = vw[-vo + i * RBT + r];
         }
         __syncthreads();
     }
@@ -381,8 +414,10 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_fwd_small(const T *L, int64_t Lstride, const FrontDesc *sd,
                                                   const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
     __shared__ double vs[64 * RB];
-    const int s = tasks[blockIdx.x];
-    const int n = blockIdx.y, i = threadIdx.x;
+    int tx, n;
+    period_task(tx, n);
+    const int s = tasks[tx];
+    const int i = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
@@ -453,8 +488,10 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_bwd_small(const T *L, int64_t Lstride, const FrontDesc *sd,
                                                   const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
     __shared__ double vs[64 * RB];
-    const int s = tasks[blockIdx.x];
-    const int n = blockIdx.y, i = threadIdx.x;
+    int tx, n;
+    period_task(tx, n);
+    const int s = tasks[tx];
+    const int i = threadIdx.x;
     const FrontDesc d = sd[s];
     const int m = d.m, c = d.c;
     if (c == 0) return;
@@ -817,67 +854,108 @@ static int rhs_block(int64_t nrhs, int rows, size_t fixed) {
 }
 
 template <typename T, int RBT>
-static void fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *large, int nlarge, int maxm,
-                    const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+static void fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxm,
+                    int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     const size_t lds = sizeof(double) * ((size_t)maxm * RBT + 64 * 65);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)k_fwd_tri<T, RBT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_fwd_tri<T, RBT>), dim3(nlarge, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, large,
-                       tr, sa);
+    hipLaunchKernelGGL((k_fwd_tri<T, RBT>), dim3(nfront, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, fronts,
+                       tr, sa, p0, pw);
 }
 
 template <typename T, int RBT>
-static void bwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *large, int nlarge, int maxc,
-                    const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+static void bwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxc,
+                    int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     const size_t lds = sizeof(double) * ((size_t)maxc * RBT + 129 * 64 + 8 * 64 * RBT);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)k_bwd_tri<T, RBT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_bwd_tri<T, RBT>), dim3(nlarge, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, large,
-                       tr, sa);
+    hipLaunchKernelGGL((k_bwd_tri<T, RBT>), dim3(nfront, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, fronts,
+                       tr, sa, p0, pw);
 }
 
+template <typename T>
+static void fwd_tri_rb(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxm,
+                       int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+    if (nfront <= 0) return;
+    const int rb = rhs_block(sa.nrhs, maxm, sizeof(double) * 64 * 65);
+    if (rb == 4) fwd_tri<T, 4>(L, Lstride, sd, fronts, nfront, maxm, p0, pw, tr, sa, st);
+    else if (rb == 2) fwd_tri<T, 2>(L, Lstride, sd, fronts, nfront, maxm, p0, pw, tr, sa, st);
+    else fwd_tri<T, 1>(L, Lstride, sd, fronts, nfront, maxm, p0, pw, tr, sa, st);
+}
+
+template <typename T>
+static void bwd_tri_rb(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxc,
+                       int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+    if (nfront <= 0) return;
+    const int rb = rhs_block(sa.nrhs, maxc, sizeof(double) * (129 * 64 + 8 * 64 * RB));
+    if (rb == 4) bwd_tri<T, 4>(L, Lstride, sd, fronts, nfront, maxc, p0, pw, tr, sa, st);
+    else if (rb == 2) bwd_tri<T, 2>(L, Lstride, sd, fronts, nfront, maxc, p0, pw, tr, sa, st);
+    else bwd_tri<T, 1>(L, Lstride, sd, fronts, nfront, maxc, p0, pw, tr, sa, st);
+}
+
+template <typename T>
+static void fwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd, const RowTask *rows, int nrows, int q0w, int qw,
+                     const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+    if (nrows <= 0) return;
+    const dim3 g(nrows, (unsigned)sa.N);
+    if (sa.nrhs >= 3)
+        hipLaunchKernelGGL((k_fwd_rect<T, 4>), g, dim3(256), 0, st, L, Lstride, sd, rows, tr, sa, q0w, qw);
+    else if (sa.nrhs >= 2)
+        hipLaunchKernelGGL((k_fwd_rect<T, 2>), g, dim3(256), 0, st, L, Lstride, sd, rows, tr, sa, q0w, qw);
+    else
+        hipLaunchKernelGGL((k_fwd_rect<T, 1>), g, dim3(256), 0, st, L, Lstride, sd, rows, tr, sa, q0w, qw);
+}
+
+template <typename T>
+static void bwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd, const RowTask *cols, int ncols, int q0w, int qw,
+                     const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+    if (ncols <= 0) return;
+    const dim3 g(ncols, (unsigned)sa.N);
+    if (sa.nrhs >= 3)
+        hipLaunchKernelGGL((k_bwd_rect<T, 4>), g, dim3(256), 0, st, L, Lstride, sd, cols, tr, sa, q0w, qw);
+    else if (sa.nrhs >= 2)
+        hipLaunchKernelGGL((k_bwd_rect<T, 2>), g, dim3(256), 0, st, L, Lstride, sd, cols, tr, sa, q0w, qw);
+    else
+        hipLaunchKernelGGL((k_bwd_rect<T, 1>), g, dim3(256), 0, st, L, Lstride, sd, cols, tr, sa, q0w, qw);
+}
+
+constexpr int WHOLE = 1 << 30;  // pivot window covering every pivot
+
+// Forward level: small fronts, the pivot part of the other fronts (a wide
+// front window by window, each window's products with the pivot rows below
+// it spread over 64-row workgroups), then their update rows.
 template <typename T>
 void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
                       SolveArgs sa, hipStream_t st) {
     if (lt.nsmall > 0)
         hipLaunchKernelGGL(k_fwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
                            tr, sa);
-    if (lt.nlarge <= 0) return;
-    const int rb = rhs_block(sa.nrhs, lt.maxm, sizeof(double) * 64 * 65);
-    if (rb == 4) fwd_tri<T, 4>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
-    else if (rb == 2) fwd_tri<T, 2>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
-    else fwd_tri<T, 1>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, tr, sa, st);
-    if (lt.nrect_rows > 0) {
-        const dim3 g(lt.nrect_rows, (unsigned)sa.N);
-        if (sa.nrhs >= 3)
-            hipLaunchKernelGGL((k_fwd_rect<T, 4>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_rows, tr, sa);
-        else if (sa.nrhs >= 2)
-            hipLaunchKernelGGL((k_fwd_rect<T, 2>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_rows, tr, sa);
-        else
-            hipLaunchKernelGGL((k_fwd_rect<T, 1>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_rows, tr, sa);
+    fwd_tri_rb<T>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, 0, WHOLE, tr, sa, st);
+    for (int w = 0; w < lt.nwin; ++w) {
+        const TriWindow &tw = lt.win[w];
+        fwd_tri_rb<T>(L, Lstride, sd, tw.fronts, tw.nfront, lt.maxm, tw.p0, TRI_W, tr, sa, st);
+        fwd_rect<T>(L, Lstride, sd, tw.rows, tw.nrows, tw.p0, TRI_W, tr, sa, st);
     }
+    fwd_rect<T>(L, Lstride, sd, lt.rect_rows, lt.nrect_rows, 0, 0, tr, sa, st);
 }
 
+// Backward level: small fronts, the update rows of the other fronts, then
+// their pivot part (a wide front window by window from the last, each
+// window's products with the pivot columns before it spread over 64-column
+// workgroups).
 template <typename T>
 void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
                       SolveArgs sa, hipStream_t st) {
     if (lt.nsmall > 0)
         hipLaunchKernelGGL(k_bwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
                            tr, sa);
-    if (lt.nlarge <= 0) return;
-    if (lt.nrect_cols > 0) {
-        const dim3 g(lt.nrect_cols, (unsigned)sa.N);
-        if (sa.nrhs >= 3)
-            hipLaunchKernelGGL((k_bwd_rect<T, 4>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_cols, tr, sa);
-        else if (sa.nrhs >= 2)
-            hipLaunchKernelGGL((k_bwd_rect<T, 2>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_cols, tr, sa);
-        else
-            hipLaunchKernelGGL((k_bwd_rect<T, 1>), g, dim3(256), 0, st, L, Lstride, sd, lt.rect_cols, tr, sa);
+    bwd_rect<T>(L, Lstride, sd, lt.rect_cols, lt.nrect_cols, 0, 0, tr, sa, st);
+    bwd_tri_rb<T>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, 0, WHOLE, tr, sa, st);
+    for (int w = lt.nwin - 1; w >= 0; --w) {
+        const TriWindow &tw = lt.win[w];
+        bwd_tri_rb<T>(L, Lstride, sd, tw.fronts, tw.nfront, lt.maxc, tw.p0, TRI_W, tr, sa, st);
+        bwd_rect<T>(L, Lstride, sd, tw.cols, tw.ncols, tw.p0, TRI_W, tr, sa, st);
     }
-    const int rb = rhs_block(sa.nrhs, lt.maxc, sizeof(double) * (129 * 64 + 8 * 64 * RB));
-    if (rb == 4) bwd_tri<T, 4>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, tr, sa, st);
-    else if (rb == 2) bwd_tri<T, 2>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, tr, sa, st);
-    else bwd_tri<T, 1>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, tr, sa, st);
 }
 
 void launch_scatter_x(double *x, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa, const double *xg,

@@ -33,6 +33,10 @@ struct TreeArgs {
     const int32_t *rel;
     const int32_t *rows;
     const int64_t *rowptr;
+    // children's update rows by front: vea[vea[s]] = ng groups, then the
+    // groups' cumulative entry counts, then (update-vector offset, front row)
+    // pairs; within a group no two entries share a front row
+    const int32_t *vea;
 };
 
 // One launch of the blocked right-looking factorisation over a group of large
@@ -72,7 +76,7 @@ template <typename T>
 void launch_small_fronts(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *tasks, const int *ncls, int64_t N,
                          const TreeArgs &tr, hipStream_t st);
 template <typename T>
-void launch_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const RowTask *tasks, int ntasks, int64_t N,
+void launch_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const EaTask *tasks, int ntasks, int64_t N,
                        const TreeArgs &tr, hipStream_t st);
 template <typename T>
 void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_t N, hipStream_t st);
@@ -88,14 +92,27 @@ struct SolveArgs {
 template <typename T>
 void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa,
                        hipStream_t st);
+// Fronts with more than TRI_W pivots (and rows below them) go through the
+// pivot part of the solves in windows of TRI_W pivots: one workgroup per
+// front solves a window, and the products of the window with the rest of the
+// pivot part are spread over many workgroups.
+constexpr int TRI_W = 256;
+struct TriWindow {
+    int p0;                      // first pivot of the window
+    const int32_t *fronts;       // wide fronts with more than p0 pivots
+    const RowTask *rows;         // (front, first row) of 64 pivot rows after the window
+    const RowTask *cols;         // (front, first column) of 64 pivot columns before the window
+    int nfront, nrows, ncols;
+};
 // device task lists of one level for the solve kernels
 struct LevelTasks {
     const int32_t *small;        // fronts of at most 64 rows
-    const int32_t *large;        // the others
-    const RowTask *rect_rows;    // (front, first row) of 64 update rows of large fronts
-    const RowTask *rect_cols;    // (front, first column) of 64 pivot columns of large fronts
-    int nsmall, nlarge, nrect_rows, nrect_cols;
-    int maxm, maxc;              // largest rows / pivots of the large fronts
+    const int32_t *large;        // the others, except the wide ones
+    const RowTask *rect_rows;    // (front, first row) of 64 update rows of large and wide fronts
+    const RowTask *rect_cols;    // (front, first column) of 64 pivot columns of large and wide fronts
+    const TriWindow *win;        // pivot windows of the wide fronts (host array)
+    int nsmall, nlarge, nrect_rows, nrect_cols, nwin;
+    int maxm, maxc;              // largest rows / pivots of the large and wide fronts
 };
 
 template <typename T>

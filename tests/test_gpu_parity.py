@@ -202,6 +202,34 @@ def test_parity_small(case):
 # solves use: a second block 16 wide, a second block of exactly half width
 # (built from two 256-wide inverses, no second half to combine), and three
 # blocks with a 52-wide tail
+def test_parity_wide_fronts_unrefined():
+    """A front with more pivots than two of the solves' 256-pivot windows
+    (526 pivots in the growth-free order: windows of 256, 256 and 14, each
+    window solved by one workgroup per period and its products with the
+    rest of the pivot part spread over many): with refine_max = 0 the
+    solution meets the small cases' bar (1e-11, or 3 x the oracle's
+    unrefined Algorithm 1 in the same order) and matches the oracle's
+    unrefined Algorithm 1 element by element, for 3 right-hand sides (one
+    pass of four with a padded one) and for 1."""
+    import paper_1907_05420_amd as pk
+    for nrhs in (3, 1):
+        inst = kktgen.make_small(nb=400, nextra=200, ng=50, ns=20, N=2, nrhs=nrhs, seed=21,
+                                 barrier_range=(1e-2, 1e2))
+        st, _ = pk.kkt_plan(inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind, inst.C0_rowptr,
+                            inst.C0_colind, inst.C1_rowptr, inst.C1_colind, dual_wait=GROWTH_FREE)
+        assert st["max_pivots"] > 2 * 256
+        K = ah.assemble(inst)
+        ora = sc.algorithm1(inst)
+        g = run_gpu(inst, want_schur=False, refine_max=0, dual_wait=GROWTH_FREE)
+        rel = ah.rel_residual_ld(inst, g["x"], inst.b, K)
+        rel_g = ah.rel_residual_ld(inst, oracle_in_order(inst, GROWTH_FREE)["x"], inst.b, K)
+        assert rel <= max(1e-11, 3.0 * rel_g), (nrhs, rel, rel_g)
+        assert g["info"]["refine_iters"] == 0 and g["rc_solve"] == 0
+        assert_x_close(g["x"], ora["x"], 1e-10, 1e-7)
+        inn = g["inertia"]
+        assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == ora["inertia"] and inn["n_perturbed"] == 0
+
+
 DENSE_BLOCKS = [
     dict(nb=40, nextra=20, ng=6, ns=40, N=26, nrhs=2, seed=15),    # n_g = 1040
     dict(nb=60, nextra=30, ng=6, ns=48, N=32, nrhs=1, seed=16),    # n_g = 1536
