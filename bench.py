@@ -382,8 +382,9 @@ def main():
     ap.add_argument("--recompute-periods", type=int, default=0,
                     help="hold the factors of this many periods only and recompute them in every solve pass "
                          "(0 = keep all)")
-    ap.add_argument("--dual-wait", type=int, default=0,
-                    help="elimination order: primal neighbours a dual waits for (0 = library default)")
+    ap.add_argument("--dual-wait", type=int, default=-1,
+                    help="elimination order: primal neighbours a dual waits for (0 = library default, "
+                         "-1 = autotuned on the workload before the timed steps)")
     ap.add_argument("--schur", default="both", choices=["both", "dense", "structured"],
                     help="mesh2000_N96: factor S densely (the timed value), by structured block elimination, or "
                          "both (dense timed, structured reported beside it)")
@@ -413,6 +414,11 @@ def main():
     vals2 = kktgen.redraw_barrier(inst, rng)
     prec = pk.KKT_MIXED if args.precision == "mixed" else pk.KKT_FP64
     main_mode = pk.KKT_SCHUR_STRUCTURED if args.schur == "structured" else pk.KKT_SCHUR_DENSE
+    order_times = None
+    if args.dual_wait < 0:
+        # elimination order tuned once for the network (untimed, like the analysis)
+        from paper_1907_05420_amd import autotune
+        args.dual_wait, order_times = autotune.tune_order(inst, prec, schur_mode=main_mode, log=log)
     m = measure(args, inst, vals2, prec, log, schur_mode=main_mode)
     ph = m["phases"]
     ng = inst.n_g
@@ -467,6 +473,9 @@ def main():
                    "storage": w["ns"], "periods": w["N"], "block_rows": inst.n_A, "schur_dim": ng,
                    "nrhs": w["nrhs"], "barrier_range": list(w["barrier"]), "precision": args.precision,
                    "refine": args.refine, "recompute_periods": args.recompute_periods,
+                   "dual_wait": args.dual_wait,
+                   "dual_wait_tuned_ms": ({str(k): round(v, 2) for k, v in order_times.items()}
+                                          if order_times else None),
                    "schur": "structured" if main_mode == pk.KKT_SCHUR_STRUCTURED else "dense"},
         "device_bytes": m["stats"]["footprint_after"],
         "p50_ms": float(np.percentile(m["lat_ms"], 50)),

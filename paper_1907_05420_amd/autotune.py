@@ -1,7 +1,7 @@
 """Autotuning of tile shapes and stream counts for batches of KKT systems.
 
 Host-side timing loops over the C-ABI: every candidate runs the library's own
-kernels on the device, and the fastest is kept. Two knobs:
+kernels on the device, and the fastest is kept. Three knobs:
 
 * big_tile_rows (kkt_options): the trailing-update size from which the
   128x128 MFMA tile kernel replaces the 64x64 one. Tuned per size class (the
@@ -9,6 +9,12 @@ kernels on the device, and the fastest is kept. Two knobs:
   the class's largest member, by the measured factorisation time.
 * the number of streams a batch spreads its instances over, by the measured
   time of runs of the whole batch.
+* dual_wait (kkt_options): how many primal neighbours a dual waits for in the
+  elimination order. Fewer give fronts with fewer update entries (less
+  extend-add traffic) but more factor flops on some networks; the measured
+  factorisation plus refined solve of the instance decides. The pattern is
+  the same in every interior-point iteration, so this is tuned once per
+  network.
 """
 from __future__ import annotations
 
@@ -19,6 +25,7 @@ import time
 
 CANDIDATE_ROWS = (256, 512, 1024, 2048)
 CANDIDATE_STREAMS = (2, 4, 8)
+CANDIDATE_DUAL_WAIT = (2, 4)
 
 
 def size_class(inst, stats):
@@ -95,3 +102,28 @@ def tune_streams(batch, refine_steps, candidates=CANDIDATE_STREAMS, reps=2, log=
             best, best_t = ns, t
     batch.restream(best)
     return best
+
+
+def tune_order(inst, precision=0, candidates=CANDIDATE_DUAL_WAIT, reps=1, schur_mode=0, log=None):
+    """dual_wait with the shortest measured factorisation + refined solve of
+    `inst` (best of reps + 1 runs each). Returns (choice, {dual_wait: ms})."""
+    import torch
+    from . import Solver, device_inputs
+    d = device_inputs(inst)
+    x = torch.empty_like(d["b"])
+    times = {}
+    for dw in candidates:
+        s = Solver(inst, precision=precision, dual_wait=dw, schur_mode=schur_mode)
+        best = float("inf")
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.factor(d["vals"], d["C0"], d["C1"], d["corner"], want_inertia=False)
+            s.solve(d["b"], x)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        s.close()
+        times[dw] = best * 1e3
+        if log:
+            log(f"order dual_wait {dw}: {times[dw]:.2f} ms per factor + solve")
+    return min(times, key=times.get), times
