@@ -239,7 +239,6 @@ __global__ __launch_bounds__(64) void k_small_front(FactorArgs<T> fa, const Fron
 // --------------------------------------------------------------------------
 // large fronts
 // --------------------------------------------------------------------------
-constexpr int EA_RL = 1024;  // staged target columns of an extend-add tile
 
 template <typename T>
 __device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q);
@@ -269,58 +268,64 @@ __device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q) {
     return q < c ? P + r + (int64_t)q * m : Ub + (r - c) + (int64_t)(q - c) * (m - c);
 }
 
-// Extend-add of the children's update blocks into 64-row tiles of a large
-// front. The child rows landing in a tile form one contiguous range (the
-// relative indices increase), so every tile owns its target rows; the task
-// lists the children with rows in the tile and those ranges, and they are
-// added one after another in increasing order.
+// Extend-add of the children's update blocks into tiles of 64 rows by EA_CW
+// columns of a large front. The child rows and columns landing in a tile
+// each form one contiguous range (the relative indices increase), so every
+// tile owns its target entries; the task lists those ranges for the children
+// that reach the tile, and they are added one after another in increasing
+// order. The tile first clears its entries of the front's update block
+// (rows and columns at or past the pivots, lower triangle): nothing else
+// writes them before, so the update blocks need no clearing pass (their
+// strict upper triangles are never read).
 template <typename T>
 __global__ __launch_bounds__(256) void k_extend_add(FactorArgs<T> fa, const FrontDesc *sd, const EaTask *tasks,
                                                     const int32_t *segs, const int64_t *relptr, const int32_t *rel) {
-    __shared__ int32_t rls[EA_RL];
+    __shared__ int32_t rls[EA_CW];
     const EaTask tk = tasks[blockIdx.x];
     const int n = blockIdx.y;
     const FrontDesc d = sd[tk.f];
+    const int m = d.m, c = d.c;
+    const int r1 = min(tk.r0 + 64, m), c1 = min(tk.c0 + EA_CW, r1);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     T *P = fa.L + (int64_t)n * fa.Lstride + d.Loff;
     T *Ub = fa.U + (int64_t)n * fa.Ustride + d.Uoff;
+    {
+        const int r = max(tk.r0, c) + lane, q0 = max(tk.c0, c);
+        if (r < r1)
+            for (int q = q0 + wv; q < c1 && q <= r; q += 4) Ub[(r - c) + (int64_t)(q - c) * (m - c)] = T(0);
+    }
     for (int k = 0; k < tk.nseg; ++k) {
-        const int32_t *sg = segs + tk.seg + 3 * k;
-        const int ch = sg[0], i_lo = sg[1], i_hi = sg[2];
+        const int32_t *sg = segs + tk.seg + EA_SEG * k;
+        const int ch = sg[0], i_lo = sg[1], i_hi = sg[2], j_lo = sg[3], jn = sg[4] - sg[3];
         const FrontDesc dc = sd[ch];
         const int uc = dc.m - dc.c;
         const T *Uc = fa.U + (int64_t)n * fa.Ustride + dc.Uoff;
         const int32_t *rl = rel + relptr[ch];
-        // the columns j <= i_hi - 1 of those rows, target column indices staged
-        for (int j0 = 0; j0 < i_hi; j0 += EA_RL) {
-            const int jn = min(EA_RL, i_hi - j0);
-            __syncthreads();
-            for (int t = threadIdx.x; t < jn; t += 256) rls[t] = rl[j0 + t];
-            __syncthreads();
-            const int i = i_lo + lane;
-            if (i < i_hi) {
-                const int R = rl[i];
-                const T *Ui = Uc + i;
-                const int jend = min(jn, i - j0 + 1);
-                for (int jj = wv; jj < jend; jj += 32) {
-                    T v[8];
-                    T *ad[8];
+        __syncthreads();
+        for (int t = threadIdx.x; t < jn; t += 256) rls[t] = rl[j_lo + t];
+        __syncthreads();
+        const int i = i_lo + lane;
+        if (i < i_hi) {
+            const int R = rl[i];
+            const T *Ui = Uc + i;
+            const int jend = min(jn, i - j_lo + 1);  // columns j <= i
+            for (int jj = wv; jj < jend; jj += 32) {
+                T v[8];
+                T *ad[8];
 #pragma unroll
-                    for (int u2 = 0; u2 < 8; ++u2) {
-                        const int jc = min(jj + 4 * u2, jend - 1);
-                        v[u2] = Ui[(int64_t)(j0 + jc) * uc];
-                        ad[u2] = front_addr(P, Ub, d.m, d.c, R, rls[jc]);
-                    }
-                    T o[8];
-#pragma unroll
-                    for (int u2 = 0; u2 < 8; ++u2) o[u2] = *ad[u2];
-#pragma unroll
-                    for (int u2 = 0; u2 < 8; ++u2)
-                        if (jj + 4 * u2 < jend) *ad[u2] = o[u2] + v[u2];
+                for (int u2 = 0; u2 < 8; ++u2) {
+                    const int jc = min(jj + 4 * u2, jend - 1);
+                    v[u2] = Ui[(int64_t)(j_lo + jc) * uc];
+                    ad[u2] = front_addr(P, Ub, m, c, R, rls[jc]);
                 }
+                T o[8];
+#pragma unroll
+                for (int u2 = 0; u2 < 8; ++u2) o[u2] = *ad[u2];
+#pragma unroll
+                for (int u2 = 0; u2 < 8; ++u2)
+                    if (jj + 4 * u2 < jend) *ad[u2] = o[u2] + v[u2];
             }
         }
-        __syncthreads();
     }
 }
 
