@@ -44,6 +44,7 @@ struct LevelPlan {
     int maxm = 0, maxm_large = 0, maxc_large = 0;
     int step_begin = 0, step_end = 0;
     int win_begin = 0, win_end = 0;  // pivot windows of the wide fronts (solve)
+    int maxc_wide = 0;
 };
 
 // a pivot window of the solve's wide fronts as offsets into the task buffer
@@ -396,9 +397,8 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             if (S.nrow[t] > S.ncol[t])
                 for (int q0 = 0; q0 < S.ncol[t]; q0 += 64) { buf.push_back(t); buf.push_back(q0); ++lp.nrcol; }
         lp.win_begin = (int)ctx->win_plan.size();
-        int maxc_wide = 0;
-        for (int32_t t : wide) maxc_wide = std::max(maxc_wide, S.ncol[t]);
-        for (int p0 = 0; p0 < maxc_wide; p0 += TRI_W) {
+        for (int32_t t : wide) lp.maxc_wide = std::max(lp.maxc_wide, S.ncol[t]);
+        for (int p0 = 0; p0 < lp.maxc_wide; p0 += TRI_W) {
             WindowPlan w;
             w.p0 = p0;
             w.f_off = (int64_t)buf.size();
@@ -719,6 +719,11 @@ int factor_range(kkt_ctx *ctx, int64_t p0, int64_t np, int64_t *cnt) {
         launch_extend_add<T>(fa, ctx->d_sd, (const EaTask *)(ctx->d_tasks + lp.ea_off), lp.nea, np, tr, st);
         for (int q = lp.step_begin; q < lp.step_end; ++q)
             launch_step<T>(fa, ctx->d_sd, step_dev(ctx->steps[q], ctx->d_tasks), np, st);
+        if (lp.win_end > lp.win_begin) {
+            // the solves' windows of the wide fronts: their diagonal blocks inverted
+            const WindowPlan &w0 = ctx->win_plan[lp.win_begin];
+            launch_window_inverses<T>(fa, ctx->d_sd, ctx->d_tasks + w0.f_off, w0.nfront, lp.maxc_wide, np, st);
+        }
     }
     return KKT_OK;
 }

@@ -98,6 +98,17 @@ __device__ inline void period_task(int &task, int &n) {
     }
 }
 
+__device__ inline double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// butterfly sum over the wavefront (the same order on every run)
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 template <typename T> struct Acc;
 template <> struct Acc<double> { typedef v4d type; };
 template <> struct Acc<float> { typedef v4f type; };

@@ -886,17 +886,18 @@ __global__ __launch_bounds__(256, 2) void k_update_big(FactorArgs<T> fa, const F
     }
 }
 
-// In-place inverse of the unit lower 256x256 diagonal block of a dense
-// factor (FP64, after its outer panel is complete), from the inverses of its
-// 64x64 diagonal sub-blocks: for every sub-block column j and row i > j,
+// In-place inverse of the unit lower 256x256 diagonal block of a factor
+// (after the panel holding it is complete), from the inverses of its 64x64
+// diagonal sub-blocks: for every sub-block column j and row i > j,
 //   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj     (X_jj unit lower, stored below
 // its diagonal), processed column by column so that every L_ik still needed
-// is intact. Products on MFMA through the 64x64 tile helpers.
-__global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl,
-                                                int j0) {
-    typedef Acc<double>::type acc_t;
-    __shared__ double sA[NB * LDS_LD];
-    __shared__ double sB[NB * LDS_LD];
+// is intact. Products on MFMA through the 64x64 tile helpers. blockIdx.x
+// picks the front, blockIdx.y the diagonal block, blockIdx.z the period.
+template <typename T>
+__global__ __launch_bounds__(256) void k_inv256(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl, int j0) {
+    typedef typename Acc<T>::type acc_t;
+    __shared__ T sA[NB * LDS_LD];
+    __shared__ T sB[NB * LDS_LD];
     const FrontDesc d = sd[fl[blockIdx.x]];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m = d.m;
@@ -904,15 +905,15 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
     if (j0 >= d.c) return;
     const int nbw = min(INV_W, d.c - j0);
     const int nsb = (nbw + 63) / 64;
-    double *P = fa.L + d.Loff;
+    T *P = fa.L + (int64_t)blockIdx.z * fa.Lstride + d.Loff;
     const int row = tid & 63, kk = tid >> 6;
     // load a 64x64 sub-block (rows r0.., cols c0..) as sX[k][r] = M[r][k]
     // (transposed, "A" operand) or sX[k][q] = M[k][q] ("B" operand); unit
     // lower when diag.
-    auto load = [&](double *sX, int r0, int c0, bool asA, bool diag) {
+    auto load = [&](T *sX, int r0, int c0, bool asA, bool diag) {
         // clamped addresses, all 16 loads issued before the first use
         const int lim = j0 + nbw - 1;
-        double val[16];
+        T val[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int k = kk + 4 * j;
@@ -924,8 +925,8 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
             const int k = kk + 4 * j;
             const int a = asA ? row : k, b = asA ? k : row;
             const bool in = r0 + a <= lim && c0 + b <= lim;
-            double v = in ? val[j] : 0.0;
-            if (diag) v = a > b ? v : (a == b ? 1.0 : 0.0);
+            T v = in ? val[j] : T(0);
+            if (diag) v = a > b ? v : (a == b ? T(1) : T(0));
             sX[k * LDS_LD + row] = v;
         }
     };
@@ -941,11 +942,11 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
                 load(sA, j0 + 64 * i, j0 + 64 * k, true, false);        // L_ik
                 load(sB, j0 + 64 * k, j0 + 64 * j, false, k == j);      // X_kj
                 __syncthreads();
-                tile_mma<double>(sA, sB, acc, lane, w);
+                tile_mma<T>(sA, sB, acc, lane, w);
             }
             // T -> sB as a "B" operand (sB[k][q] = T[k][q]), X_ii -> sA
             __syncthreads();
-            double *sC = sB;
+            T *sC = sB;
             {
                 const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
                 const int li = lane & 15, lk = lane >> 4;
@@ -955,7 +956,7 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
                     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
                         for (int rr = 0; rr < 4; ++rr)
-                            sC[(wr + bi * 16 + mfma_row(0.0, lk, rr)) * LDS_LD + (wc + bj * 16 + li)] = acc[bi][bj][rr];
+                            sC[(wr + bi * 16 + mfma_row(T(0), lk, rr)) * LDS_LD + (wc + bj * 16 + li)] = acc[bi][bj][rr];
             }
             load(sA, j0 + 64 * i, j0 + 64 * i, true, true);             // X_ii
             __syncthreads();
@@ -963,9 +964,9 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
-            tile_mma<double>(sA, sB, acc, lane, w);
+            tile_mma<T>(sA, sB, acc, lane, w);
             __syncthreads();
-            tile_stage<double>(sA, acc, lane, w);
+            tile_stage<T>(sA, acc, lane, w);
             __syncthreads();
             const int r = j0 + 64 * i + row;
             if (r < j0 + nbw)
@@ -975,6 +976,38 @@ __global__ __launch_bounds__(256) void k_inv256(FactorArgs<double> fa, const Fro
                 }
         }
     }
+}
+
+// Copy of the inverted INV_W window of a wide front (strictly below its
+// diagonal) into the window's strict upper triangle, transposed, so that the
+// backward solve reads X^T with the same row-wise products as the forward
+// solve reads X. The upper triangle of a front's pivot block holds nothing
+// else. 64x64 tiles through LDS: blockIdx.x the front, blockIdx.y the
+// window, blockIdx.z the period.
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_transpose(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fl) {
+    __shared__ T tile[64 * 65];
+    const FrontDesc d = sd[fl[blockIdx.x]];
+    const int j0 = INV_W * blockIdx.y;
+    if (j0 >= d.c) return;
+    const int nbw = min(INV_W, d.c - j0), nsb = (nbw + 63) / 64;
+    const int m = d.m;
+    T *P = fa.L + (int64_t)blockIdx.z * fa.Lstride + d.Loff + j0 + (int64_t)j0 * m;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int kb = 0; kb < nsb; ++kb)
+        for (int qb = 0; qb <= kb; ++qb) {
+            // tile rows 64 kb + a, columns 64 qb + q (a lane, q over the waves)
+            const int r = min(64 * kb + lane, nbw - 1);
+            for (int q = w; q < 64; q += 4) tile[lane + q * 65] = P[r + (int64_t)min(64 * qb + q, nbw - 1) * m];
+            __syncthreads();
+            // written transposed: row 64 qb + lane, column 64 kb + a
+            const int i = 64 * qb + lane;
+            for (int a = w; a < 64; a += 4) {
+                const int col = 64 * kb + a;
+                if (i < nbw && col < nbw && col > i) P[i + (int64_t)col * m] = tile[a + lane * 65];
+            }
+            __syncthreads();
+        }
 }
 
 // Inverse of the unit lower 2W block [ja, ja + 2W) of a dense factor from
@@ -1059,7 +1092,16 @@ __global__ __launch_bounds__(256) void k_inv_combine(FactorArgs<double> fa, cons
 }
 
 void launch_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, hipStream_t st) {
-    hipLaunchKernelGGL(k_inv256, dim3(1), dim3(256), 0, st, fa, sd, fl, j0);
+    hipLaunchKernelGGL(k_inv256<double>, dim3(1), dim3(256), 0, st, fa, sd, fl, j0);
+}
+
+template <typename T>
+void launch_window_inverses(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxc,
+                            int64_t N, hipStream_t st) {
+    if (nfront <= 0 || maxc <= 0) return;
+    const dim3 g(nfront, (unsigned)((maxc + INV_W - 1) / INV_W), (unsigned)N);
+    hipLaunchKernelGGL(k_inv256<T>, g, dim3(256), 0, st, fa, sd, fronts, 0);
+    hipLaunchKernelGGL(k_win_transpose<T>, g, dim3(256), 0, st, fa, sd, fronts);
 }
 
 void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, int c, double *tmp,
@@ -1074,7 +1116,8 @@ void launch_inv_combine(FactorArgs<double> fa, const FrontDesc *sd, const int32_
 void launch_inverses_all(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int c, double *tmp,
                          hipStream_t st) {
     if (c <= 0) return;
-    hipLaunchKernelGGL(k_inv256, dim3(1, (unsigned)((c + INV_W - 1) / INV_W)), dim3(256), 0, st, fa, sd, fl, 0);
+    hipLaunchKernelGGL(k_inv256<double>, dim3(1, (unsigned)((c + INV_W - 1) / INV_W)), dim3(256), 0, st, fa, sd, fl,
+                       0);
     // 2 INV_W blocks from pairs of INV_W ones, then DENSE_INV_W blocks
     for (int W = INV_W; 2 * W <= DENSE_INV_W && c > W; W *= 2) {
         const int pairs = (c + 2 * W - 1) / (2 * W);
@@ -1265,7 +1308,9 @@ void launch_step(FactorArgs<T> fa, const FrontDesc *sd, const StepDev &s, int64_
                                          const TreeArgs &, hipStream_t);                                  \
     template void launch_extend_add<T>(FactorArgs<T>, const FrontDesc *, const EaTask *, int, int64_t,    \
                                        const TreeArgs &, hipStream_t);                                    \
-    template void launch_step<T>(FactorArgs<T>, const FrontDesc *, const StepDev &, int64_t, hipStream_t);
+    template void launch_step<T>(FactorArgs<T>, const FrontDesc *, const StepDev &, int64_t, hipStream_t); \
+    template void launch_window_inverses<T>(FactorArgs<T>, const FrontDesc *, const int32_t *, int, int, int64_t, \
+                                            hipStream_t);
 KKT_INST(double)
 KKT_INST(float)
 template void launch_zero<int64_t>(int64_t *, int64_t, hipStream_t);

@@ -27,16 +27,6 @@ __device__ inline void block_scan256(double *buf, int tid) {
     }
 }
 
-__device__ inline double wave_max(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-    return v;
-}
-
-// butterfly sum over the wavefront (the same order on every run)
-__device__ inline double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
 // s + e = a + b exactly (Knuth's TwoSum; no branch on the magnitudes)
 __device__ inline void two_sum(double a, double b, double &s, double &e) {

@@ -130,16 +130,14 @@ __device__ inline void add_child(double *v, int uc, const int32_t *rel, const do
 // children's update vectors, then y = L11^-1 v over 64-column blocks with the
 // stored inverses of the pivot blocks. Rows below the pivots leave with the
 // children's contributions only; k_fwd_rect subtracts L21 y from them.
-// Only the pivot window [p0, p0 + pw) is solved, and only its own rows take
-// its products: the window starting at 0 also does the extend-add and stores
-// every row of the front, a later one reads and stores its own rows (a wide
-// front's windows alternate with k_fwd_rect's products below each window).
+// With npiv = 0 only the extend-add is done (a wide front, whose pivot part
+// k_fwd_win solves window by window).
 template <typename T, int RBT>
 __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
-                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa, int p0, int pw) {
+                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa, int npiv) {
     extern __shared__ double smem[];
     double *Lt = smem;             // 64 x 65 staging tile
-    double *vw = smem + 64 * 65;   // rows [vb, ve) x RBT
+    double *v = smem + 64 * 65;    // m x RBT
     int tx, n;
     period_task(tx, n);
     const int s = tasks[tx];
@@ -149,20 +147,17 @@ __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, co
     const T *P = L + (int64_t)n * Lstride + d.Loff;
     const int32_t *R = tr.rows + tr.rowptr[s];
     const int64_t ro = tr.relptr[s];
-    const int p1 = min(c, p0 + pw);
-    const bool first = p0 == 0;
-    const int vb = first ? 0 : p0, ve = first ? m : p1;
-    const int vo = vb * RBT;  // vw[i * RBT + r - vo] holds row i
+    const int p1 = min(c, npiv);
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
         double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
-        for (int idx = tid; idx < (ve - vb) * RBT; idx += SNT) {
-            const int i = vb + idx / RBT, r = idx % RBT;
-            vw[idx] = (r < nr && i < c) ? x0[(int64_t)r * sa.nv + R[i]] : 0.0;
+        for (int idx = tid; idx < m * RBT; idx += SNT) {
+            const int i = idx / RBT, r = idx % RBT;
+            v[idx] = (r < nr && i < c) ? x0[(int64_t)r * sa.nv + R[i]] : 0.0;
         }
         __syncthreads();
-        if (first) {
+        {
             // children's update vectors, one group of row-disjoint children at a time
             const int32_t *rec = tr.vea + tr.vea[s];
             const int ng = rec[0];
@@ -171,39 +166,39 @@ __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, co
                 const int e1 = rec[1 + g];
                 for (int idx = tid; idx < (e1 - e0) * nr; idx += SNT) {
                     const int e = e0 + idx / nr, r = idx % nr;
-                    vw[pr[2 * e + 1] * RBT + r] += U0[(int64_t)r * sa.usz + pr[2 * e]];
+                    v[pr[2 * e + 1] * RBT + r] += U0[(int64_t)r * sa.usz + pr[2 * e]];
                 }
                 __syncthreads();
                 e0 = e1;
             }
         }
-        for (int k0 = p0; k0 < p1; k0 += 64) {
+        for (int k0 = 0; k0 < p1; k0 += 64) {
             const int nb = min(64, p1 - k0);
             stage_tile<T, SNT>(Lt, P, m, k0, k0, nb, nb, true, tid);
             __syncthreads();
             const int i = tid & 63, r = tid >> 6;
             double yv = 0.0;
             if (i < nb && r < nr) {
-                yv = vw[-vo + (k0 + i) * RBT + r];
-                for (int q = 0; q < i; ++q) yv += Lt[i + q * 65] * vw[-vo + (k0 + q) * RBT + r];
+                yv = v[(k0 + i) * RBT + r];
+                for (int q = 0; q < i; ++q) yv += Lt[i + q * 65] * v[(k0 + q) * RBT + r];
             }
             __syncthreads();
-            if (i < nb && r < nr) vw[-vo + (k0 + i) * RBT + r] = yv;
+            if (i < nb && r < nr) v[(k0 + i) * RBT + r] = yv;
             __syncthreads();
             for (int i2 = k0 + nb + tid; i2 < p1; i2 += SNT) {
                 double acc[RBT];
 #pragma unroll
                 for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
-                row_dot<T, RBT>(P + i2 + (int64_t)k0 * m, m, nb, vw + (k0 * RBT - vo), acc);
+                row_dot<T, RBT>(P + i2 + (int64_t)k0 * m, m, nb, v + k0 * RBT, acc);
 #pragma unroll
-                for (int rr = 0; rr < RBT; ++rr) vw[-vo + i2 * RBT + rr] -= acc[rr];
+                for (int rr = 0; rr < RBT; ++rr) v[i2 * RBT + rr] -= acc[rr];
             }
             __syncthreads();
         }
-        for (int idx = tid; idx < (ve - vb) * nr; idx += SNT) {
-            const int i = vb + idx / nr, r = idx % nr;
-            if (i < c) x0[(int64_t)r * sa.nv + R[i]] = vw[-vo + i * RBT + r];
-            else U0[(int64_t)r * sa.usz + ro + (i - c)] = vw[-vo + i * RBT + r];
+        for (int idx = tid; idx < m * nr; idx += SNT) {
+            const int i = idx / nr, r = idx % nr;
+            if (i < c) x0[(int64_t)r * sa.nv + R[i]] = v[i * RBT + r];
+            else U0[(int64_t)r * sa.usz + ro + (i - c)] = v[i * RBT + r];
         }
         __syncthreads();
     }
@@ -327,16 +322,14 @@ __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, c
 // 64-column blocks from the last, z_b -= L[below b, b]^T x (rows < c only),
 // then x_b = X_b^T z_b with X_b the stored inverse of the pivot block. The
 // division by D and the rows below the pivots were applied by k_bwd_rect,
-// except for fronts without such rows. Only the pivot window [p0, p0 + pw)
-// is solved, with the rows of the window: the later windows of a wide front
-// were applied to it by k_bwd_rect's window products.
+// except for fronts without such rows.
 template <typename T, int RBT>
 __global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
-                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa, int p0, int pw) {
+                                                 const int32_t *tasks, TreeArgs tr, SolveArgs sa) {
     extern __shared__ double smem[];
     double *Lt = smem;                 // 128 x 64 staging tile (ld 129)
     double *red = smem + 129 * 64;     // 8 groups x 64 columns x RBT partial sums
-    double *vw = red + 8 * 64 * RBT;   // rows [p0, p1) x RBT
+    double *v = red + 8 * 64 * RBT;    // c x RBT
     int tx, n;
     period_task(tx, n);
     const int s = tasks[tx];
@@ -348,35 +341,33 @@ __global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, co
     const int32_t *R = tr.rows + tr.rowptr[s];
     const int q = tid & 63, g = tid >> 6;
     const bool divide = m == c;
-    const int p1 = min(c, p0 + pw);
-    const int vo = p0 * RBT;  // vw[i * RBT + r - vo] holds row i
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
-        gather_rows<RBT, SNT>(vw, p1 - p0, p1 - p0, R + p0, x0, sa.nv, nr, tid);
+        gather_rows<RBT, SNT>(v, c, c, R, x0, sa.nv, nr, tid);
         if (divide) {
             __syncthreads();
-            for (int i = p0 + tid; i < p1; i += SNT) {
+            for (int i = tid; i < c; i += SNT) {
                 const double dd = (double)P[i + (int64_t)i * m];
 #pragma unroll
-                for (int r = 0; r < RBT; ++r) vw[-vo + i * RBT + r] /= dd;
+                for (int r = 0; r < RBT; ++r) v[i * RBT + r] /= dd;
             }
         }
         __syncthreads();
-        for (int kb = p0 + ((p1 - p0 - 1) / 64) * 64; kb >= p0; kb -= 64) {
-            const int nb = min(64, p1 - kb);
+        for (int kb = ((c - 1) / 64) * 64; kb >= 0; kb -= 64) {
+            const int nb = min(64, c - kb);
             double acc[RBT];
 #pragma unroll
             for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
-            for (int ib = kb + nb; ib < p1; ib += 128) {
-                const int nrow = min(128, p1 - ib);
+            for (int ib = kb + nb; ib < c; ib += 128) {
+                const int nrow = min(128, c - ib);
                 stage_tile<T, SNT, 128>(Lt, P, m, ib, kb, nrow, nb, false, tid);
                 __syncthreads();
                 const int a1 = min(16 * g + 16, nrow);
                 for (int a = 16 * g; a < a1; ++a) {
                     const double l = Lt[a + q * 129];
 #pragma unroll
-                    for (int rr = 0; rr < RBT; ++rr) acc[rr] += l * vw[-vo + (ib + a) * RBT + rr];
+                    for (int rr = 0; rr < RBT; ++rr) acc[rr] += l * v[(ib + a) * RBT + rr];
                 }
                 __syncthreads();
             }
@@ -388,22 +379,68 @@ __global__ __launch_bounds__(SNT) void k_bwd_tri(const T *L, int64_t Lstride, co
                 double t = 0.0;
 #pragma unroll
                 for (int gg = 0; gg < 8; ++gg) t += red[(gg * 64 + q) * RBT + g];
-                vw[-vo + (kb + q) * RBT + g] -= t;
+                v[(kb + q) * RBT + g] -= t;
             }
             __syncthreads();
             double xv = 0.0;
             if (g < nr && q < nb) {
-                xv = vw[-vo + (kb + q) * RBT + g];
-                for (int i = q + 1; i < nb; ++i) xv += Lt[i + q * 65] * vw[-vo + (kb + i) * RBT + g];
+                xv = v[(kb + q) * RBT + g];
+                for (int i = q + 1; i < nb; ++i) xv += Lt[i + q * 65] * v[(kb + i) * RBT + g];
             }
             __syncthreads();
-            if (g < nr && q < nb) vw[-vo + (kb + q) * RBT + g] = xv;
+            if (g < nr && q < nb) v[(kb + q) * RBT + g] = xv;
             __syncthreads();
         }
-        for (int idx = tid; idx < (p1 - p0) * nr; idx += SNT) {
-            const int i = p0 + idx / nr, r = idx % nr;
-            x0[(int64_t)r * sa.nv + R[i]] = vw[-vo + i * RBT + r];
+        for (int idx = tid; idx < c * nr; idx += SNT) {
+            const int i = idx / nr, r = idx % nr;
+            x0[(int64_t)r * sa.nv + R[i]] = v[i * RBT + r];
         }
+        __syncthreads();
+    }
+}
+
+// Pivot window [p0, p0 + TRI_W) of a wide front, whose diagonal block holds
+// the inverse X of its unit lower triangle below the diagonal and X^T above
+// it (built after the factorisation): y = X v (forward, UPPER false) or
+// x = X^T z (backward, UPPER true) in place for the window's rows, as
+// products along the rows of the stored triangle: 1024 threads as 256 rows
+// by four 64-column quarters, the loads of a quarter in flight in batches.
+template <typename T, int RBT, bool UPPER>
+__global__ __launch_bounds__(1024) void k_win(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts,
+                                              TreeArgs tr, SolveArgs sa, int p0) {
+    __shared__ double v[TRI_W * RBT];
+    __shared__ double part[4 * TRI_W * RBT];
+    int tx, n;
+    period_task(tx, n);
+    const int s = fronts[tx];
+    const FrontDesc d = sd[s];
+    const int m = d.m, c = d.c;
+    const int nw = min(TRI_W, c - p0);
+    const T *P = L + (int64_t)n * Lstride + d.Loff + p0 + (int64_t)p0 * m;  // the window's diagonal block
+    const int32_t *R = tr.rows + tr.rowptr[s] + p0;
+    const int tid = threadIdx.x, i = tid & (TRI_W - 1), g = tid >> 8;
+    // columns [qa, qb) of row i: below the diagonal (q < i) or above it (q > i)
+    const int qa = UPPER ? max(64 * g, i + 1) : 64 * g;
+    const int qb = UPPER ? min(64 * g + 64, nw) : min(64 * g + 64, min(i, nw));
+    for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
+        const int nr = min(RBT, (int)sa.nrhs - k0r);
+        double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+        if (g == 0)
+#pragma unroll
+            for (int r = 0; r < RBT; ++r) v[i * RBT + r] = (i < nw && r < nr) ? x0[(int64_t)r * sa.nv + R[i]] : 0.0;
+        __syncthreads();
+        double acc[RBT];
+#pragma unroll
+        for (int r = 0; r < RBT; ++r) acc[r] = 0.0;
+        if (i < nw && qb > qa) row_dot<T, RBT>(P + i + (int64_t)qa * m, m, qb - qa, v + qa * RBT, acc);
+#pragma unroll
+        for (int r = 0; r < RBT; ++r) part[(g * TRI_W + i) * RBT + r] = acc[r];
+        __syncthreads();
+        if (g == 0 && i < nw)
+            for (int r = 0; r < nr; ++r)
+                x0[(int64_t)r * sa.nv + R[i]] = v[i * RBT + r] + ((part[i * RBT + r] + part[(TRI_W + i) * RBT + r]) +
+                                                                  (part[(2 * TRI_W + i) * RBT + r] +
+                                                                   part[(3 * TRI_W + i) * RBT + r]));
         __syncthreads();
     }
 }
@@ -855,42 +892,60 @@ static int rhs_block(int64_t nrhs, int rows, size_t fixed) {
 
 template <typename T, int RBT>
 static void fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxm,
-                    int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+                    int npiv, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     const size_t lds = sizeof(double) * ((size_t)maxm * RBT + 64 * 65);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)k_fwd_tri<T, RBT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_fwd_tri<T, RBT>), dim3(nfront, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, fronts,
-                       tr, sa, p0, pw);
+                       tr, sa, npiv);
 }
 
 template <typename T, int RBT>
 static void bwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxc,
-                    int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+                    const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     const size_t lds = sizeof(double) * ((size_t)maxc * RBT + 129 * 64 + 8 * 64 * RBT);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)k_bwd_tri<T, RBT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_bwd_tri<T, RBT>), dim3(nfront, (unsigned)sa.N), dim3(SNT), lds, st, L, Lstride, sd, fronts,
-                       tr, sa, p0, pw);
+                       tr, sa);
 }
 
 template <typename T>
 static void fwd_tri_rb(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxm,
-                       int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+                       int npiv, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     if (nfront <= 0) return;
     const int rb = rhs_block(sa.nrhs, maxm, sizeof(double) * 64 * 65);
-    if (rb == 4) fwd_tri<T, 4>(L, Lstride, sd, fronts, nfront, maxm, p0, pw, tr, sa, st);
-    else if (rb == 2) fwd_tri<T, 2>(L, Lstride, sd, fronts, nfront, maxm, p0, pw, tr, sa, st);
-    else fwd_tri<T, 1>(L, Lstride, sd, fronts, nfront, maxm, p0, pw, tr, sa, st);
+    if (rb == 4) fwd_tri<T, 4>(L, Lstride, sd, fronts, nfront, maxm, npiv, tr, sa, st);
+    else if (rb == 2) fwd_tri<T, 2>(L, Lstride, sd, fronts, nfront, maxm, npiv, tr, sa, st);
+    else fwd_tri<T, 1>(L, Lstride, sd, fronts, nfront, maxm, npiv, tr, sa, st);
 }
 
 template <typename T>
 static void bwd_tri_rb(const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxc,
-                       int p0, int pw, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+                       const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
     if (nfront <= 0) return;
     const int rb = rhs_block(sa.nrhs, maxc, sizeof(double) * (129 * 64 + 8 * 64 * RB));
-    if (rb == 4) bwd_tri<T, 4>(L, Lstride, sd, fronts, nfront, maxc, p0, pw, tr, sa, st);
-    else if (rb == 2) bwd_tri<T, 2>(L, Lstride, sd, fronts, nfront, maxc, p0, pw, tr, sa, st);
-    else bwd_tri<T, 1>(L, Lstride, sd, fronts, nfront, maxc, p0, pw, tr, sa, st);
+    if (rb == 4) bwd_tri<T, 4>(L, Lstride, sd, fronts, nfront, maxc, tr, sa, st);
+    else if (rb == 2) bwd_tri<T, 2>(L, Lstride, sd, fronts, nfront, maxc, tr, sa, st);
+    else bwd_tri<T, 1>(L, Lstride, sd, fronts, nfront, maxc, tr, sa, st);
+}
+
+// the window kernels: up to four right-hand sides per pass (LDS 40 KiB)
+template <typename T>
+static void win_solve(bool fwd, const T *L, int64_t Lstride, const FrontDesc *sd, const int32_t *fronts, int nfront,
+                      int p0, const TreeArgs &tr, SolveArgs sa, hipStream_t st) {
+    if (nfront <= 0) return;
+    const dim3 g(nfront, (unsigned)sa.N);
+    if (sa.nrhs >= 3) {
+        if (fwd) hipLaunchKernelGGL((k_win<T, 4, false>), g, dim3(1024), 0, st, L, Lstride, sd, fronts, tr, sa, p0);
+        else hipLaunchKernelGGL((k_win<T, 4, true>), g, dim3(1024), 0, st, L, Lstride, sd, fronts, tr, sa, p0);
+    } else if (sa.nrhs == 2) {
+        if (fwd) hipLaunchKernelGGL((k_win<T, 2, false>), g, dim3(1024), 0, st, L, Lstride, sd, fronts, tr, sa, p0);
+        else hipLaunchKernelGGL((k_win<T, 2, true>), g, dim3(1024), 0, st, L, Lstride, sd, fronts, tr, sa, p0);
+    } else {
+        if (fwd) hipLaunchKernelGGL((k_win<T, 1, false>), g, dim3(1024), 0, st, L, Lstride, sd, fronts, tr, sa, p0);
+        else hipLaunchKernelGGL((k_win<T, 1, true>), g, dim3(1024), 0, st, L, Lstride, sd, fronts, tr, sa, p0);
+    }
 }
 
 template <typename T>
@@ -919,30 +974,32 @@ static void bwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd, const Row
         hipLaunchKernelGGL((k_bwd_rect<T, 1>), g, dim3(256), 0, st, L, Lstride, sd, cols, tr, sa, q0w, qw);
 }
 
-constexpr int WHOLE = 1 << 30;  // pivot window covering every pivot
+constexpr int WHOLE = 1 << 30;  // no limit on the pivots solved
 
 // Forward level: small fronts, the pivot part of the other fronts (a wide
-// front window by window, each window's products with the pivot rows below
-// it spread over 64-row workgroups), then their update rows.
+// front's extend-add, then window by window: the window's inverse, then its
+// products with the pivot rows below it over 64-row workgroups), then their
+// update rows.
 template <typename T>
 void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
                       SolveArgs sa, hipStream_t st) {
     if (lt.nsmall > 0)
         hipLaunchKernelGGL(k_fwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
                            tr, sa);
-    fwd_tri_rb<T>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, 0, WHOLE, tr, sa, st);
+    fwd_tri_rb<T>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, WHOLE, tr, sa, st);
+    if (lt.nwin > 0) fwd_tri_rb<T>(L, Lstride, sd, lt.win[0].fronts, lt.win[0].nfront, lt.maxm, 0, tr, sa, st);
     for (int w = 0; w < lt.nwin; ++w) {
         const TriWindow &tw = lt.win[w];
-        fwd_tri_rb<T>(L, Lstride, sd, tw.fronts, tw.nfront, lt.maxm, tw.p0, TRI_W, tr, sa, st);
+        win_solve<T>(true, L, Lstride, sd, tw.fronts, tw.nfront, tw.p0, tr, sa, st);
         fwd_rect<T>(L, Lstride, sd, tw.rows, tw.nrows, tw.p0, TRI_W, tr, sa, st);
     }
     fwd_rect<T>(L, Lstride, sd, lt.rect_rows, lt.nrect_rows, 0, 0, tr, sa, st);
 }
 
 // Backward level: small fronts, the update rows of the other fronts, then
-// their pivot part (a wide front window by window from the last, each
-// window's products with the pivot columns before it spread over 64-column
-// workgroups).
+// their pivot part (a wide front window by window from the last: the
+// window's inverse, then its products with the pivot columns before it over
+// 64-column workgroups).
 template <typename T>
 void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
                       SolveArgs sa, hipStream_t st) {
@@ -950,10 +1007,10 @@ void launch_bwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const Le
         hipLaunchKernelGGL(k_bwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
                            tr, sa);
     bwd_rect<T>(L, Lstride, sd, lt.rect_cols, lt.nrect_cols, 0, 0, tr, sa, st);
-    bwd_tri_rb<T>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, 0, WHOLE, tr, sa, st);
+    bwd_tri_rb<T>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxc, tr, sa, st);
     for (int w = lt.nwin - 1; w >= 0; --w) {
         const TriWindow &tw = lt.win[w];
-        bwd_tri_rb<T>(L, Lstride, sd, tw.fronts, tw.nfront, lt.maxc, tw.p0, TRI_W, tr, sa, st);
+        win_solve<T>(false, L, Lstride, sd, tw.fronts, tw.nfront, tw.p0, tr, sa, st);
         bwd_rect<T>(L, Lstride, sd, tw.cols, tw.ncols, tw.p0, TRI_W, tr, sa, st);
     }
 }

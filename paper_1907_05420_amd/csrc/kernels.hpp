@@ -93,10 +93,12 @@ template <typename T>
 void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t *perm, SolveArgs sa,
                        hipStream_t st);
 // Fronts with more than TRI_W pivots (and rows below them) go through the
-// pivot part of the solves in windows of TRI_W pivots: one workgroup per
-// front solves a window, and the products of the window with the rest of the
-// pivot part are spread over many workgroups.
+// pivot part of the solves in windows of TRI_W pivots: the window's diagonal
+// block is inverted after the factorisation, one workgroup per front applies
+// the inverse, and the products of the window with the rest of the pivot
+// part are spread over many workgroups.
 constexpr int TRI_W = 256;
+static_assert(TRI_W == INV_W, "the solves' windows are the factor's inverted diagonal blocks");
 struct TriWindow {
     int p0;                      // first pivot of the window
     const int32_t *fronts;       // wide fronts with more than p0 pivots
@@ -138,6 +140,12 @@ void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, i
                       double *out, hipStream_t st);
 // inverse of the INV_W diagonal block at j0 of the (single) front fl[0]
 void launch_inv256(FactorArgs<double> fa, const FrontDesc *sd, const int32_t *fl, int j0, hipStream_t st);
+// the TRI_W-wide diagonal-block inverses of the pivot part of every listed
+// front of N periods (in place below the diagonal, after the front's
+// factorisation, and transposed above it): the solves' windows of wide fronts
+template <typename T>
+void launch_window_inverses(FactorArgs<T> fa, const FrontDesc *sd, const int32_t *fronts, int nfront, int maxc,
+                            int64_t N, hipStream_t st);
 // the DENSE_INV_W diagonal-block inverses of the dense factor of one front
 // with c pivots, after its factorisation (through INV_W and 2 INV_W ones;
 // tmp: W^2 doubles per 2W block at each doubling, W < DENSE_INV_W)
