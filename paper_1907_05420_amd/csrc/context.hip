@@ -387,9 +387,10 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             buf.insert(buf.end(), segs.begin(), segs.end());
         }
         if (buf.size() % 2) buf.push_back(0);  // RowTask alignment (pairs of int32)
-        // solve: 64 update rows / 64 pivot columns of each large front
+        // solve: 64 update rows / 64 pivot columns of each large front (the
+        // update rows of wide fronts go with their windows' products)
         lp.rrow_off = (int64_t)buf.size();
-        for (int32_t t : large)
+        for (int32_t t : plain)
             if (S.ncol[t] > 0)
                 for (int r0 = S.ncol[t]; r0 < S.nrow[t]; r0 += 64) { buf.push_back(t); buf.push_back(r0); ++lp.nrrow; }
         lp.rcol_off = (int64_t)buf.size();
@@ -407,7 +408,12 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             if (buf.size() % 2) buf.push_back(0);  // RowTask alignment
             w.r_off = (int64_t)buf.size();
             for (int32_t t : wide)
-                for (int r0 = p0 + TRI_W; r0 < S.ncol[t]; r0 += 64) { buf.push_back(t); buf.push_back(r0); ++w.nrows; }
+                if (S.ncol[t] > p0)
+                    for (int r0 = std::min(p0 + TRI_W, S.ncol[t]); r0 < S.nrow[t]; r0 += 64) {
+                        buf.push_back(t);
+                        buf.push_back(r0);
+                        ++w.nrows;
+                    }
             w.c_off = (int64_t)buf.size();
             for (int32_t t : wide)
                 if (S.ncol[t] > p0)

@@ -206,8 +206,9 @@ __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, co
 
 // Forward pass, rows below the pivots: u -= L21 y for 64 update rows of a
 // front per workgroup (four column groups, reduced at the end). With qw > 0
-// the rows are pivot rows of a wide front below its window [q0w, q0w + qw):
-// v -= L[rows, window] y_window on those pivot rows.
+// the rows lie below the window [q0w, q0w + qw) of a wide front and take
+// that window's product only: v -= L[rows, window] y_window, on pivot rows
+// and update rows alike.
 template <typename T, int RBT>
 __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd,
                                                   const RowTask *tasks, TreeArgs tr, SolveArgs sa, int q0w, int qw) {
@@ -227,7 +228,6 @@ __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, c
     const int i = i0 + a;
     const T *rowp = P + min(i, m - 1);
     const int qb = qw > 0 ? q0w : 0, qe = qw > 0 ? min(c, q0w + qw) : c;
-    const int iend = qw > 0 ? c : m;
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
@@ -246,11 +246,11 @@ __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, c
 #pragma unroll
         for (int rr = 0; rr < RBT; ++rr) red[(g * 64 + a) * RBT + rr] = acc[rr];
         __syncthreads();
-        if (g == 0 && i < iend) {
+        if (g == 0 && i < m) {
             for (int rr = 0; rr < nr; ++rr) {
                 const double t = red[(0 * 64 + a) * RBT + rr] + red[(1 * 64 + a) * RBT + rr] +
                                  red[(2 * 64 + a) * RBT + rr] + red[(3 * 64 + a) * RBT + rr];
-                if (qw > 0) x0[(int64_t)rr * sa.nv + R[i]] -= t;
+                if (i < c) x0[(int64_t)rr * sa.nv + R[i]] -= t;
                 else U0[(int64_t)rr * sa.usz + ro + (i - c)] -= t;
             }
         }
@@ -267,9 +267,9 @@ __global__ __launch_bounds__(256) void k_fwd_rect(const T *L, int64_t Lstride, c
 template <typename T, int RBT>
 __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd,
                                                   const RowTask *tasks, TreeArgs tr, SolveArgs sa, int q0w, int qw) {
-    __shared__ double Lt[64 * 65];
+    __shared__ double Lt[64 * 65];  // the staged tile; the partial sums at the end
     __shared__ double xb[64 * RBT];
-    __shared__ double red[4 * 64 * RBT];
+    double *red = Lt;
     int tx, n;
     period_task(tx, n);
     const RowTask tk = tasks[tx];
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, c
     const int m = d.m, c = d.c;
     if (qw == 0 && m == c) return;
     const T *P = L + (int64_t)n * Lstride + d.Loff;
+    const BufRes rs = make_bufres(P, (int64_t)m * c * sizeof(T));
     const int32_t *R = tr.rows + tr.rowptr[s];
     const int q = tid & 63, g = tid >> 6;
     const int ncol = min(64, (qw > 0 ? q0w : c) - q0);
@@ -289,12 +290,40 @@ __global__ __launch_bounds__(256) void k_bwd_rect(const T *L, int64_t Lstride, c
         double acc[RBT];
 #pragma unroll
         for (int rr = 0; rr < RBT; ++rr) acc[rr] = 0.0;
+        // the next tile's factor entries (16 per thread: row q, columns g + 4 u
+        // of the 64 x 64 tile, by buffer loads at 32-bit offsets from the
+        // front, whose at most 16 320 x 11 712 entries stay below 2^31 bytes)
+        // and, for the first 64 threads, its row's x values: loaded while the
+        // current tile is used
+        T lv[16];
+        double xv[RBT];
+        auto fetch = [&](int ib) {
+            const int nrow = min(64, ib1 - ib);
+            const int base = (int)sizeof(T) * (ib + min(q, nrow - 1) + q0 * m);
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                lv[u] = buf_load(rs, base + (int)sizeof(T) * min(g + 4 * u, ncol - 1) * m, T(0));
+            if (tid < 64) {
+                const int32_t ri = R[ib + min(tid, nrow - 1)];
+#pragma unroll
+                for (int rr = 0; rr < RBT; ++rr)
+                    xv[rr] = (tid < nrow && rr < nr) ? x0[(int64_t)rr * sa.nv + ri] : 0.0;
+            }
+        };
+        if (ib0 < ib1) fetch(ib0);
         for (int ib = ib0; ib < ib1; ib += 64) {
             const int nrow = min(64, ib1 - ib);
-            stage_tile<T, 256>(Lt, P, m, ib, q0, nrow, ncol, false, tid);
-            gather_rows<RBT, 256>(xb, 64, nrow, R + ib, x0, sa.nv, nr, tid);
-            __syncthreads();
 #pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int qq = g + 4 * u;
+                Lt[q + qq * 65] = (q < nrow && qq < ncol) ? (double)lv[u] : 0.0;
+            }
+            if (tid < 64)
+#pragma unroll
+                for (int rr = 0; rr < RBT; ++rr) xb[tid * RBT + rr] = xv[rr];
+            __syncthreads();
+            if (ib + 64 < ib1) fetch(ib + 64);
+#pragma unroll 4
             for (int a = 16 * g; a < 16 * g + 16; ++a) {
                 const double l = Lt[a + q * 65];
 #pragma unroll
@@ -976,10 +1005,10 @@ static void bwd_rect(const T *L, int64_t Lstride, const FrontDesc *sd, const Row
 
 constexpr int WHOLE = 1 << 30;  // no limit on the pivots solved
 
-// Forward level: small fronts, the pivot part of the other fronts (a wide
-// front's extend-add, then window by window: the window's inverse, then its
-// products with the pivot rows below it over 64-row workgroups), then their
-// update rows.
+// Forward level: small fronts, the pivot part of the other fronts and their
+// update rows (a wide front's extend-add, then window by window: the
+// window's inverse, then its products with every row below it over 64-row
+// workgroups).
 template <typename T>
 void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const LevelTasks &lt, const TreeArgs &tr,
                       SolveArgs sa, hipStream_t st) {

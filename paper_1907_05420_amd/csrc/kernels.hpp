@@ -102,7 +102,7 @@ static_assert(TRI_W == INV_W, "the solves' windows are the factor's inverted dia
 struct TriWindow {
     int p0;                      // first pivot of the window
     const int32_t *fronts;       // wide fronts with more than p0 pivots
-    const RowTask *rows;         // (front, first row) of 64 pivot rows after the window
+    const RowTask *rows;         // (front, first row) of 64 rows after the window (pivot and update rows)
     const RowTask *cols;         // (front, first column) of 64 pivot columns before the window
     int nfront, nrows, ncols;
 };
@@ -110,7 +110,7 @@ struct TriWindow {
 struct LevelTasks {
     const int32_t *small;        // fronts of at most 64 rows
     const int32_t *large;        // the others, except the wide ones
-    const RowTask *rect_rows;    // (front, first row) of 64 update rows of large and wide fronts
+    const RowTask *rect_rows;    // (front, first row) of 64 update rows of the large fronts that are not wide
     const RowTask *rect_cols;    // (front, first column) of 64 pivot columns of large and wide fronts
     const TriWindow *win;        // pivot windows of the wide fronts (host array)
     int nsmall, nlarge, nrect_rows, nrect_cols, nwin;
