@@ -45,6 +45,24 @@ def test_mixed_small(case):
         assert np.max(np.abs(g["Sbar"] - sb)) <= 1e-5 * np.max(np.abs(sb))
 
 
+def test_mixed_wide_front():
+    """FP32 factors with a 526-pivot front (growth-free order: the solves'
+    256-pivot windows, inverted in FP32 after the factorisation): refinement
+    reaches the FP64 bar on the oracle's K without falling back, x matches
+    the oracle's, and the inertia is exact."""
+    from test_gpu_parity import GROWTH_FREE
+    inst = kktgen.make_small(nb=400, nextra=200, ng=50, ns=20, N=2, nrhs=3, seed=21, barrier_range=(1e-2, 1e2))
+    ref, xref, K = reference(inst)
+    g = run_gpu(inst, precision=KKT_MIXED, want_schur=False, dual_wait=GROWTH_FREE)
+    rel = ah.rel_residual_ld(inst, g["x"], inst.b, K)
+    assert rel <= 1e-10, rel
+    assert g["info"]["fallback_used"] == 0 and g["rc_solve"] == 0
+    assert _rel(g["x"], xref) <= 1e-9, _rel(g["x"], xref)
+    expect = (inst.N * inst.n_primal, inst.N * (inst.n_A - inst.n_primal) + inst.n_g, 0)
+    inn = g["inertia"]
+    assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == expect
+
+
 def test_mixed_ring30():
     inst = kktgen.make_workload(1)
     ref, xref, K = reference(inst)
