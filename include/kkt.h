@@ -186,8 +186,12 @@ int kkt_create(kkt_ctx **ctx, void *stream, const kkt_options *opt);
  * and extend-add maps; then allocates device factors and workspace. Host
  * time only plus one host->device copy of the maps. May be called again
  * (re-analysis frees the previous state). Returns KKT_ERR_ARG when a front
- * has more than 16 320 rows or 11 712 pivots (the triangular solves keep a
- * front's vector in the 160 KiB of LDS of one workgroup) or N*Ns > 46 000. */
+ * with at most 256 pivots, or without rows below its pivots, has more than
+ * 16 320 rows or 11 712 pivots (the triangular solves keep such a front's
+ * vector in the 160 KiB of LDS of one workgroup), when a front with more
+ * pivots and rows below them has a factor panel of 2^31 bytes or more
+ * (rows x pivots x 8; its solves stream the vector through HBM with 32-bit
+ * offsets), or when N*Ns > 46 000. */
 int kkt_analyze(kkt_ctx *ctx, const kkt_structure *s);
 
 /* Exact device bytes the context holds after kkt_analyze (for admission). */

@@ -322,8 +322,10 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             if (S.nrow[t] <= 64) small.push_back(t);
             else {
                 large.push_back(t);
-                lp.maxm_large = std::max(lp.maxm_large, S.nrow[t]);
-                lp.maxc_large = std::max(lp.maxc_large, S.ncol[t]);
+                if (!wide_front(S.nrow[t], S.ncol[t])) {  // the solve vectors held in LDS
+                    lp.maxm_large = std::max(lp.maxm_large, S.nrow[t]);
+                    lp.maxc_large = std::max(lp.maxc_large, S.ncol[t]);
+                }
             }
         }
         lp.small_off = (int64_t)buf.size();
@@ -341,7 +343,7 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         buf.insert(buf.end(), all.begin(), all.end());
         // the solve's pivot part: wide fronts window by window, the others whole
         std::vector<int32_t> plain, wide;
-        for (int32_t t : large) (S.ncol[t] > TRI_W && S.nrow[t] > S.ncol[t] ? wide : plain).push_back(t);
+        for (int32_t t : large) (wide_front(S.nrow[t], S.ncol[t]) ? wide : plain).push_back(t);
         lp.large_off = (int64_t)buf.size();
         lp.nlarge = (int)plain.size();
         buf.insert(buf.end(), plain.begin(), plain.end());
@@ -1043,11 +1045,19 @@ int analyze_checked(const kkt_structure *s, const kkt_options &o, Symbolic &S) {
         if (o.verbose) std::fprintf(stderr, "kkt_analyze: %s\n", err.c_str());
         return KKT_ERR_STRUCT;
     }
-    // fronts whose solve vectors fit in LDS; 32-bit launch and index limits of
-    // the dense S; the structured Schur's block inverses cover Ns <= 2 INV_W
+    // fronts whose solve vectors must fit in LDS (all but the wide ones, whose
+    // solves go window by window through HBM; those need their factor panel
+    // below 2^31 bytes for 32-bit buffer offsets); 32-bit launch and index
+    // limits of the dense S; the structured Schur's block inverses cover
+    // Ns <= 2 INV_W
     const bool structured = o.schur_mode == KKT_SCHUR_STRUCTURED;
-    if (S.max_front > MAX_FRONT_ROWS || S.max_pivots > MAX_FRONT_PIVOTS || (!structured && s->N * s->Ns > 46000) ||
-        (structured && s->Ns > 2 * INV_W)) {
+    bool fronts_ok = true;
+    for (int32_t t = 0; t < S.nsup && fronts_ok; ++t) {
+        const int m = S.nrow[t], c = S.ncol[t];
+        fronts_ok = wide_front(m, c) ? (int64_t)m * c * 8 < ((int64_t)1 << 31)
+                                     : (m <= MAX_FRONT_ROWS && c <= MAX_FRONT_PIVOTS);
+    }
+    if (!fronts_ok || (!structured && s->N * s->Ns > 46000) || (structured && s->Ns > 2 * INV_W)) {
         if (o.verbose)
             std::fprintf(stderr, "kkt_analyze: front of %lld rows / %lld pivots or Schur size %lld over the limits\n",
                          (long long)S.max_front, (long long)S.max_pivots, (long long)(s->N * s->Ns));

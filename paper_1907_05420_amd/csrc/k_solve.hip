@@ -130,8 +130,10 @@ __device__ inline void add_child(double *v, int uc, const int32_t *rel, const do
 // children's update vectors, then y = L11^-1 v over 64-column blocks with the
 // stored inverses of the pivot blocks. Rows below the pivots leave with the
 // children's contributions only; k_fwd_rect subtracts L21 y from them.
-// With npiv = 0 only the extend-add is done (a wide front, whose pivot part
-// k_fwd_win solves window by window).
+// With npiv = 0 only the extend-add is done, in place in HBM (a wide front,
+// whose pivot part k_win solves window by window): the front's update
+// vector cleared, then the children's groups added to it and to the pivot
+// rows' x, with no vector in LDS (any front size).
 template <typename T, int RBT>
 __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, const FrontDesc *sd,
                                                  const int32_t *tasks, TreeArgs tr, SolveArgs sa, int npiv) {
@@ -148,6 +150,34 @@ __global__ __launch_bounds__(SNT) void k_fwd_tri(const T *L, int64_t Lstride, co
     const int32_t *R = tr.rows + tr.rowptr[s];
     const int64_t ro = tr.relptr[s];
     const int p1 = min(c, npiv);
+    if (npiv == 0) {
+        const int32_t *rec = tr.vea + tr.vea[s];
+        const int ng = rec[0];
+        const int32_t *pr = rec + 1 + ng;
+        for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
+            const int nr = min(RBT, (int)sa.nrhs - k0r);
+            double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
+            double *U0 = sa.uv + ((int64_t)n * sa.nrhs + k0r) * sa.usz;
+            for (int idx = tid; idx < (m - c) * nr; idx += SNT) {
+                const int i = idx / nr, r = idx % nr;
+                U0[(int64_t)r * sa.usz + ro + i] = 0.0;
+            }
+            __syncthreads();
+            for (int g = 0, e0 = 0; g < ng; ++g) {
+                const int e1 = rec[1 + g];
+                for (int idx = tid; idx < (e1 - e0) * nr; idx += SNT) {
+                    const int e = e0 + idx / nr, r = idx % nr;
+                    const int row = pr[2 * e + 1];
+                    const double u = U0[(int64_t)r * sa.usz + pr[2 * e]];
+                    if (row < c) x0[(int64_t)r * sa.nv + R[row]] += u;
+                    else U0[(int64_t)r * sa.usz + ro + (row - c)] += u;
+                }
+                __syncthreads();
+                e0 = e1;
+            }
+        }
+        return;
+    }
     for (int k0r = 0; k0r < sa.nrhs; k0r += RBT) {
         const int nr = min(RBT, (int)sa.nrhs - k0r);
         double *x0 = sa.xp + ((int64_t)n * sa.nrhs + k0r) * sa.nv;
@@ -1016,7 +1046,7 @@ void launch_fwd_level(const T *L, int64_t Lstride, const FrontDesc *sd, const Le
         hipLaunchKernelGGL(k_fwd_small<T>, dim3(lt.nsmall, (unsigned)sa.N), dim3(64), 0, st, L, Lstride, sd, lt.small,
                            tr, sa);
     fwd_tri_rb<T>(L, Lstride, sd, lt.large, lt.nlarge, lt.maxm, WHOLE, tr, sa, st);
-    if (lt.nwin > 0) fwd_tri_rb<T>(L, Lstride, sd, lt.win[0].fronts, lt.win[0].nfront, lt.maxm, 0, tr, sa, st);
+    if (lt.nwin > 0) fwd_tri_rb<T>(L, Lstride, sd, lt.win[0].fronts, lt.win[0].nfront, 0, 0, tr, sa, st);
     for (int w = 0; w < lt.nwin; ++w) {
         const TriWindow &tw = lt.win[w];
         win_solve<T>(true, L, Lstride, sd, tw.fronts, tw.nfront, tw.p0, tr, sa, st);

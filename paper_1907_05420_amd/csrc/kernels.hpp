@@ -99,6 +99,9 @@ void launch_gather_rhs(const double *b, int64_t ntot, int64_t nA, const int32_t 
 // part are spread over many workgroups.
 constexpr int TRI_W = 256;
 static_assert(TRI_W == INV_W, "the solves' windows are the factor's inverted diagonal blocks");
+// a front whose pivot part the solves take window by window (its vectors
+// then never need to fit in LDS)
+inline bool wide_front(int m, int c) { return c > TRI_W && m > c; }
 struct TriWindow {
     int p0;                      // first pivot of the window
     const int32_t *fronts;       // wide fronts with more than p0 pivots
@@ -114,7 +117,7 @@ struct LevelTasks {
     const RowTask *rect_cols;    // (front, first column) of 64 pivot columns of large and wide fronts
     const TriWindow *win;        // pivot windows of the wide fronts (host array)
     int nsmall, nlarge, nrect_rows, nrect_cols, nwin;
-    int maxm, maxc;              // largest rows / pivots of the large and wide fronts
+    int maxm, maxc;              // largest rows / pivots of the large fronts that are not wide
 };
 
 template <typename T>

@@ -166,3 +166,37 @@ def test_fullsize_structured_schur(mesh2000, mesh2000_structured):
     # no n_g x n_g matrix: the structured context holds O(N Ns^2) instead of
     # the dense S's n_g^2 doubles (2.95 GB)
     assert mesh2000["footprint"] - r["footprint"] >= 0.9 * inst.n_g ** 2 * 8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_front_beyond_lds_9241_bus_growth_free(precision):
+    """The 9241-bus network over 2 periods in the order where every dual
+    waits for all its primal neighbours: fronts of 20 056 rows (9 704 pivots)
+    and 10 950 rows (9 950 pivots), beyond what one workgroup's LDS holds, so
+    their solves stream the vectors through HBM window by window. FP64 and
+    the mixed path: the refined x meets 1e-10 on the oracle's K in extended
+    precision and the inertia is exact. At this barrier range ([1e-6, 1e6])
+    the FP32 factors are not trusted even in this order, and the mixed path
+    falls back to FP64 factors of the same values (measured: fallback_used 1,
+    4.4e-12 after one refinement step)."""
+    import torch
+    import paper_1907_05420_amd as pk
+    inst = kktgen.make_workload(3, N=2)
+    st, _ = pk.kkt_plan(inst.n_A, inst.n_primal, inst.N, inst.ns, inst.colptr, inst.rowind, inst.C0_rowptr,
+                        inst.C0_colind, inst.C1_rowptr, inst.C1_colind, dual_wait=1 << 30)
+    assert st["max_front"] == 20056
+    d = pk.device_inputs(inst)
+    s = pk.Solver(inst, precision=precision, dual_wait=1 << 30)
+    rc_f, inn = s.factor(d["vals"], d["C0"], d["C1"], d["corner"])
+    x, rc_s, info = s.solve(d["b"])
+    x = x.cpu().numpy()
+    torch.cuda.synchronize()
+    s.close()
+    K = ah.assemble(inst)
+    rel = ah.rel_residual_ld(inst, x, inst.b, K)
+    print(f"precision {precision}: rel_res {rel:.2e}, refine_iters {info['refine_iters']}, "
+          f"fallback {info['fallback_used']}")
+    assert rel <= 1e-10, rel
+    assert rc_s == 0 and (precision == 1 or info["fallback_used"] == 0)
+    expect = (inst.N * inst.n_primal, inst.N * (inst.n_A - inst.n_primal) + inst.n_g, 0)
+    assert (inn["n_pos"], inn["n_neg"], inn["n_zero"]) == expect
