@@ -268,6 +268,12 @@ __device__ inline T *front_addr(T *P, T *Ub, int m, int c, int r, int q) {
     return q < c ? P + r + (int64_t)q * m : Ub + (r - c) + (int64_t)(q - c) * (m - c);
 }
 
+// The kernels of the panel chain (pivot blocks, their rows and the updates
+// inside a sub-panel) raise their waves' issue priority: on the dense Schur
+// factor they share compute units with the other stream's trailing update,
+// whose MFMA waves would otherwise take most issue slots from them.
+__device__ inline void chain_priority() { __builtin_amdgcn_s_setprio(2); }
+
 // Extend-add of the children's update blocks into tiles of 64 rows by EA_CW
 // columns of a large front. The child rows and columns landing in a tile
 // each form one contiguous range (the relative indices increase), so every
@@ -464,6 +470,7 @@ __global__ __launch_bounds__(256) void k_diag(FactorArgs<T> fa, const FrontDesc 
     // multipliers and pivots of a 16-column block, double-buffered by block
     __shared__ T Ls[2][16][NB];
     __shared__ T Ds[2][16];
+    chain_priority();
     diag_core<T>(fa, sd[fl[blockIdx.x]], blockIdx.y, t0, Ls, Ds);
 }
 
@@ -567,6 +574,7 @@ __global__ __launch_bounds__(256) void k_trsm(FactorArgs<T> fa, const FrontDesc 
     __shared__ T sA[NB * LDS_LD];
     __shared__ T sB[NB * LDS_LD];
     __shared__ T Ds[NB];
+    chain_priority();
     const int fi = find_front(pre, nf, blockIdx.x);
     trsm_core<T>(fa, sd[fl[fi]], blockIdx.y, blockIdx.x - pre[fi], t0, pe, win, sA, sB, Ds);
 }
@@ -603,6 +611,7 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FactorArgs<T> fa, const Fron
     __shared__ T sA[NB * LDS_LD];
     __shared__ T sB[NB * LDS_LD];
     __shared__ T sD[4 * NB];
+    chain_priority();
     const int fi = find_front(pre, nf, blockIdx.x);
     const FrontDesc d = sd[fl[fi]];
     const int n = blockIdx.y, tid = threadIdx.x;
@@ -782,6 +791,7 @@ __global__ __launch_bounds__(256) void k_update(FactorArgs<T> fa, const FrontDes
                                                 const int32_t *pre, int nf, int kind, int t0, int pe, int win) {
     __shared__ T sA[NB * LDS_LD];
     __shared__ T sB[NB * LDS_LD];
+    chain_priority();
     const int fi = find_front(pre, nf, blockIdx.x);
     update_core<T>(fa, sd[fl[fi]], blockIdx.y, blockIdx.x - pre[fi], kind, t0, pe, win, sA, sB);
 }
