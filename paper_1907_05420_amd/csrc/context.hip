@@ -470,7 +470,8 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         if ((rc = upload(ctx, &ctx->d_sdS, sdS))) return rc;
         std::vector<int32_t> sbuf;
         ctx->ssteps.clear();
-        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true, ctx->big_rows, SCHUR_OUTER_W, INNER_W);
+        plan_steps(sdS, std::vector<int32_t>{0}, sbuf, ctx->ssteps, true, ctx->big_rows, SCHUR_OUTER_W, INNER_W,
+                   std::max(ctx->big_rows, SCHUR_CHAIN_BIG_ROWS));
         if ((rc = upload(ctx, &ctx->d_stasks, sbuf))) return rc;
     }
     // residual: full symmetric CSR of the pattern (caller order) and C^T by column

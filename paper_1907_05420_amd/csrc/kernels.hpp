@@ -52,6 +52,9 @@ struct TreeArgs {
 constexpr int OUTER_W = 512;
 constexpr int INNER_W = 256;  // at most four pivot blocks (k_panel_trsm)
 constexpr int SCHUR_OUTER_W = 512;
+// the dense Schur factor's panel-chain updates take 128x128 tiles only with
+// at least this many rows below the panel (enough tiles for every CU)
+constexpr int SCHUR_CHAIN_BIG_ROWS = 12288;
 constexpr int MAX_OUTER_W = 512;
 constexpr int INV_W = 256;
 // width of the inverted diagonal blocks of the dense Schur factor that its

@@ -94,9 +94,15 @@ struct StepHost {
 // With lookahead (dense Schur), each trailing update is split: the next
 // panel's columns on the main stream, the rest on the side stream, so that the
 // latency-bound factorisation of the next panel overlaps the large update.
+// big_rows_chain (0: big_rows) is the threshold for the updates on the
+// panel chain (the next sub-panel's and, with lookahead, the next panel's
+// columns): there the launch's parallelism decides, and 64x64 tiles give
+// four times the workgroups of 128x128 ones.
 template <class FD>
 void plan_steps(const std::vector<FD> &fd, const std::vector<int32_t> &fl, std::vector<int32_t> &buf,
-                std::vector<StepHost> &steps, bool lookahead, int big_rows, int outer_w, int inner_w) {
+                std::vector<StepHost> &steps, bool lookahead, int big_rows, int outer_w, int inner_w,
+                int big_rows_chain = 0) {
+    if (big_rows_chain <= 0) big_rows_chain = big_rows;
     // sub-panels of at most four pivot blocks (k_panel_trsm)
     if (inner_w > 4 * PIVOT_NB) inner_w = 4 * PIVOT_NB;
     int cmax = 0;
@@ -134,9 +140,10 @@ void plan_steps(const std::vector<FD> &fd, const std::vector<int32_t> &fl, std::
         steps.push_back(s);
     };
     // large trailing matrices (rows below column `col`) take the 128x128 tile kernel
-    auto big_from = [&](int t0, int col) {
+    auto big_from = [&](int t0, int col, int rows = -1) {
+        if (rows < 0) rows = big_rows;
         for (int32_t f : fl)
-            if (fd[f].c > t0 && fd[f].m - std::min(col, fd[f].c) >= big_rows) return 1;
+            if (fd[f].c > t0 && fd[f].m - std::min(col, fd[f].c) >= rows) return 1;
         return 0;
     };
     for (int k = 0; k < cmax; k += outer_w) {
@@ -167,7 +174,7 @@ void plan_steps(const std::vector<FD> &fd, const std::vector<int32_t> &fl, std::
                 add(2, j0, se, one_launch ? 3 : 0);
             }
             if (one_launch) add(7, s0, se);
-            if (se < std::min(pe, cmax)) add(big_from(s0, se) ? 4 : 3, s0, se, 1, 0);
+            if (se < std::min(pe, cmax)) add(big_from(s0, se, big_rows_chain) ? 4 : 3, s0, se, 1, 0);
         }
         const int big = big_from(k, pe);
         if (!lookahead) {
@@ -177,7 +184,7 @@ void plan_steps(const std::vector<FD> &fd, const std::vector<int32_t> &fl, std::
         // the next panel's columns: the side stream's update from the
         // previous panel must be done before this panel's update of them
         if (k > 0) sync(SYNC_TO_MAIN);
-        add(big ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
+        add(big_from(k, pe, big_rows_chain) ? 4 : 3, k, pe, 1, 0);  // next panel's columns, main stream
         // the side stream updates the columns beyond the next panel once the
         // main stream's update of the next panel's columns is done: started
         // together, the large update takes the compute units first and the

@@ -60,11 +60,12 @@ struct Cov {
     }
 };
 
-static void run(const char *name, const std::vector<FD> &fd, bool lookahead, int outer, int inner) {
+static void run(const char *name, const std::vector<FD> &fd, bool lookahead, int outer, int inner,
+                int big_rows_chain = 0) {
     std::vector<int32_t> fl, buf;
     for (int i = 0; i < (int)fd.size(); ++i) fl.push_back(i);
     std::vector<StepHost> steps;
-    plan_steps(fd, fl, buf, steps, lookahead, 512, outer, inner);
+    plan_steps(fd, fl, buf, steps, lookahead, 512, outer, inner, big_rows_chain);
     std::vector<Cov> cov;
     for (const FD &f : fd) cov.emplace_back(f.m, f.c);
     for (const StepHost &s : steps) {
@@ -107,8 +108,10 @@ int main() {
                                      {130, 65},  {200, 64},  {1300, 260}, {1350, 513}};
     run("periods 512/256", periods, false, 512, 256);
     run("periods 256/256", periods, false, 256, 256);
-    for (int n : {1100, 1024, 1300, 800})
+    for (int n : {1100, 1024, 1300, 800, 2600}) {
         run("dense with lookahead", std::vector<FD>{{n, n}}, true, 512, 256);
+        run("dense with lookahead, 64x64 chain updates below 1500 rows", std::vector<FD>{{n, n}}, true, 512, 256, 1500);
+    }
     printf("bad %ld\n", bad);
     return bad != 0;
 }
