@@ -56,6 +56,8 @@ constexpr int SCHUR_OUTER_W = 512;
 // at least this many rows below the panel (enough tiles for every CU)
 constexpr int SCHUR_CHAIN_BIG_ROWS = 12288;
 constexpr int MAX_OUTER_W = 512;
+static_assert(OUTER_W <= 2 * INNER_W && SCHUR_OUTER_W <= 2 * INNER_W && SCHUR_OUTER_W <= MAX_OUTER_W,
+              "at most two sub-panels per outer panel");
 constexpr int INV_W = 256;
 // width of the inverted diagonal blocks of the dense Schur factor that its
 // solves use (built from INV_W ones by doubling)

@@ -103,8 +103,11 @@ void plan_steps(const std::vector<FD> &fd, const std::vector<int32_t> &fl, std::
                 std::vector<StepHost> &steps, bool lookahead, int big_rows, int outer_w, int inner_w,
                 int big_rows_chain = 0) {
     if (big_rows_chain <= 0) big_rows_chain = big_rows;
-    // sub-panels of at most four pivot blocks (k_panel_trsm)
+    // sub-panels of at most four pivot blocks (k_panel_trsm), at most two per
+    // outer panel: a finished sub-panel updates only the next sub-panel's
+    // columns (the next panel of its width, upd_geom win 1)
     if (inner_w > 4 * PIVOT_NB) inner_w = 4 * PIVOT_NB;
+    if (outer_w > 2 * inner_w) outer_w = 2 * inner_w;
     int cmax = 0;
     for (int32_t f : fl) cmax = std::max(cmax, fd[f].c);
     auto sync = [&](int kind) {

@@ -111,6 +111,8 @@ int main() {
     for (int n : {1100, 1024, 1300, 800, 2600}) {
         run("dense with lookahead", std::vector<FD>{{n, n}}, true, 512, 256);
         run("dense with lookahead, 64x64 chain updates below 1500 rows", std::vector<FD>{{n, n}}, true, 512, 256, 1500);
+        // three sub-panels asked for: the plan keeps two per outer panel
+        run("dense with lookahead, 768-wide outer panels asked for", std::vector<FD>{{n, n}}, true, 768, 256);
     }
     printf("bad %ld\n", bad);
     return bad != 0;
