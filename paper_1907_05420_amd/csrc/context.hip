@@ -423,8 +423,13 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
             ctx->win_plan.push_back(w);
         }
         lp.win_end = (int)ctx->win_plan.size();
+        // levels with a front of many pivots take the lookahead plan: its
+        // trailing updates beyond the next panel go on the side stream while
+        // the main stream factors the next panel
+        bool lookahead = false;
+        for (int32_t t : large) lookahead = lookahead || S.ncol[t] >= LOOKAHEAD_PIVOTS;
         lp.step_begin = (int)ctx->steps.size();
-        plan_steps(fd, large, buf, ctx->steps, false, ctx->big_rows, OUTER_W, INNER_W);
+        plan_steps(fd, large, buf, ctx->steps, lookahead, ctx->big_rows, OUTER_W, INNER_W);
         lp.step_end = (int)ctx->steps.size();
     }
     if ((rc = upload(ctx, &ctx->d_tasks, buf))) return rc;
@@ -726,8 +731,18 @@ int factor_range(kkt_ctx *ctx, int64_t p0, int64_t np, int64_t *cnt) {
     for (const LevelPlan &lp : ctx->levels) {
         launch_small_fronts<T>(fa, ctx->d_sd, ctx->d_tasks + lp.small_off, lp.nsmall_cls, np, tr, st);
         launch_extend_add<T>(fa, ctx->d_sd, (const EaTask *)(ctx->d_tasks + lp.ea_off), lp.nea, np, tr, st);
-        for (int q = lp.step_begin; q < lp.step_end; ++q)
-            launch_step<T>(fa, ctx->d_sd, step_dev(ctx->steps[q], ctx->d_tasks), np, st);
+        for (int q = lp.step_begin; q < lp.step_end; ++q) {
+            const StepHost &s = ctx->steps[q];
+            if (s.kind == SYNC_TO_SIDE) {
+                HIPCHK(hipEventRecord(ctx->ev_main, st));
+                HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_main, 0));
+            } else if (s.kind == SYNC_TO_MAIN) {
+                HIPCHK(hipEventRecord(ctx->ev_side, ctx->side));
+                HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
+            } else {
+                launch_step<T>(fa, ctx->d_sd, step_dev(s, ctx->d_tasks), np, s.side ? ctx->side : st);
+            }
+        }
         if (lp.win_end > lp.win_begin) {
             // the solves' windows of the wide fronts: their diagonal blocks inverted
             const WindowPlan &w0 = ctx->win_plan[lp.win_begin];

@@ -52,6 +52,8 @@ struct TreeArgs {
 constexpr int OUTER_W = 512;
 constexpr int INNER_W = 256;  // at most four pivot blocks (k_panel_trsm)
 constexpr int SCHUR_OUTER_W = 512;
+// period levels with a front of at least this many pivots use the lookahead plan
+constexpr int LOOKAHEAD_PIVOTS = 2048;
 // the dense Schur factor's panel-chain updates take 128x128 tiles only with
 // at least this many rows below the panel (enough tiles for every CU)
 constexpr int SCHUR_CHAIN_BIG_ROWS = 12288;

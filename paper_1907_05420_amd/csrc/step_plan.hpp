@@ -44,11 +44,12 @@ __host__ __device__ inline UpdGeom upd_geom(int kind, int t0, int pe, int c, int
         g.lo = cend;
         g.qhi = m;
         // the next panel has the width of this one (pe - t0); its columns
-        // end at the front's last pivot (the update block's columns take
-        // the whole outer panel's update after it)
+        // end at the front's last pivot, and the rest (win 2) starts there
+        // at the latest: the update block's columns take the whole outer
+        // panel's update with the rest
         const int nxt = pe + (pe - t0) < m ? pe + (pe - t0) : m;
         if (win == 1) g.qhi = nxt < c ? nxt : c;
-        else if (win == 2) g.lo = nxt;
+        else if (win == 2) g.lo = nxt < c ? nxt : c;
     }
     return g;
 }

@@ -108,6 +108,7 @@ int main() {
                                      {130, 65},  {200, 64},  {1300, 260}, {1350, 513}};
     run("periods 512/256", periods, false, 512, 256);
     run("periods 256/256", periods, false, 256, 256);
+    run("periods 512/256 with lookahead", periods, true, 512, 256);
     for (int n : {1100, 1024, 1300, 800, 2600}) {
         run("dense with lookahead", std::vector<FD>{{n, n}}, true, 512, 256);
         run("dense with lookahead, 64x64 chain updates below 1500 rows", std::vector<FD>{{n, n}}, true, 512, 256, 1500);
