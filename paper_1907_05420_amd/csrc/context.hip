@@ -347,47 +347,10 @@ int build_device_symbolic(kkt_ctx *ctx, const kkt_structure *s) {
         lp.large_off = (int64_t)buf.size();
         lp.nlarge = (int)plain.size();
         buf.insert(buf.end(), plain.begin(), plain.end());
-        // extend-add tiles of 64 rows by EA_CW columns (lower triangle), each
-        // with the segments of the children that reach it; a tile without
-        // segments is kept where it holds entries of the update block (it
-        // clears them)
+        // extend-add tiles and their children's segments (ea_plan.hpp)
         while (buf.size() % 8) buf.push_back(0);  // EaTask alignment
         lp.ea_off = (int64_t)buf.size();
-        {
-            std::vector<int32_t> tiles, segs, rows_of;  // rows_of: (child, i_lo, i_hi) of a row tile
-            for (int32_t t : large)
-                for (int r0 = 0; r0 < S.nrow[t]; r0 += 64) {
-                    const int r1 = std::min(r0 + 64, S.nrow[t]);
-                    rows_of.clear();
-                    for (int32_t k = S.child_ptr[t]; k < S.child_ptr[t + 1]; ++k) {
-                        const int32_t ch = S.child_list[k];
-                        const int32_t *rl = S.rel.data() + S.relptr[ch];
-                        const int uc = S.nrow[ch] - S.ncol[ch];
-                        const int lo = (int)(std::lower_bound(rl, rl + uc, r0) - rl);
-                        const int hi = (int)(std::lower_bound(rl + lo, rl + uc, r1) - rl);
-                        if (lo < hi) rows_of.insert(rows_of.end(), {ch, lo, hi});
-                    }
-                    for (int c0 = 0; c0 < r1; c0 += EA_CW) {
-                        const int c1 = std::min(c0 + EA_CW, r1);
-                        const int32_t s0 = (int32_t)segs.size();
-                        for (size_t q = 0; q < rows_of.size(); q += 3) {
-                            const int32_t ch = rows_of[q], lo = rows_of[q + 1], hi = rows_of[q + 2];
-                            const int32_t *rl = S.rel.data() + S.relptr[ch];
-                            const int jl = (int)(std::lower_bound(rl, rl + hi, c0) - rl);
-                            const int jh = (int)(std::lower_bound(rl + jl, rl + hi, c1) - rl);
-                            if (jl < jh) segs.insert(segs.end(), {ch, lo, hi, jl, jh});
-                        }
-                        const int nseg = ((int32_t)segs.size() - s0) / EA_SEG;
-                        const bool clears = r1 > S.ncol[t] && c1 > S.ncol[t];
-                        if (nseg > 0 || clears) tiles.insert(tiles.end(), {t, r0, c0, s0, nseg, 0, 0, 0});
-                    }
-                }
-            lp.nea = (int)(tiles.size() / 8);
-            // segment offsets count from the first task
-            for (size_t q = 0; q < tiles.size(); q += 8) tiles[q + 3] += (int32_t)tiles.size();
-            buf.insert(buf.end(), tiles.begin(), tiles.end());
-            buf.insert(buf.end(), segs.begin(), segs.end());
-        }
+        lp.nea = plan_extend_add(S, large, buf);
         if (buf.size() % 2) buf.push_back(0);  // RowTask alignment (pairs of int32)
         // solve: 64 update rows / 64 pivot columns of each large front (the
         // update rows of wide fronts go with their windows' products)

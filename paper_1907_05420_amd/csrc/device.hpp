@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "ea_plan.hpp"
+
 namespace kkt {
 
 // A dense front of one supernode in the per-period storage: a column-major
@@ -25,16 +27,6 @@ struct RowTask {    // up to 256 consecutive rows [r0, ...) of front `f`
     int32_t f, r0;
 };
 
-// Extend-add into the tile of rows [r0, r0 + 64) and columns [c0, c0 +
-// EA_CW) of front f: nseg segments of EA_SEG int32 at seg int32 past the
-// first task of the list, each (child, i_lo, i_hi, j_lo, j_hi): the child's
-// update rows [i_lo, i_hi) land in the tile's rows and its update columns
-// [j_lo, j_hi) in the tile's columns; children in increasing order.
-struct EaTask {
-    int32_t f, r0, c0, seg, nseg, pad0, pad1, pad2;
-};
-constexpr int EA_CW = 256;  // columns of an extend-add tile
-constexpr int EA_SEG = 5;   // int32 per segment
 
 // Factor-wide pointers handed to every factor kernel.
 template <typename T>
