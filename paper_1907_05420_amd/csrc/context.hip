@@ -131,7 +131,7 @@ struct kkt_ctx {
     double *d_V = nullptr, *d_Z = nullptr, *d_h = nullptr, *d_kpart = nullptr, *h_pin = nullptr;
     // side stream and events of the lookahead
     hipStream_t side = nullptr;
-    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr, ev_asm = nullptr;
     // timing
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -795,9 +795,22 @@ int factor_schur(kkt_ctx *ctx) {
         return factor_schur_structured(ctx);
     }
     launch_schur_prefix(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, st);
-    launch_schur_assemble(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix,
-                          ctx->has_corner ? ctx->d_corner : nullptr, ctx->d_S, ctx->d_tauS, ctx->eps,
-                          ctx->d_amaxS, 0, st);
+    // the pivot thresholds from S's diagonal, the first panel's columns on
+    // the main stream, the other columns on the side stream while the first
+    // panel is factored; the main stream waits for them before its first
+    // update beyond the first panel
+    const double *corner = ctx->has_corner ? ctx->d_corner : nullptr;
+    const int64_t w0 = std::min<int64_t>(SCHUR_OUTER_W, ctx->ng);
+    launch_schur_diag(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_tauS,
+                      ctx->eps, ctx->d_amaxS, st);
+    launch_schur_assemble(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_S,
+                          nullptr, 0.0, nullptr, 0, st, 0, w0);
+    HIPCHK(hipEventRecord(ctx->ev_main, st));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_main, 0));
+    launch_schur_assemble(sb.p, sb.stride, sb.off, ctx->N, S.Ns, ctx->opt.precision, ctx->d_prefix, corner, ctx->d_S,
+                          nullptr, 0.0, nullptr, 0, ctx->side, w0, -1);
+    HIPCHK(hipEventRecord(ctx->ev_asm, ctx->side));
+    bool assembled = false;
     mark(ctx, 2);
     ctx->kcount = 0;
     ctx->kstat = kkt_kernel_stat{};
@@ -811,6 +824,10 @@ int factor_schur(kkt_ctx *ctx) {
             HIPCHK(hipStreamWaitEvent(st, ctx->ev_side, 0));
         } else {
             hipStream_t ss = s.side ? ctx->side : st;
+            if (!assembled && !s.side && (s.kind == 3 || s.kind == 4) && s.pe >= w0) {
+                HIPCHK(hipStreamWaitEvent(st, ctx->ev_asm, 0));
+                assembled = true;
+            }
             const bool timed = ctx->timing && s.kind == 4;
             if (timed) {
                 if ((size_t)(2 * ctx->kcount + 2) > ctx->kev.size()) {
@@ -999,7 +1016,8 @@ extern "C" int kkt_create(kkt_ctx **out, void *stream, const kkt_options *opt) {
     if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return KKT_ERR_HIP; }
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_asm, hipEventDisableTiming) != hipSuccess) {
         kkt_destroy(ctx);
         return KKT_ERR_HIP;
     }
@@ -1821,6 +1839,7 @@ extern "C" void kkt_destroy(kkt_ctx *ctx) {
     for (auto &e : ctx->kev) (void)hipEventDestroy(e);
     if (ctx->ev_main) (void)hipEventDestroy(ctx->ev_main);
     if (ctx->ev_side) (void)hipEventDestroy(ctx->ev_side);
+    if (ctx->ev_asm) (void)hipEventDestroy(ctx->ev_asm);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }

@@ -37,10 +37,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_schur_assemble(const T *U, int64_t Ustride, int64_t uoff, int64_t N,
                                                         int64_t Ns, const double *prefix, const double *corner,
                                                         double *S, double *tau_s, double eps, double *amax_s,
-                                                        int mirror) {
+                                                        int mirror, int64_t q0) {
     const int64_t ng = N * Ns, nb = 2 * Ns;
     const int64_t R = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t Q = blockIdx.y;
+    const int64_t Q = q0 + blockIdx.y;
     if (R >= ng || (R < Q && !mirror)) return;
     const int64_t r = R >= Q ? R : Q, q = R >= Q ? Q : R;
     const int64_t m = r / Ns, i = r % Ns, mp = q / Ns, j = q % Ns;
@@ -57,6 +57,23 @@ __global__ __launch_bounds__(256) void k_schur_assemble(const T *U, int64_t Ustr
         if (tau_s) tau_s[R] = eps * fabs(v);
         if (amax_s) atomic_max_nonneg(amax_s, fabs(v));
     }
+}
+
+// The diagonal entries of S alone (the same sums as k_schur_assemble's), for
+// the pivot thresholds: lets the factorisation's first panel start before
+// the rest of S is assembled.
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur_diag(const T *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns,
+                                                    const double *prefix, const double *corner, double *tau_s,
+                                                    double eps, double *amax_s) {
+    const int64_t ng = N * Ns, nb = 2 * Ns;
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= ng) return;
+    const int64_t m = r / Ns, i = r % Ns;
+    double v = sbar_at(U + m * Ustride + uoff, nb, i, i) + prefix[m * Ns * Ns + i + i * Ns];
+    if (corner) v += corner[r];
+    tau_s[r] = eps * fabs(v);
+    atomic_max_nonneg(amax_s, fabs(v));
 }
 
 template <typename T>
@@ -535,15 +552,30 @@ void launch_schur_prefix(const void *U, int64_t Ustride, int64_t uoff, int64_t N
 
 void launch_schur_assemble(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
                            const double *prefix, const double *corner, double *S, double *tau_s, double eps,
-                           double *amax_s, int mirror, hipStream_t st) {
+                           double *amax_s, int mirror, hipStream_t st, int64_t q0, int64_t q1) {
     const int64_t ng = N * Ns;
-    dim3 g((unsigned)((ng + 255) / 256), (unsigned)ng);
+    if (q1 < 0 || q1 > ng) q1 = ng;
+    if (q1 <= q0) return;
+    const dim3 gg((unsigned)((ng + 255) / 256), (unsigned)(q1 - q0));  // columns [q0, q1)
     if (precision == 1)
-        hipLaunchKernelGGL(k_schur_assemble<float>, g, dim3(256), 0, st, (const float *)U, Ustride, uoff, N, Ns,
-                           prefix, corner, S, tau_s, eps, amax_s, mirror);
+        hipLaunchKernelGGL(k_schur_assemble<float>, gg, dim3(256), 0, st, (const float *)U, Ustride, uoff, N, Ns,
+                           prefix, corner, S, tau_s, eps, amax_s, mirror, q0);
     else
-        hipLaunchKernelGGL(k_schur_assemble<double>, g, dim3(256), 0, st, (const double *)U, Ustride, uoff, N, Ns,
-                           prefix, corner, S, tau_s, eps, amax_s, mirror);
+        hipLaunchKernelGGL(k_schur_assemble<double>, gg, dim3(256), 0, st, (const double *)U, Ustride, uoff, N, Ns,
+                           prefix, corner, S, tau_s, eps, amax_s, mirror, q0);
+}
+
+void launch_schur_diag(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
+                       const double *prefix, const double *corner, double *tau_s, double eps, double *amax_s,
+                       hipStream_t st) {
+    const int64_t ng = N * Ns;
+    const dim3 g((unsigned)((ng + 255) / 256));
+    if (precision == 1)
+        hipLaunchKernelGGL(k_schur_diag<float>, g, dim3(256), 0, st, (const float *)U, Ustride, uoff, N, Ns, prefix,
+                           corner, tau_s, eps, amax_s);
+    else
+        hipLaunchKernelGGL(k_schur_diag<double>, g, dim3(256), 0, st, (const double *)U, Ustride, uoff, N, Ns,
+                           prefix, corner, tau_s, eps, amax_s);
 }
 
 void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t nb, int precision,

@@ -143,9 +143,15 @@ void launch_border_values(const double *xg, SolveArgs sa, int64_t nA, int64_t Ns
 // dense Schur: assembly, factor steps reuse launch_step, triangular solves
 void launch_schur_prefix(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
                          double *prefix, hipStream_t st);
+// columns [q0, q1) of S (q1 < 0: to the last); the diagonal's entries set
+// tau_s and amax_s when those are given
 void launch_schur_assemble(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
                            const double *prefix, const double *corner, double *S, double *tau_s, double eps,
-                           double *amax_s, int mirror, hipStream_t st);
+                           double *amax_s, int mirror, hipStream_t st, int64_t q0 = 0, int64_t q1 = -1);
+// the diagonal of S only: tau_s and amax_s (S itself is not written)
+void launch_schur_diag(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t Ns, int precision,
+                       const double *prefix, const double *corner, double *tau_s, double eps, double *amax_s,
+                       hipStream_t st);
 void launch_copy_sbar(const void *U, int64_t Ustride, int64_t uoff, int64_t N, int64_t nb, int precision,
                       double *out, hipStream_t st);
 // inverse of the INV_W diagonal block at j0 of the (single) front fl[0]
